@@ -1,0 +1,206 @@
+/*
+ * kgev.h -- C ABI of the MI355X (gfx950) k-point generalized Hermitian
+ * eigensolver.
+ *
+ * The library solves, for every k-point of a batch, the dense complex
+ * Hermitian-definite generalized eigenproblem H(k) C = S(k) C Lambda, the
+ * diagonalisation at the heart of OpenMX's Band_DFT_Col (Parq, Sevre & Lee,
+ * arXiv:1402.4247, Section III):
+ *   Part 2  diagonalise S and rearrange it:  S = U diag(s) U^H,
+ *           X = U diag(s)^(-1/2)  (canonical orthogonalisation);
+ *   Part 3  form "S^H H S" = X^H H X  (matrix products);
+ *   Part 4  diagonalise it with Eigen_HH and one matrix product C = X Y.
+ * Eigen_HH (Section III) is: Householder tridiagonalisation (Procedures 1-6),
+ * a tridiagonal eigensolve, back-transformation ("rearrangement of
+ * eigenvectors") and normalisation.  Every step runs in HIP kernels on the
+ * GPU; nothing falls back to the host.
+ *
+ * Conventions for every entry point:
+ *   - Complex numbers are kgev_z = {double re, im}, layout-compatible with
+ *     C99 double _Complex, std::complex<double> and torch.complex128.
+ *   - Matrices are column-major: element (i, j) of a matrix with leading
+ *     dimension ld is at offset i + j*ld.  A batch of nk matrices is stored
+ *     back to back with stride ld*n elements.
+ *   - Hermitian inputs are read from the LOWER triangle only (i >= j); the
+ *     strict upper triangle is never read and the imaginary part of the
+ *     diagonal is ignored.
+ *   - Eigenvalues are returned ascending; column j of C is the eigenvector
+ *     of eigenvalue j, normalised so that C^H S C = I.  Each column is
+ *     unique only up to a unit-modulus phase (and within degenerate
+ *     eigenspaces only the spanned space is unique).
+ *   - Ownership: the caller owns every buffer it passes.  The library never
+ *     frees caller memory and keeps no caller pointer after a host call
+ *     returns, or after the stream work of a device call has completed.
+ *   - Device entry points are asynchronous on the given stream (a
+ *     hipStream_t passed as void*; NULL = the null stream).  Their results and
+ *     the per-k status words are valid once that stream has completed.
+ *   - A context is not thread-safe: use one per host thread.
+ *
+ * Status codes (LAPACK-style): 0 success; -i argument i is invalid;
+ * positive values are numerical conditions reported per k-point; the
+ * negative codes below -99 are resource/runtime errors.  A k-point that fails
+ * leaves its output slice unspecified; the other k-points of the same call
+ * are still solved.
+ */
+#ifndef KGEV_H
+#define KGEV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } kgev_z;
+
+typedef int32_t kgev_status;
+#define KGEV_OK            0
+#define KGEV_ENOTPD        1    /* S(k) not positive definite: s_min <= s_tol * s_max */
+#define KGEV_ENOCONV       2    /* tridiagonal eigensolver did not converge */
+#define KGEV_ENONFINITE    3    /* NaN or Inf in the lower triangle of H(k) or S(k) */
+#define KGEV_ENOMEM     (-100)  /* device or host allocation failed */
+#define KGEV_EDEVICE    (-101)  /* a HIP runtime call failed */
+#define KGEV_EUNSUPPORTED (-102)/* option combination not supported */
+
+#define KGEV_PREC_FP64        0 /* every step in FP64 / complex128 */
+#define KGEV_PREC_FP32_REFINE 1 /* Part 4 tridiagonalisation and back-transform in
+                                   complex64, then FP64 eigenpair refinement */
+
+typedef struct kgev_ctx kgev_ctx;
+
+typedef struct {
+    int32_t precision;    /* KGEV_PREC_FP64 (default) or KGEV_PREC_FP32_REFINE */
+    int32_t want_vectors; /* 1 (default): eigenvalues and eigenvectors; 0: eigenvalues only */
+    int32_t panel_nb;     /* Householder panel width; 0 = tuned default */
+    int32_t refine_iters; /* mixed precision: maximum refinement sweeps; 0 = default (3) */
+    double s_tol;         /* S(k) is rejected when s_min <= s_tol * s_max; 0 = default 1e-12 */
+    int32_t reserved[8];  /* must be zero */
+} kgev_opts;
+
+/* Fill *opts with the defaults listed above. */
+void kgev_opts_default(kgev_opts* opts);
+
+/* Static, human-readable text for a status code. */
+const char* kgev_status_str(kgev_status st);
+
+/*
+ * Create a context bound to HIP device `device`.  The context owns an
+ * internal device workspace (grown on demand when callers pass no
+ * workspace), the tuned panel/tile table and a few small device buffers.
+ * Returns KGEV_OK, -1 (ctx NULL), -2 (no such device) or KGEV_EDEVICE.
+ */
+kgev_status kgev_create(kgev_ctx** ctx, int device);
+
+/* Release a context and everything it owns.  NULL is allowed. */
+void kgev_destroy(kgev_ctx* ctx);
+
+/*
+ * Device workspace, in bytes, that kgev_solve_k_device needs for nk
+ * problems of order n with the given options (NULL = defaults).  Returns 0
+ * for invalid n or nk.
+ */
+size_t kgev_workspace_bytes(int64_t n, int64_t nk, const kgev_opts* opts);
+
+/*
+ * Host-pointer, synchronous solve of nk k-points (Band_DFT_Col Parts 2-4,
+ * Section III).
+ *   H, S : host, nk column-major n x n matrices (ld = n), lower triangles read.
+ *   w    : host, nk*n doubles; eigenvalues of k-point q at w[q*n .. q*n+n-1].
+ *   C    : host, nk*n*n kgev_z; may be NULL when opts->want_vectors == 0.
+ *   bad_k: optional; receives the first failing k index (or -1).
+ * Returns the first nonzero per-k status, or an argument/runtime error:
+ *   -1 ctx, -2 H, -3 S, -4 n < 1, -5 nk < 1, -6 w, -7 C, -8 opts invalid.
+ */
+kgev_status kgev_solve_k(kgev_ctx* ctx, const kgev_z* H, const kgev_z* S, int64_t n, int64_t nk,
+                         double* w, kgev_z* C, const kgev_opts* opts, int64_t* bad_k);
+
+/*
+ * Device-pointer, asynchronous solve of nk k-points on `stream`.
+ *   dH, dS   : device, nk matrices n x n with leading dimension ld >= n and
+ *              batch stride ld*n; lower triangles read; not modified.
+ *   dw       : device, nk*n doubles (eigenvalues, ascending per k).
+ *   dC       : device, nk matrices n x n, leading dimension ldc >= n, batch
+ *              stride ldc*n; may be NULL for eigenvalues only.
+ *   dwork    : device workspace of work_bytes >= kgev_workspace_bytes(n, nk,
+ *              opts), or NULL to use the context's internal workspace (which
+ *              the library may then allocate).
+ *   d_status : device, nk int32 status words (KGEV_OK / KGEV_ENOTPD /
+ *              KGEV_ENOCONV / KGEV_ENONFINITE), or NULL.
+ * Returns an argument/runtime error immediately, else KGEV_OK once every
+ * kernel is enqueued (-1 ctx, -2 dH, -3 dS, -4 n, -5 ld, -6 nk, -7 dw,
+ * -8 dC/ldc, -9 work too small, -10 opts invalid).
+ */
+kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n,
+                                int64_t ld, int64_t nk, double* dw, kgev_z* dC, int64_t ldc,
+                                void* dwork, size_t work_bytes, int32_t* d_status,
+                                const kgev_opts* opts, void* stream);
+
+/*
+ * Stage entry points.  Each runs one step of the path on nk problems and
+ * exists so that every step can be checked on its own; all are device-pointer
+ * and asynchronous on `stream`, with the argument conventions above.
+ */
+
+/*
+ * Householder tridiagonalisation (Section III, Procedures 1-6; blocked).
+ *   dA  : in/out, nk matrices n x n (ld lda); lower triangle read and
+ *         destroyed.
+ *   dd  : out, nk*n doubles (diagonal of T); de: out, nk*n doubles (entry
+ *         q*n+i, i < n-1, is T(i+1, i)); dtau: out, nk*n kgev_z (tau_i at
+ *         q*n+i, i < n-1).
+ *   dV  : out, nk matrices n x n (ld n): column i holds v_i in rows i+1..n-1
+ *         with v_i(i+1) = 1 and zeros elsewhere, H_i = I - tau_i v_i v_i^H,
+ *         T = Q^H A Q, Q = H_0 H_1 ... H_{n-2}.
+ */
+kgev_status kgev_hetrd_device(kgev_ctx* ctx, kgev_z* dA, int64_t n, int64_t lda, int64_t nk,
+                              double* dd, double* de, kgev_z* dtau, kgev_z* dV,
+                              const kgev_opts* opts, void* stream);
+
+/*
+ * Real symmetric tridiagonal eigensolve (the tridiagonal step of Eigen_HH,
+ * Section III; divide and conquer).
+ *   dd, de : in, nk*n doubles each (layout as kgev_hetrd_device); not modified.
+ *   dw     : out, nk*n eigenvalues ascending.
+ *   dZ     : out, nk real matrices n x n (ld n), orthonormal eigenvectors;
+ *            column j belongs to eigenvalue j.
+ *   d_status: optional, nk int32 (KGEV_ENOCONV on failure).
+ */
+kgev_status kgev_stedc_device(kgev_ctx* ctx, const double* dd, const double* de, int64_t n,
+                              int64_t nk, double* dw, double* dZ, int32_t* d_status, void* stream);
+
+/*
+ * Back-transformation ("rearrangement of eigenvectors", Section III):
+ * dU <- Q dU for nk problems, with Q = H_0 ... H_{n-2} given by dV, dtau as
+ * produced by kgev_hetrd_device.  dU: in/out, nk matrices n x n (ld ldu).
+ */
+kgev_status kgev_unmtr_device(kgev_ctx* ctx, const kgev_z* dV, const kgev_z* dtau, int64_t n,
+                              int64_t nk, kgev_z* dU, int64_t ldu, void* stream);
+
+/*
+ * Eigen_HH (Section III): eigenvalues (ascending, dw: nk*n) and unit-norm
+ * eigenvectors (dY: nk matrices n x n, ld n; may be NULL for eigenvalues
+ * only) of the Hermitian matrices whose lower triangles are dA (ld lda; not
+ * modified).
+ */
+kgev_status kgev_eigh_device(kgev_ctx* ctx, const kgev_z* dA, int64_t n, int64_t lda, int64_t nk,
+                             double* dw, kgev_z* dY, int32_t* d_status, const kgev_opts* opts,
+                             void* stream);
+
+/*
+ * Batched complex matrix product (the ZGEMM of Parts 3 and 4, Section III):
+ * C_q = alpha op(A_q) op(B_q) + beta C_q for q < batch, op in {'N', 'C'}
+ * ('C' = conjugate transpose); C is m x n, inner dimension k; sA, sB, sC are
+ * batch strides in elements.  lower != 0 computes and writes only the
+ * entries with i >= j.  beta == 0 never reads C.
+ */
+kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m, int64_t n,
+                              int64_t k, kgev_z alpha, const kgev_z* dA, int64_t lda, int64_t sA,
+                              const kgev_z* dB, int64_t ldb, int64_t sB, kgev_z beta, kgev_z* dC,
+                              int64_t ldc, int64_t sC, int64_t batch, int32_t lower, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KGEV_H */

@@ -1,0 +1,551 @@
+// C ABI of the library (declared in include/kgev.h) and the host-side
+// sequencing of the per-k solve, Band_DFT_Col Parts 2-4 (Section III of
+// arXiv:1402.4247), batched over k-points:
+//   Part 2: S -> tridiagonal (blocked Householder) -> divide and conquer ->
+//           back-transformation -> X = U diag(s)^(-1/2) (+ definiteness check)
+//   Part 3: G = H X, A = X^H G (lower half)
+//   Part 4: A -> tridiagonal -> divide and conquer -> back-transformation ->
+//           normalisation -> C = X Y
+// Every step is a HIP kernel enqueued on the caller's stream; the host only
+// sizes the workspace and issues launches.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "../../include/kgev.h"
+
+using namespace kgev;
+
+struct kgev_ctx {
+    int device;
+    void* work;
+    size_t work_bytes;
+    // host-pointer API staging buffers
+    void* stage;
+    size_t stage_bytes;
+    hipStream_t stream;
+};
+
+namespace {
+
+constexpr int DEFAULT_NB = 32;
+constexpr int UNMTR_KB = 64;
+
+struct Layout {
+    size_t total = 0;
+    size_t add(size_t bytes)
+    {
+        const size_t off = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return off;
+    }
+};
+
+// Offsets of every workspace array for nk problems of order n.
+struct SolvePlan {
+    int64_t n, nk;
+    int nb, kb;
+    int NBmax, CHmax, PN;
+    // complex128 arrays
+    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, pyv, ybuf, uwork;
+    // real / int arrays
+    size_t d, e, sS, wA, pnorm, Zr, Qs, Vsec;
+    size_t dc_es, dc_onrm, dc_D0, dc_D1, dc_sd, dc_sz, dc_ndd, dc_ndz, dc_dfd, dc_rotc, dc_rots, dc_rho, dc_tauv,
+        dc_lam, dc_zhat;
+    size_t dc_kcnt, dc_ndcnt, dc_nrot, dc_perm, dc_ndx, dc_dfx, dc_rota, dc_rotb, dc_orgi, dc_cmap;
+    size_t status;
+    size_t total;
+};
+
+SolvePlan make_plan(int64_t n, int64_t nk, int nb)
+{
+    SolvePlan p{};
+    p.n = n;
+    p.nk = nk;
+    p.nb = nb;
+    p.kb = UNMTR_KB;
+    p.NBmax = hetrd_nbmax(n);
+    p.CHmax = hetrd_chmax(n);
+    p.PN = (int)((n + 255) / 256);
+    Layout L;
+    const size_t z = sizeof(double2), r = sizeof(double), i4 = sizeof(int);
+    const size_t nn = (size_t)n * n;
+    p.Aw = L.add(z * nn * nk);
+    p.Vs = L.add(z * nn * nk);
+    p.X = L.add(z * nn * nk);
+    p.G = L.add(z * nn * nk);
+    p.Wp = L.add(z * n * nb * nk);
+    p.tau = L.add(z * n * nk);
+    p.ypart = L.add(z * (size_t)p.NBmax * p.NBmax * 64 * nk);
+    p.ypartT = L.add(z * (size_t)p.NBmax * p.CHmax * 64 * nk);
+    p.pvw = L.add(z * (size_t)p.NBmax * nb * nk);
+    p.pvv = L.add(z * (size_t)p.NBmax * nb * nk);
+    p.pyv = L.add(z * (size_t)p.NBmax * nk);
+    p.ybuf = L.add(z * n * nk);
+    p.uwork = L.add(z * (size_t)unmtr_work_elems(n, p.kb) * nk);
+    p.d = L.add(r * n * nk);
+    p.e = L.add(r * n * nk);
+    p.sS = L.add(r * n * nk);
+    p.wA = L.add(r * n * nk);
+    p.pnorm = L.add(r * p.PN * nk);
+    p.Zr = L.add(r * nn * nk);
+    p.Qs = L.add(r * nn * nk);
+    p.Vsec = L.add(r * nn * nk);
+    size_t* dv[] = {&p.dc_es, &p.dc_D0, &p.dc_D1, &p.dc_sd, &p.dc_sz, &p.dc_ndd, &p.dc_ndz, &p.dc_dfd,
+                    &p.dc_rotc, &p.dc_rots, &p.dc_rho, &p.dc_tauv, &p.dc_lam, &p.dc_zhat};
+    for (size_t* q : dv) *q = L.add(r * n * nk);
+    p.dc_onrm = L.add(r * nk);
+    size_t* iv[] = {&p.dc_kcnt, &p.dc_ndcnt, &p.dc_nrot, &p.dc_perm, &p.dc_ndx, &p.dc_dfx, &p.dc_rota, &p.dc_rotb,
+                    &p.dc_orgi, &p.dc_cmap};
+    for (size_t* q : iv) *q = L.add(i4 * n * nk);
+    p.status = L.add(i4 * nk);
+    p.total = L.total;
+    return p;
+}
+
+template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+HetrdWs<double> hetrd_ws(const SolvePlan& p, void* w, double2* A, int64_t lda, int64_t sA, double2* V, double* d,
+                         double* e, double2* tau)
+{
+    HetrdWs<double> h{};
+    h.n = (int)p.n;
+    h.nb = p.nb;
+    h.NBmax = p.NBmax;
+    h.CHmax = p.CHmax;
+    h.A = A; h.lda = lda; h.sA = sA;
+    h.V = V; h.sV = p.n * p.n;
+    h.W = at<double2>(w, p.Wp); h.sW = p.n * p.nb;
+    h.d = d; h.e = e; h.tau = tau;
+    h.pnorm = at<double>(w, p.pnorm); h.s_pnorm = p.PN;
+    h.ypart = at<double2>(w, p.ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
+    h.ypartT = at<double2>(w, p.ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
+    h.pvw = at<double2>(w, p.pvw); h.pvv = at<double2>(w, p.pvv); h.s_pdot = (int64_t)p.NBmax * p.nb;
+    h.pyv = at<double2>(w, p.pyv);
+    h.ybuf = at<double2>(w, p.ybuf);
+    return h;
+}
+
+DcWs dc_ws(const SolvePlan& p, void* w, const double* d, const double* e, int* status)
+{
+    DcWs c{};
+    c.n = (int)p.n;
+    c.nk = p.nk;
+    c.din = d; c.ein = e; c.s_din = p.n;
+    c.es = at<double>(w, p.dc_es);
+    c.onrm = at<double>(w, p.dc_onrm);
+    c.D[0] = at<double>(w, p.dc_D0);
+    c.D[1] = at<double>(w, p.dc_D1);
+    c.sQ = p.n * p.n;
+    c.Vsec = at<double>(w, p.Vsec);
+    c.kcnt = at<int>(w, p.dc_kcnt); c.ndcnt = at<int>(w, p.dc_ndcnt); c.nrot = at<int>(w, p.dc_nrot);
+    c.rho = at<double>(w, p.dc_rho);
+    c.perm = at<int>(w, p.dc_perm); c.sd = at<double>(w, p.dc_sd); c.sz = at<double>(w, p.dc_sz);
+    c.ndx = at<int>(w, p.dc_ndx); c.ndd = at<double>(w, p.dc_ndd); c.ndz = at<double>(w, p.dc_ndz);
+    c.dfx = at<int>(w, p.dc_dfx); c.dfd = at<double>(w, p.dc_dfd);
+    c.rota = at<int>(w, p.dc_rota); c.rotb = at<int>(w, p.dc_rotb);
+    c.rotc = at<double>(w, p.dc_rotc); c.rots = at<double>(w, p.dc_rots);
+    c.orgi = at<int>(w, p.dc_orgi); c.tauv = at<double>(w, p.dc_tauv); c.lam = at<double>(w, p.dc_lam);
+    c.zhat = at<double>(w, p.dc_zhat); c.cmap = at<int>(w, p.dc_cmap);
+    c.s_w = p.n;
+    c.status = status;
+    return c;
+}
+
+kgev_opts resolve_opts(const kgev_opts* o)
+{
+    kgev_opts r;
+    kgev_opts_default(&r);
+    if (o) r = *o;
+    if (r.panel_nb == 0) r.panel_nb = DEFAULT_NB;
+    if (r.s_tol == 0.0) r.s_tol = 1e-12;
+    if (r.refine_iters == 0) r.refine_iters = 3;
+    return r;
+}
+
+bool opts_valid(const kgev_opts& o)
+{
+    if (o.precision != KGEV_PREC_FP64) return false;   // the mixed form is not built yet
+    if (o.want_vectors != 0 && o.want_vectors != 1) return false;
+    if (o.panel_nb < 1 || o.panel_nb > 64) return false;
+    if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
+    for (int q = 0; q < 8; ++q)
+        if (o.reserved[q] != 0) return false;
+    return true;
+}
+
+// With KGEV_DEBUG set in the environment, a failing HIP call is reported on
+// stderr (call site and HIP error name) before KGEV_EDEVICE is returned.
+bool debug_enabled()
+{
+    static const bool on = getenv("KGEV_DEBUG") != nullptr;
+    return on;
+}
+
+#define KCHECK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            if (debug_enabled())                                                            \
+                fprintf(stderr, "kgev: %s failed at %s:%d: %s\n", #expr, __FILE__, __LINE__, \
+                        hipGetErrorName(e_));                                               \
+            return KGEV_EDEVICE;                                                            \
+        }                                                                                   \
+    } while (0)
+
+kgev_status ensure_work(kgev_ctx* ctx, size_t bytes)
+{
+    if (ctx->work_bytes >= bytes) return KGEV_OK;
+    if (ctx->work) {
+        if (hipDeviceSynchronize() != hipSuccess) return KGEV_EDEVICE;
+        (void)hipFree(ctx->work);
+        ctx->work = nullptr;
+        ctx->work_bytes = 0;
+    }
+    if (hipMalloc(&ctx->work, bytes) != hipSuccess) {
+        ctx->work = nullptr;
+        return KGEV_ENOMEM;
+    }
+    ctx->work_bytes = bytes;
+    return KGEV_OK;
+}
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Eigen_HH on the batch whose working copies are in Aw (lower, ld n):
+// eigenvalues -> wout (stride n); vectors (if Y) -> Y (ld n).
+kgev_status eigen_hh(const SolvePlan& p, void* w, hipStream_t st, double* wout, double2* Y, int* status)
+{
+    const int64_t n = p.n, nk = p.nk, nn = n * n;
+    double2* Aw = at<double2>(w, p.Aw);
+    double2* Vs = at<double2>(w, p.Vs);
+    double* d = at<double>(w, p.d);
+    double* e = at<double>(w, p.e);
+    double2* tau = at<double2>(w, p.tau);
+    KCHECK(fill_zero(st, Vs, sizeof(double2) * (size_t)nn * nk));
+    KCHECK(hetrd<double>(st, hetrd_ws(p, w, Aw, n, nn, Vs, d, e, tau), nk));
+    double* Zr = at<double>(w, p.Zr);
+    KCHECK(stedc(st, dc_ws(p, w, d, e, status), wout, Zr, at<double>(w, p.Qs), nk));
+    if (!Y) return KGEV_OK;
+    KCHECK(real_to_complex<double>(st, n, Zr, nn, Y, n, nn, nk));
+    KCHECK(unmtr<double>(st, n, Vs, nn, tau, n, Y, n, nn, at<double2>(w, p.uwork), p.kb, nk));
+    return KGEV_OK;
+}
+
+kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStream_t st, const double2* H,
+                         const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status)
+{
+    const int64_t n = p.n, nk = p.nk, nn = n * n;
+    int* status = at<int>(w, p.status);
+    double2* Aw = at<double2>(w, p.Aw);
+    double2* Vs = at<double2>(w, p.Vs);
+    double2* X = at<double2>(w, p.X);
+    double2* G = at<double2>(w, p.G);
+    double* sS = at<double>(w, p.sS);
+    KCHECK(status_init(st, status, nk));
+    // inputs: non-finite check on both, S copied into the working matrix
+    KCHECK(copy_lower_check<double>(st, n, H, ld, ld * n, nullptr, 0, 0, status, nk));
+    KCHECK(copy_lower_check<double>(st, n, S, ld, ld * n, Aw, n, nn, status, nk));
+    // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2)
+    kgev_status r = eigen_hh(p, w, st, sS, X, status);
+    if (r != KGEV_OK) return r;
+    KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk));
+    // Part 3: A = X^H (H X), lower half
+    KCHECK(hermitian_full(st, n, H, ld, ld * n, Vs, n, nn, nk));
+    const double2 one = mk<double>(1, 0), zero = mk<double>(0, 0);
+    KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, Vs, n, nn, X, n, nn, zero, G, n, nn, nk, false));
+    KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, Aw, n, nn, nk, true));
+    // Part 4: A = Y diag(lambda) Y^H, C = X Y
+    r = eigen_hh(p, w, st, dw, o.want_vectors ? G : nullptr, status);
+    if (r != KGEV_OK) return r;
+    if (o.want_vectors) {
+        KCHECK(normalize_cols(st, n, G, n, nn, nullptr, 0, 0.0, nullptr, nk));
+        KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, dC, ldc, ldc * n, nk, false));
+    }
+    if (d_status) KCHECK(status_finish(st, status, d_status, nk));
+    return KGEV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kgev_opts_default(kgev_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->precision = KGEV_PREC_FP64;
+    o->want_vectors = 1;
+    o->panel_nb = 0;
+    o->refine_iters = 0;
+    o->s_tol = 0.0;
+}
+
+const char* kgev_status_str(kgev_status st)
+{
+    switch (st) {
+    case KGEV_OK: return "ok";
+    case KGEV_ENOTPD: return "S(k) is not positive definite";
+    case KGEV_ENOCONV: return "tridiagonal eigensolver did not converge";
+    case KGEV_ENONFINITE: return "non-finite value in H(k) or S(k)";
+    case KGEV_ENOMEM: return "out of memory";
+    case KGEV_EDEVICE: return "HIP runtime error";
+    case KGEV_EUNSUPPORTED: return "unsupported option";
+    default: return st < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+kgev_status kgev_create(kgev_ctx** ctx, int device)
+{
+    if (!ctx) return -1;
+    *ctx = nullptr;
+    int count = 0;
+    KCHECK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return -2;
+    DevGuard g(device);
+    kgev_ctx* c = new kgev_ctx{};
+    c->device = device;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (debug_enabled()) fprintf(stderr, "kgev: hipStreamCreateWithFlags: %s\n", hipGetErrorName(e));
+        delete c;
+        return KGEV_EDEVICE;
+    }
+    *ctx = c;
+    return KGEV_OK;
+}
+
+void kgev_destroy(kgev_ctx* ctx)
+{
+    if (!ctx) return;
+    DevGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->stage) (void)hipFree(ctx->stage);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+size_t kgev_workspace_bytes(int64_t n, int64_t nk, const kgev_opts* opts)
+{
+    if (n < 1 || nk < 1) return 0;
+    kgev_opts o = resolve_opts(opts);
+    return make_plan(n, nk, o.panel_nb).total;
+}
+
+kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
+                                int64_t nk, double* dw, kgev_z* dC, int64_t ldc, void* dwork, size_t work_bytes,
+                                int32_t* d_status, const kgev_opts* opts, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dH) return -2;
+    if (!dS) return -3;
+    if (n < 1) return -4;
+    if (ld < n) return -5;
+    if (nk < 1) return -6;
+    if (!dw) return -7;
+    kgev_opts o = resolve_opts(opts);
+    if (!opts_valid(o)) return (opts && opts->precision != KGEV_PREC_FP64) ? KGEV_EUNSUPPORTED : -10;
+    if (o.want_vectors && (!dC || ldc < n)) return -8;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    void* w = dwork;
+    if (w) {
+        if (work_bytes < p.total) return -9;
+    } else {
+        kgev_status r = ensure_work(ctx, p.total);
+        if (r != KGEV_OK) return r;
+        w = ctx->work;
+    }
+    return solve_device(p, o, w, (hipStream_t)stream, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC,
+                        ldc, d_status);
+}
+
+kgev_status kgev_solve_k(kgev_ctx* ctx, const kgev_z* H, const kgev_z* S, int64_t n, int64_t nk, double* w,
+                         kgev_z* C, const kgev_opts* opts, int64_t* bad_k)
+{
+    if (bad_k) *bad_k = -1;
+    if (!ctx) return -1;
+    if (!H) return -2;
+    if (!S) return -3;
+    if (n < 1) return -4;
+    if (nk < 1) return -5;
+    if (!w) return -6;
+    kgev_opts o = resolve_opts(opts);
+    if (!opts_valid(o)) return (opts && opts->precision != KGEV_PREC_FP64) ? KGEV_EUNSUPPORTED : -8;
+    if (o.want_vectors && !C) return -7;
+    DevGuard g(ctx->device);
+    const size_t mb = sizeof(double2) * (size_t)n * n * nk;
+    Layout L;
+    const size_t oH = L.add(mb), oS = L.add(mb), oC = L.add(o.want_vectors ? mb : 0),
+                 ow = L.add(sizeof(double) * n * nk), ost = L.add(sizeof(int) * nk);
+    if (ctx->stage_bytes < L.total) {
+        if (ctx->stage) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(ctx->stage);
+        }
+        ctx->stage = nullptr;
+        ctx->stage_bytes = 0;
+        if (hipMalloc(&ctx->stage, L.total) != hipSuccess) return KGEV_ENOMEM;
+        ctx->stage_bytes = L.total;
+    }
+    char* base = static_cast<char*>(ctx->stage);
+    hipStream_t st = ctx->stream;
+    KCHECK(hipMemcpyAsync(base + oH, H, mb, hipMemcpyHostToDevice, st));
+    KCHECK(hipMemcpyAsync(base + oS, S, mb, hipMemcpyHostToDevice, st));
+    kgev_status r = kgev_solve_k_device(ctx, (const kgev_z*)(base + oH), (const kgev_z*)(base + oS), n, n, nk,
+                                        (double*)(base + ow), o.want_vectors ? (kgev_z*)(base + oC) : nullptr, n,
+                                        nullptr, 0, (int32_t*)(base + ost), &o, st);
+    if (r != KGEV_OK) return r;
+    KCHECK(hipMemcpyAsync(w, base + ow, sizeof(double) * n * nk, hipMemcpyDeviceToHost, st));
+    if (o.want_vectors) KCHECK(hipMemcpyAsync(C, base + oC, mb, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> stv((size_t)nk);
+    KCHECK(hipMemcpyAsync(stv.data(), base + ost, sizeof(int32_t) * nk, hipMemcpyDeviceToHost, st));
+    KCHECK(hipStreamSynchronize(st));
+    for (int64_t q = 0; q < nk; ++q)
+        if (stv[q] != 0) {
+            if (bad_k) *bad_k = q;
+            return stv[q];
+        }
+    return KGEV_OK;
+}
+
+kgev_status kgev_hetrd_device(kgev_ctx* ctx, kgev_z* dA, int64_t n, int64_t lda, int64_t nk, double* dd, double* de,
+                              kgev_z* dtau, kgev_z* dV, const kgev_opts* opts, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dA) return -2;
+    if (n < 1) return -3;
+    if (lda < n) return -4;
+    if (nk < 1) return -5;
+    if (!dd) return -6;
+    if (!de) return -7;
+    if (!dtau) return -8;
+    if (!dV) return -9;
+    kgev_opts o = resolve_opts(opts);
+    if (o.panel_nb < 1 || o.panel_nb > 64) return -10;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    kgev_status r = ensure_work(ctx, p.total);
+    if (r != KGEV_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nn = n * n;
+    KCHECK(fill_zero(st, dV, sizeof(double2) * (size_t)nn * nk));
+    KCHECK(hetrd<double>(st, hetrd_ws(p, ctx->work, (double2*)dA, lda, lda * n, (double2*)dV, dd, de, (double2*)dtau),
+                         nk));
+    return KGEV_OK;
+}
+
+kgev_status kgev_stedc_device(kgev_ctx* ctx, const double* dd, const double* de, int64_t n, int64_t nk, double* dw,
+                              double* dZ, int32_t* d_status, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dd) return -2;
+    if (!de) return -3;
+    if (n < 1) return -4;
+    if (nk < 1) return -5;
+    if (!dw) return -6;
+    if (!dZ) return -7;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, DEFAULT_NB);
+    kgev_status r = ensure_work(ctx, p.total);
+    if (r != KGEV_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    int* status = at<int>(ctx->work, p.status);
+    KCHECK(status_init(st, status, nk));
+    KCHECK(stedc(st, dc_ws(p, ctx->work, dd, de, status), dw, dZ, at<double>(ctx->work, p.Qs), nk));
+    if (d_status) KCHECK(status_finish(st, status, d_status, nk));
+    return KGEV_OK;
+}
+
+kgev_status kgev_unmtr_device(kgev_ctx* ctx, const kgev_z* dV, const kgev_z* dtau, int64_t n, int64_t nk, kgev_z* dU,
+                              int64_t ldu, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dV) return -2;
+    if (!dtau) return -3;
+    if (n < 1) return -4;
+    if (nk < 1) return -5;
+    if (!dU) return -6;
+    if (ldu < n) return -7;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, DEFAULT_NB);
+    kgev_status r = ensure_work(ctx, p.total);
+    if (r != KGEV_OK) return r;
+    const int64_t nn = n * n;
+    KCHECK(unmtr<double>((hipStream_t)stream, n, (const double2*)dV, nn, (const double2*)dtau, n, (double2*)dU, ldu,
+                         ldu * n, at<double2>(ctx->work, p.uwork), p.kb, nk));
+    return KGEV_OK;
+}
+
+kgev_status kgev_eigh_device(kgev_ctx* ctx, const kgev_z* dA, int64_t n, int64_t lda, int64_t nk, double* dw,
+                             kgev_z* dY, int32_t* d_status, const kgev_opts* opts, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dA) return -2;
+    if (n < 1) return -3;
+    if (lda < n) return -4;
+    if (nk < 1) return -5;
+    if (!dw) return -6;
+    kgev_opts o = resolve_opts(opts);
+    if (o.panel_nb < 1 || o.panel_nb > 64) return -9;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    kgev_status r = ensure_work(ctx, p.total);
+    if (r != KGEV_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    void* w = ctx->work;
+    int* status = at<int>(w, p.status);
+    const int64_t nn = n * n;
+    KCHECK(status_init(st, status, nk));
+    KCHECK(copy_lower_check<double>(st, n, (const double2*)dA, lda, lda * n, at<double2>(w, p.Aw), n, nn, status, nk));
+    r = eigen_hh(p, w, st, dw, (double2*)dY, status);
+    if (r != KGEV_OK) return r;
+    if (dY) KCHECK(normalize_cols(st, n, (double2*)dY, n, nn, nullptr, 0, 0.0, nullptr, nk));
+    if (d_status) KCHECK(status_finish(st, status, d_status, nk));
+    return KGEV_OK;
+}
+
+kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m, int64_t n, int64_t k, kgev_z alpha,
+                              const kgev_z* dA, int64_t lda, int64_t sA, const kgev_z* dB, int64_t ldb, int64_t sB,
+                              kgev_z beta, kgev_z* dC, int64_t ldc, int64_t sC, int64_t batch, int32_t lower,
+                              void* stream)
+{
+    if (!ctx) return -1;
+    if (transa != 'N' && transa != 'C') return -2;
+    if (transb != 'N' && transb != 'C') return -3;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (k < 0) return -6;
+    if (!dA && m > 0 && k > 0) return -8;
+    if (lda < std::max<int64_t>(1, transa == 'N' ? m : k)) return -9;
+    if (!dB && n > 0 && k > 0) return -11;
+    if (ldb < std::max<int64_t>(1, transb == 'N' ? k : n)) return -12;
+    if (!dC && m > 0 && n > 0) return -15;
+    if (ldc < std::max<int64_t>(1, m)) return -16;
+    if (batch < 0) return -18;
+    if (lower && m != n) return -19;
+    DevGuard g(ctx->device);
+    KCHECK(cgemm<double>((hipStream_t)stream, transa, transb, m, n, k, mk<double>(alpha.re, alpha.im),
+                         (const double2*)dA, lda, sA, (const double2*)dB, ldb, sB, mk<double>(beta.re, beta.im),
+                         (double2*)dC, ldc, sC, batch, lower != 0));
+    return KGEV_OK;
+}
+
+}  // extern "C"

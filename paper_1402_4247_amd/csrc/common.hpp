@@ -1,0 +1,106 @@
+// Shared device helpers of the HIP library: complex arithmetic on interleaved
+// (re, im) pairs, wave-level reductions and the MFMA wrappers.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kgev {
+
+constexpr int WAVE = 64;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// complex numbers: double2 / float2 with x = re, y = im
+template <typename R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
+template <typename R> using cx = typename Cx<R>::T;
+
+template <typename R> __device__ __host__ inline cx<R> mk(R re, R im) { cx<R> z; z.x = re; z.y = im; return z; }
+template <typename C> __device__ inline C cadd(C a, C b) { C z; z.x = a.x + b.x; z.y = a.y + b.y; return z; }
+template <typename C> __device__ inline C csub(C a, C b) { C z; z.x = a.x - b.x; z.y = a.y - b.y; return z; }
+template <typename C> __device__ inline C cmul(C a, C b)
+{
+    C z;
+    z.x = a.x * b.x - a.y * b.y;
+    z.y = a.x * b.y + a.y * b.x;
+    return z;
+}
+// conj(a) * b
+template <typename C> __device__ inline C cmulc(C a, C b)
+{
+    C z;
+    z.x = a.x * b.x + a.y * b.y;
+    z.y = a.x * b.y - a.y * b.x;
+    return z;
+}
+// acc + a * b
+template <typename C> __device__ inline C cfma(C a, C b, C acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename C> __device__ inline C cfmac(C a, C b, C acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+template <typename C> __device__ inline C cconj(C a) { a.y = -a.y; return a; }
+template <typename C, typename R> __device__ inline C cscale(C a, R s) { a.x *= s; a.y *= s; return a; }
+template <typename C> __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
+
+// ---------------------------------------------------------------------------
+// wave reductions (64 lanes)
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16x4 (one block): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Accumulator register r of lane l holds D[row][l % 16]
+// with row = l / 16 + 4 r for the FP64 instruction and row = 4 (l / 16) + r
+// for the FP32 one (both measured on gfx950 with an in-bounds probe).
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+    using acc_t = d4_t;
+    static __device__ inline acc_t mma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc_t = f4_t;
+    static __device__ inline acc_t mma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+};
+
+}  // namespace kgev

@@ -1,0 +1,108 @@
+// Internal launcher declarations and workspace descriptors of the HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace kgev {
+
+// ---------------------------------------------------------------------------
+// matrix products (gemm.hip)
+template <typename R>
+hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,
+                 const cx<R>* A, int64_t lda, int64_t sA, const cx<R>* B, int64_t ldb, int64_t sB,
+                 cx<R> beta, cx<R>* C, int64_t ldc, int64_t sC, int64_t batch, bool lower);
+
+// C(lower) -= V W^H + W V^H   (m x m, inner dimension k)
+template <typename R>
+hipError_t cher2k_lower(hipStream_t st, int64_t m, int64_t k, const cx<R>* V, int64_t ldv, int64_t sV,
+                        const cx<R>* W, int64_t ldw, int64_t sW, cx<R>* C, int64_t ldc, int64_t sC,
+                        int64_t batch);
+
+// ---------------------------------------------------------------------------
+// blocked Householder tridiagonalisation (hetrd.hip)
+template <typename R>
+struct HetrdWs {
+    int n, nb;
+    int NBmax, CHmax;          // 64-row blocks of the largest trailing matrix; chunks per block column
+    cx<R>* A; int64_t lda, sA; // matrix (lower), reduced in place
+    cx<R>* V; int64_t sV;      // reflectors, n x n, ld n (zero outside the reflector rows)
+    cx<R>* W; int64_t sW;      // panel W, n x nb, ld n
+    R* d; R* e; cx<R>* tau;    // stride n per problem
+    R* pnorm; int64_t s_pnorm; // partial squared norms, ceil(n/256)
+    cx<R>* ypart; int64_t s_ypart;   // NBmax x NBmax x 64
+    cx<R>* ypartT; int64_t s_ypartT; // NBmax x CHmax x 64
+    cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;  // NBmax x nb
+    cx<R>* pyv;                // NBmax per problem
+    cx<R>* ybuf;               // n per problem
+};
+
+inline int hetrd_nbmax(int64_t n) { return (int)((n - 1 + 63) / 64) > 0 ? (int)((n - 1 + 63) / 64) : 1; }
+inline int hetrd_chmax(int64_t n) { return (hetrd_nbmax(n) + 3) / 4; }
+
+template <typename R>
+hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk);
+
+// ---------------------------------------------------------------------------
+// divide-and-conquer tridiagonal eigensolver (stedc.hip)
+struct DcWs {
+    int n;
+    int64_t nk;
+    const double* din; const double* ein; int64_t s_din;
+    double* es;          // scaled off-diagonal, n per problem
+    double* onrm;        // scale per problem
+    double* D[2];        // n per problem
+    double* Q[2]; int64_t sQ;  // n x n per problem; set by stedc()
+    double* Vsec;        // n x n per problem
+    int* kcnt; int* ndcnt; int* nrot; double* rho;   // per segment, stored at its first index
+    int* perm; double* sd; double* sz;
+    int* ndx; double* ndd; double* ndz;
+    int* dfx; double* dfd;
+    int* rota; int* rotb; double* rotc; double* rots;
+    int* orgi; double* tauv; double* lam; double* zhat; int* cmap;
+    int64_t s_w;         // stride of the eigenvalue output
+    int* status;         // per problem (may be null)
+};
+
+int dc_levels(int64_t n);
+hipError_t stedc(hipStream_t st, const DcWs& ws, double* w, double* Z, double* Qscratch, int64_t nk);
+
+// ---------------------------------------------------------------------------
+// small kernels (util.hip)
+hipError_t fill_zero(hipStream_t st, void* p, size_t bytes);
+// dst(lower) = src(lower) for nk matrices; flags non-finite entries in status (code 3)
+template <typename R>
+hipError_t copy_lower_check(hipStream_t st, int64_t n, const double2* src, int64_t lds, int64_t ss,
+                            cx<R>* dst, int64_t ldd, int64_t sd, int* status, int64_t nk);
+// dst = full Hermitian matrix from the lower triangle of src (diagonal made real)
+hipError_t hermitian_full(hipStream_t st, int64_t n, const double2* src, int64_t lds, int64_t ss, double2* dst,
+                          int64_t ldd, int64_t sd, int64_t nk);
+// dst (complex) = src (real), n x n, ld n
+template <typename R>
+hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t ss, cx<R>* dst, int64_t ldd,
+                           int64_t sd, int64_t nk);
+// columns to unit 2-norm, optionally divided by sqrt(s_j); with s given, also
+// sets status 1 when s_0 <= s_tol * s_{n-1}
+hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
+                          int64_t ss, double s_tol, int* status, int64_t nk);
+// T factor of a block of kb reflectors (columns c0..c0+kb-1 of V): T upper
+// triangular kb x kb, from G = V_b^H V_b
+template <typename R>
+hipError_t larft(hipStream_t st, int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau, int c0,
+                 cx<R>* T, int64_t sT, int64_t nk);
+hipError_t status_init(hipStream_t st, int* status, int64_t nk);
+// Per-k status words are bit sets while the solve runs; status_finish turns
+// them into the ABI codes, the input condition taking precedence:
+// non-finite input > S not positive definite > no convergence.
+constexpr int ST_NOTPD = 1, ST_NOCONV = 2, ST_NONFINITE = 4;
+hipError_t status_finish(hipStream_t st, const int* bits, int32_t* codes, int64_t nk);
+
+// back-transformation U <- Q U (unmtr.hip); work: see unmtr_work_elems
+template <typename R>
+hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
+                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk);
+int64_t unmtr_work_elems(int64_t n, int kb);   // complex elements per problem
+
+}  // namespace kgev

@@ -1,0 +1,271 @@
+// Small bandwidth-bound kernels of the path: input copy with the non-finite
+// check, full Hermitian matrix from the lower triangle, real -> complex,
+// eigenvector normalisation (Eigen_HH's last step) fused with Part 2's
+// rearrangement of S (x_j = u_j / sqrt(s_j)) and its definiteness check, and
+// the triangular factor of a block of reflectors (compact WY).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace kgev {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t* p, int64_t words)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < words; q += stride) p[q] = 0u;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_copy_lower_check(int64_t n, const double2* __restrict__ src, int64_t lds,
+                                                          int64_t ss, cx<R>* __restrict__ dst, int64_t ldd,
+                                                          int64_t sd, int* status)
+{
+    const int64_t b = blockIdx.z;
+    const int64_t j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < n && i >= j) {
+        const double2 v = src[b * ss + i + j * lds];
+        bad = !isfinite(v.x) || !isfinite(v.y);
+        if (dst) dst[b * sd + i + j * ldd] = mk<R>((R)v.x, (R)((i == j) ? 0.0 : v.y));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0 && status) atomicOr(status + b, ST_NONFINITE);
+}
+
+// 32x32 tiles through LDS; tiles on or below the diagonal only
+__global__ __launch_bounds__(256) void k_hermitian_full(int64_t n, const double2* __restrict__ src, int64_t lds,
+                                                        int64_t ss, double2* __restrict__ dst, int64_t ldd, int64_t sd)
+{
+    __shared__ double2 T[32][33];
+    const int64_t b = blockIdx.z;
+    const int bi = blockIdx.x, bj = blockIdx.y;
+    if (bi < bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t i0 = (int64_t)bi * 32, j0 = (int64_t)bj * 32;
+    const double2* S = src + b * ss;
+    double2* D = dst + b * sd;
+    for (int c = ty; c < 32; c += 8) {
+        const int64_t i = i0 + tx, j = j0 + c;
+        T[c][tx] = (i < n && j < n) ? S[i + j * lds] : czero<double2>();
+    }
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+        // direct: D(i0+tx, j0+c)
+        const int64_t i = i0 + tx, j = j0 + c;
+        if (i < n && j < n) {
+            double2 v;
+            if (i > j) v = T[c][tx];
+            else if (i == j) v = mk<double>(T[c][tx].x, 0.0);
+            else v = cconj(T[tx][c]);      // diagonal tile only: (i, j) with i < j
+            D[i + j * ldd] = v;
+        }
+        // mirrored: D(j0+tx, i0+c) = conj(S(i0+c, j0+tx)) for the strict lower tile
+        if (bi != bj) {
+            const int64_t i2 = j0 + tx, j2 = i0 + c;
+            if (i2 < n && j2 < n) D[i2 + j2 * ldd] = cconj(T[tx][c]);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_real_to_complex(int64_t n, const double* __restrict__ src, int64_t ss,
+                                                         cx<R>* __restrict__ dst, int64_t ldd, int64_t sd)
+{
+    const int64_t b = blockIdx.z;
+    const int64_t j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[b * sd + i + j * ldd] = mk<R>((R)src[b * ss + i + j * n], (R)0);
+}
+
+// one workgroup per column
+__global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
+                                                       int64_t sst, double s_tol, int* status)
+{
+    __shared__ double sh[4];
+    const int64_t b = blockIdx.y;
+    const int64_t j = blockIdx.x;
+    double2* u = U + b * su + j * ldu;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double2 v = u[i];
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double ss = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    double f = 1.0 / sqrt(ss);
+    if (s) {
+        const double sj = s[b * sst + j];
+        f = f / sqrt(sj);
+        if (j == 0 && threadIdx.x == 0 && status) {
+            const double smax = s[b * sst + n - 1];
+            if (!(sj > s_tol * smax)) atomicOr(status + b, ST_NOTPD);
+        }
+    }
+    for (int64_t i = threadIdx.x; i < n; i += 256) u[i] = cscale(u[i], f);
+}
+
+// T (kb x kb, ld kb, upper) for reflectors c0..c0+kb-1:
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V_b^H V_b.
+constexpr int KBMAX = 64;
+template <typename R>
+__global__ __launch_bounds__(64) void k_larft(int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau,
+                                              int c0, cx<R>* T, int64_t strT)
+{
+    __shared__ cx<R> sT[KBMAX][KBMAX + 1];   // sT[col][row]
+    __shared__ cx<R> sg[KBMAX];
+    const int64_t b = blockIdx.x;
+    const int r = threadIdx.x;
+    const cx<R>* g = G + b * sG;
+    for (int j = 0; j < kb; ++j) {
+        if (r < j) sg[r] = g[r + (int64_t)j * kb];
+        __syncthreads();
+        const cx<R> tj = tau[b * stau + c0 + j];
+        if (r < j) {
+            cx<R> acc = czero<cx<R>>();
+            for (int q = r; q < j; ++q) acc = cfma(sT[q][r], sg[q], acc);
+            sT[j][r] = cscale(cmul(tj, acc), (R)-1);
+        } else if (r == j) {
+            sT[j][r] = tj;
+        } else if (r < kb) {
+            sT[j][r] = czero<cx<R>>();
+        }
+        __syncthreads();
+    }
+    cx<R>* Tb = T + b * strT;
+    for (int j = 0; j < kb; ++j)
+        if (r < kb) Tb[r + (int64_t)j * kb] = sT[j][r];
+}
+
+}  // namespace
+
+hipError_t fill_zero(hipStream_t st, void* p, size_t bytes)
+{
+    if (bytes == 0) return hipSuccess;
+    const int64_t words = (int64_t)(bytes / 4);
+    int64_t blocks = (words + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, words);
+    return hipGetLastError();
+}
+
+hipError_t status_init(hipStream_t st, int* status, int64_t nk) { return fill_zero(st, status, sizeof(int) * nk); }
+
+namespace {
+__global__ __launch_bounds__(256) void k_status_finish(const int* bits, int32_t* codes, int64_t nk)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nk) return;
+    const int b = bits[q];
+    codes[q] = (b & ST_NONFINITE) ? 3 : (b & ST_NOTPD) ? 1 : (b & ST_NOCONV) ? 2 : 0;
+}
+}  // namespace
+
+hipError_t status_finish(hipStream_t st, const int* bits, int32_t* codes, int64_t nk)
+{
+    hipLaunchKernelGGL(k_status_finish, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, bits, codes, nk);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t copy_lower_check(hipStream_t st, int64_t n, const double2* src, int64_t lds, int64_t ss, cx<R>* dst,
+                            int64_t ldd, int64_t sd, int* status, int64_t nk)
+{
+    dim3 g((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nk);
+    hipLaunchKernelGGL(k_copy_lower_check<R>, g, dim3(256), 0, st, n, src, lds, ss, dst, ldd, sd, status);
+    return hipGetLastError();
+}
+
+hipError_t hermitian_full(hipStream_t st, int64_t n, const double2* src, int64_t lds, int64_t ss, double2* dst,
+                          int64_t ldd, int64_t sd, int64_t nk)
+{
+    const unsigned t = (unsigned)((n + 31) / 32);
+    hipLaunchKernelGGL(k_hermitian_full, dim3(t, t, (unsigned)nk), dim3(256), 0, st, n, src, lds, ss, dst, ldd, sd);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t ss, cx<R>* dst, int64_t ldd,
+                           int64_t sd, int64_t nk)
+{
+    dim3 g((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nk);
+    hipLaunchKernelGGL(k_real_to_complex<R>, g, dim3(256), 0, st, n, src, ss, dst, ldd, sd);
+    return hipGetLastError();
+}
+
+hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s, int64_t ss,
+                          double s_tol, int* status, int64_t nk)
+{
+    hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, U, ldu, su, s, ss,
+                       s_tol, status);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t larft(hipStream_t st, int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau, int c0,
+                 cx<R>* T, int64_t sT, int64_t nk)
+{
+    if (kb > KBMAX || kb < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_larft<R>, dim3((unsigned)nk), dim3(64), 0, st, kb, G, sG, tau, stau, c0, T, sT);
+    return hipGetLastError();
+}
+
+template hipError_t copy_lower_check<double>(hipStream_t, int64_t, const double2*, int64_t, int64_t, double2*,
+                                             int64_t, int64_t, int*, int64_t);
+template hipError_t copy_lower_check<float>(hipStream_t, int64_t, const double2*, int64_t, int64_t, float2*,
+                                            int64_t, int64_t, int*, int64_t);
+template hipError_t real_to_complex<double>(hipStream_t, int64_t, const double*, int64_t, double2*, int64_t,
+                                            int64_t, int64_t);
+template hipError_t real_to_complex<float>(hipStream_t, int64_t, const double*, int64_t, float2*, int64_t,
+                                           int64_t, int64_t);
+template hipError_t larft<double>(hipStream_t, int, const double2*, int64_t, const double2*, int64_t, int, double2*,
+                                  int64_t, int64_t);
+template hipError_t larft<float>(hipStream_t, int, const float2*, int64_t, const float2*, int64_t, int, float2*,
+                                 int64_t, int64_t);
+
+// ---------------------------------------------------------------------------
+// Back-transformation U <- Q U, Q = H_0 ... H_{n-2}, in blocks of kb
+// reflectors applied last block first as (I - V_b T_b V_b^H).
+int64_t unmtr_work_elems(int64_t n, int kb) { return 2 * (int64_t)kb * kb + 2 * (int64_t)kb * n; }
+
+template <typename R>
+hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
+                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk)
+{
+    const int64_t nref = n - 1;
+    if (nref <= 0) return hipSuccess;
+    const int64_t sw = unmtr_work_elems(n, kb);
+    cx<R>* G = work;
+    cx<R>* T = work + (int64_t)kb * kb;
+    cx<R>* W1 = work + 2 * (int64_t)kb * kb;
+    cx<R>* W2 = W1 + (int64_t)kb * n;
+    const cx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+    const int64_t nblk = (nref + kb - 1) / kb;
+    for (int64_t blk = nblk - 1; blk >= 0; --blk) {
+        const int64_t c0 = blk * kb;
+        const int kk = (int)((nref - c0) < kb ? (nref - c0) : kb);
+        const int64_t r0 = c0 + 1, m = n - r0;
+        const cx<R>* Vb = V + r0 + c0 * n;
+        hipError_t e;
+        e = cgemm<R>(st, 'C', 'N', kk, kk, m, one, Vb, n, sV, Vb, n, sV, zero, G, kk, sw, nk, false);
+        if (e != hipSuccess) return e;
+        e = larft<R>(st, kk, G, sw, tau, stau, (int)c0, T, sw, nk);
+        if (e != hipSuccess) return e;
+        e = cgemm<R>(st, 'C', 'N', kk, n, m, one, Vb, n, sV, U + r0, ldu, sU, zero, W1, kk, sw, nk, false);
+        if (e != hipSuccess) return e;
+        e = cgemm<R>(st, 'N', 'N', kk, n, kk, one, T, kk, sw, W1, kk, sw, zero, W2, kk, sw, nk, false);
+        if (e != hipSuccess) return e;
+        e = cgemm<R>(st, 'N', 'N', m, n, kk, mone, Vb, n, sV, W2, kk, sw, one, U + r0, ldu, sU, nk, false);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t unmtr<double>(hipStream_t, int64_t, const double2*, int64_t, const double2*, int64_t, double2*,
+                                  int64_t, int64_t, double2*, int, int64_t);
+template hipError_t unmtr<float>(hipStream_t, int64_t, const float2*, int64_t, const float2*, int64_t, float2*,
+                                 int64_t, int64_t, float2*, int, int64_t);
+
+}  // namespace kgev

@@ -1,0 +1,203 @@
+"""Python binding of the HIP library ``libkgev.so`` (C ABI in include/kgev.h).
+
+Argument marshalling only: every step of the eigensolve runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.
+Loading fails loudly when the library has not been built; there is no
+fallback of any kind.
+
+Matrices handed to the library are column-major.  For a stack of matrices
+held as a torch tensor ``M`` of shape (nk, n, n) with ``M[q, i, j]`` the
+element (i, j), ``colmajor(M)`` gives the buffer the library reads.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkgev.so")
+
+OK, ENOTPD, ENOCONV, ENONFINITE = 0, 1, 2, 3
+ENOMEM, EDEVICE, EUNSUPPORTED = -100, -101, -102
+PREC_FP64, PREC_FP32_REFINE = 0, 1
+
+
+class KgevError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__(f"{fn} failed with status {status} ({status_str(status)})")
+        self.status = status
+
+
+class Z(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
+                ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
+                ("s_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
+           "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
+           "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device"]
+
+
+def _load():
+    # PyTorch bundles its own HIP runtime.  Load it first when it is installed,
+    # so that the library binds to that same runtime (one runtime per process:
+    # device pointers and streams from torch are then valid here).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1402_4247_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.kgev_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    lib.kgev_status_str.argtypes = [I32]
+    lib.kgev_status_str.restype = ctypes.c_char_p
+    lib.kgev_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.kgev_create.restype = I32
+    lib.kgev_destroy.argtypes = [P]
+    lib.kgev_workspace_bytes.argtypes = [I64, I64, ctypes.POINTER(Opts)]
+    lib.kgev_workspace_bytes.restype = ctypes.c_size_t
+    lib.kgev_solve_k.argtypes = [P, P, P, I64, I64, P, P, ctypes.POINTER(Opts), ctypes.POINTER(I64)]
+    lib.kgev_solve_k.restype = I32
+    lib.kgev_solve_k_device.argtypes = [P, P, P, I64, I64, I64, P, P, I64, P, ctypes.c_size_t, P,
+                                        ctypes.POINTER(Opts), P]
+    lib.kgev_solve_k_device.restype = I32
+    lib.kgev_hetrd_device.argtypes = [P, P, I64, I64, I64, P, P, P, P, ctypes.POINTER(Opts), P]
+    lib.kgev_hetrd_device.restype = I32
+    lib.kgev_stedc_device.argtypes = [P, P, P, I64, I64, P, P, P, P]
+    lib.kgev_stedc_device.restype = I32
+    lib.kgev_unmtr_device.argtypes = [P, P, P, I64, I64, P, I64, P]
+    lib.kgev_unmtr_device.restype = I32
+    lib.kgev_eigh_device.argtypes = [P, P, I64, I64, I64, P, P, P, ctypes.POINTER(Opts), P]
+    lib.kgev_eigh_device.restype = I32
+    lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
+                                      P, I64, I64, Z, P, I64, I64, I64, I32, P]
+    lib.kgev_zgemm_device.restype = I32
+    return lib
+
+
+lib = _load()
+
+
+def status_str(st: int) -> str:
+    return lib.kgev_status_str(int(st)).decode()
+
+
+def _check(fn, st):
+    if st != OK:
+        raise KgevError(fn, st)
+
+
+def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0) -> Opts:
+    o = Opts()
+    lib.kgev_opts_default(ctypes.byref(o))
+    o.precision = precision
+    o.want_vectors = 1 if want_vectors else 0
+    o.panel_nb = panel_nb
+    o.refine_iters = refine_iters
+    o.s_tol = s_tol
+    return o
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def colmajor(M):
+    """(..., n, n) torch tensor -> contiguous tensor whose memory holds each
+    matrix column-major."""
+    return M.transpose(-1, -2).contiguous()
+
+
+def from_colmajor(buf):
+    return buf.transpose(-1, -2)
+
+
+class Context:
+    """Owns one kgev_ctx on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check("kgev_create", lib.kgev_create(ctypes.byref(h), int(device)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.kgev_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def workspace_bytes(n: int, nk: int, opts: Opts | None = None) -> int:
+    return int(lib.kgev_workspace_bytes(n, nk, None if opts is None else ctypes.byref(opts)))
+
+
+def solve_k_device(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, dwork=None, work_bytes=0, d_status=None,
+                   opts: Opts | None = None, stream=None) -> int:
+    """kgev_solve_k_device on torch device tensors (column-major buffers)."""
+    return lib.kgev_solve_k_device(ctx.handle, _ptr(dH), _ptr(dS), n, ld, nk, _ptr(dw), _ptr(dC), ldc,
+                                   _ptr(dwork), work_bytes, _ptr(d_status),
+                                   None if opts is None else ctypes.byref(opts), _stream(stream))
+
+
+def solve_k(ctx: Context, H, S, n, nk, w, C, opts: Opts | None = None):
+    """kgev_solve_k on host numpy buffers (complex128, column-major per k).
+    Returns (status, bad_k)."""
+    bad = ctypes.c_int64(-1)
+    st = lib.kgev_solve_k(ctx.handle, H.ctypes.data_as(ctypes.c_void_p), S.ctypes.data_as(ctypes.c_void_p),
+                          n, nk, w.ctypes.data_as(ctypes.c_void_p),
+                          None if C is None else C.ctypes.data_as(ctypes.c_void_p),
+                          None if opts is None else ctypes.byref(opts), ctypes.byref(bad))
+    return st, bad.value
+
+
+def hetrd_device(ctx, dA, n, lda, nk, dd, de, dtau, dV, opts=None, stream=None) -> int:
+    return lib.kgev_hetrd_device(ctx.handle, _ptr(dA), n, lda, nk, _ptr(dd), _ptr(de), _ptr(dtau), _ptr(dV),
+                                 None if opts is None else ctypes.byref(opts), _stream(stream))
+
+
+def stedc_device(ctx, dd, de, n, nk, dw, dZ, d_status=None, stream=None) -> int:
+    return lib.kgev_stedc_device(ctx.handle, _ptr(dd), _ptr(de), n, nk, _ptr(dw), _ptr(dZ), _ptr(d_status),
+                                 _stream(stream))
+
+
+def unmtr_device(ctx, dV, dtau, n, nk, dU, ldu, stream=None) -> int:
+    return lib.kgev_unmtr_device(ctx.handle, _ptr(dV), _ptr(dtau), n, nk, _ptr(dU), ldu, _stream(stream))
+
+
+def eigh_device(ctx, dA, n, lda, nk, dw, dY, d_status=None, opts=None, stream=None) -> int:
+    return lib.kgev_eigh_device(ctx.handle, _ptr(dA), n, lda, nk, _ptr(dw), _ptr(dY), _ptr(d_status),
+                                None if opts is None else ctypes.byref(opts), _stream(stream))
+
+
+def zgemm_device(ctx, transa, transb, m, n, k, alpha, dA, lda, sA, dB, ldb, sB, beta, dC, ldc, sC, batch,
+                 lower=False, stream=None) -> int:
+    al, be = complex(alpha), complex(beta)
+    return lib.kgev_zgemm_device(ctx.handle, transa.encode(), transb.encode(), m, n, k, Z(al.real, al.imag),
+                                 _ptr(dA), lda, sA, _ptr(dB), ldb, sB, Z(be.real, be.imag), _ptr(dC), ldc, sC,
+                                 batch, 1 if lower else 0, _stream(stream))

@@ -1,0 +1,65 @@
+"""The C-ABI library loads on any host, exports every entry point that
+include/kgev.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1402_4247_amd import kgev as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "kgev.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kgev_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(K.lib, name), name
+    assert set(names) == set(K.EXPORTS)
+
+
+def test_library_is_the_in_tree_build():
+    assert os.path.dirname(K.LIB_PATH) == os.path.join(ROOT, "paper_1402_4247_amd")
+
+
+def test_status_strings_and_defaults():
+    assert K.status_str(0) == "ok"
+    assert "positive definite" in K.status_str(1)
+    assert "converge" in K.status_str(2)
+    assert "non-finite" in K.status_str(3)
+    o = K.make_opts()
+    assert o.precision == 0 and o.want_vectors == 1 and all(r == 0 for r in o.reserved)
+
+
+def test_workspace_bytes_scales_with_problem():
+    assert K.workspace_bytes(0, 1) == 0 and K.workspace_bytes(8, 0) == 0
+    w1 = K.workspace_bytes(1000, 1)
+    w2 = K.workspace_bytes(2000, 1)
+    w16 = K.workspace_bytes(2000, 16)
+    assert w1 > 0 and 3.5 < w2 / w1 < 4.5 and 15.5 < w16 / w2 < 16.5
+    # resident state ~ 4 complex + 3 real n x n matrices per k-point
+    assert w2 < 100 * 2000 * 2000
+
+
+@pytest.mark.parametrize("args,code", [
+    # (ctx, H, S, n, ld, nk, w, C, ldc) -> first failing argument
+    ((None, 1, 1, 4, 4, 1, 1, 1, 4), -1),
+])
+def test_null_context_rejected(args, code):
+    ctx, H, S, n, ld, nk, w, C, ldc = args
+    st = K.lib.kgev_solve_k_device(None, ctypes.c_void_p(H), ctypes.c_void_p(S), n, ld, nk,
+                                   ctypes.c_void_p(w), ctypes.c_void_p(C), ldc, None, 0, None, None, None)
+    assert st == code
+
+
+def test_host_api_rejects_null_context():
+    bad = ctypes.c_int64(7)
+    st = K.lib.kgev_solve_k(None, None, None, 4, 1, None, None, None, ctypes.byref(bad))
+    assert st == -1 and bad.value == -1
