@@ -1,0 +1,172 @@
+"""Benchmark: k-point eigensolves/s of the per-k generalized Hermitian
+eigensolve (Band_DFT_Col Parts 2-4) on one MI355X.
+
+One step = one call of kgev_solve_k_device on a batch of nk k-points of the
+magnetite-like LCAO workload (n = 2000, 16 k-points of the 4x4x4 grid,
+complex128, all eigenpairs), inputs resident in HBM.  Prints ONE JSON line.
+
+Extra fields:
+  roofline      dominant kernel measured with HIP events (recorded by the
+                library around each of its launches, on the stream it is
+                enqueued on) over the timed steps;
+  cpu_baseline  the plain FP64 oracle on a bounded sample of the same work
+                (one of the k-points), timed on the host cores;
+  latency_ms    p50/p99 of single-k-point calls (nk = 1);
+  check         residuals of one k-point and its eigenvalue error against the
+                oracle's.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "k-point eigensolves/s at n=2000 (FP64 vs FP32+refine); p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2000)
+    ap.add_argument("--nk", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=2002)
+    ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
+    ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the per-k solve needs no "
+                                   "communication and shards by k-point (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1402_4247_amd import inputs as G
+    from paper_1402_4247_amd import kgev as K
+
+    n, nk = args.n, args.nk
+    log(f"[bench] generating workload n={n} nk={nk}")
+    Hs, Ss = G.config2(n, nk, args.seed)
+    dev = torch.device("cuda:0")
+    dH = torch.from_numpy(G.colmajor(Hs)).to(dev)
+    dS = torch.from_numpy(G.colmajor(Ss)).to(dev)
+    dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
+    dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
+    dst = torch.zeros(nk, dtype=torch.int32, device=dev)
+    opts = K.make_opts()
+    ctx = K.Context(0)
+
+    def step():
+        st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
+        if st != 0:
+            raise RuntimeError(f"kgev_solve_k_device returned {st}")
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    phase = K.PHASE_HEMV if args.roofline_phase == "hemv" else K.PHASE_GEMM
+    K.profile_begin(ctx, phase)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = K.profile_end(ctx)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = nk * args.steps / elapsed
+    status = dst.cpu().numpy()
+    log(f"[bench] {ms_per_step:.1f} ms/step, {value:.2f} solves/s, status {set(status.tolist())}")
+
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    if phase == K.PHASE_HEMV:
+        per_launch = prof["bytes"] / max(prof["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "hetrd_zhemv", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
+                "alg_bytes_per_launch": per_launch,
+                "share_of_step": prof["ms"] / (1e3 * elapsed)}
+    else:
+        per_launch = prof["flops"] / max(prof["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "cgemm_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
+                "alg_flops_per_launch": per_launch,
+                "share_of_step": prof["ms"] / (1e3 * elapsed)}
+
+    # latency of single-k-point calls
+    lat = []
+    w1 = torch.zeros((1, n), dtype=torch.float64, device=dev)
+    C1 = torch.zeros((1, n, n), dtype=torch.complex128, device=dev)
+    for r in range(args.latency_reps + 2):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = K.solve_k_device(ctx, dH[:1], dS[:1], n, n, 1, w1, C1, n, opts=opts)
+        torch.cuda.synchronize()
+        if st != 0:
+            raise RuntimeError(f"latency call returned {st}")
+        if r >= 2:
+            lat.append(1e3 * (time.perf_counter() - a))
+    lat = np.array(lat)
+    log(f"[bench] latency p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+
+    # accuracy of k-point 0 of the timed batch
+    w0 = dw[0].cpu().numpy()
+    C0 = dC[0].cpu().numpy().T
+    H0, S0 = Hs[0], Ss[0]
+    r_res = float(np.linalg.norm(H0 @ C0 - S0 @ C0 * w0) / np.linalg.norm(H0))
+    r_orth = float(np.abs(C0.conj().T @ S0 @ C0 - np.eye(n)).max())
+    check = {"k": 0, "r_res": r_res, "r_orth": r_orth, "status_all_ok": bool(np.all(status == 0))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.max_threads()
+        log(f"[bench] cpu baseline: oracle on k-point 0 with {threads} threads")
+        a = time.perf_counter()
+        st0, wor, _ = O.solve_k(H0, S0)
+        t_or = time.perf_counter() - a
+        cpu = {"value": 1.0 / t_or, "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"1 of the {nk} k-points (k index 0) at n={n}, all eigenpairs; {t_or:.1f} s"}
+        check["eig_err_vs_oracle_rel"] = float(np.abs(w0 - wor).max() / np.abs(wor).max())
+        check["oracle_status"] = int(st0)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
+                               "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
+                   "n": n, "nk": nk, "precision": "fp64", "seed": args.seed},
+        "roofline": roof, "cpu_baseline": cpu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "reps": int(lat.size), "nk": 1},
+        "check": check,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

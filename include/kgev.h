@@ -199,6 +199,27 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
                               const kgev_z* dB, int64_t ldb, int64_t sB, kgev_z beta, kgev_z* dC,
                               int64_t ldc, int64_t sC, int64_t batch, int32_t lower, void* stream);
 
+/*
+ * Kernel timing for measurement.  Between kgev_profile_begin and
+ * kgev_profile_end, every launch of the chosen phase made through this
+ * context is bracketed by two HIP events on the stream it is enqueued on, and
+ * the phase's algorithmic work per launch is tallied:
+ *   KGEV_PHASE_HEMV : the Hermitian product A22 v of the tridiagonalisation
+ *                     (Procedure 4); work = bytes of the lower triangle of the
+ *                     trailing matrix, 16 m (m + 1) / 2 per k-point;
+ *   KGEV_PHASE_GEMM : every complex matrix product on MFMA; work = real flops,
+ *                     8 m n k per product (half for lower-only outputs).
+ * kgev_profile_end waits for the recorded events, returns the number of
+ * launches, their summed duration in milliseconds and the summed algorithmic
+ * bytes and flops, and stops recording.  Timing adds two event records per
+ * launch of the chosen phase and nothing else.
+ */
+#define KGEV_PHASE_HEMV 1
+#define KGEV_PHASE_GEMM 2
+kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase);
+kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes,
+                             double* alg_flops);
+
 #ifdef __cplusplus
 }
 #endif

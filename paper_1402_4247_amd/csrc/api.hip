@@ -21,8 +21,15 @@
 
 using namespace kgev;
 
+namespace kgev {
+struct Profiler;
+Profiler* prof_start(int phase, size_t reserve);
+bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double* flops);
+}  // namespace kgev
+
 struct kgev_ctx {
     int device;
+    kgev::Profiler* prof;
     void* work;
     size_t work_bytes;
     // host-pointer API staging buffers
@@ -336,6 +343,7 @@ void kgev_destroy(kgev_ctx* ctx)
     if (!ctx) return;
     DevGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -546,6 +554,27 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
                          (const double2*)dA, lda, sA, (const double2*)dB, ldb, sB, mk<double>(beta.re, beta.im),
                          (double2*)dC, ldc, sC, batch, lower != 0));
     return KGEV_OK;
+}
+
+kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase)
+{
+    if (!ctx) return -1;
+    if (phase != KGEV_PHASE_HEMV && phase != KGEV_PHASE_GEMM) return -2;
+    DevGuard g(ctx->device);
+    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
+    ctx->prof = prof_start(phase, 16384);
+    return KGEV_OK;
+}
+
+kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes,
+                             double* alg_flops)
+{
+    if (!ctx) return -1;
+    if (!ctx->prof) return KGEV_EUNSUPPORTED;
+    DevGuard g(ctx->device);
+    const bool ok = prof_stop(ctx->prof, launches, total_ms, alg_bytes, alg_flops);
+    ctx->prof = nullptr;
+    return ok ? KGEV_OK : KGEV_EDEVICE;
 }
 
 }  // extern "C"

@@ -212,7 +212,11 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
     p.tiles_m = (int)((a.m + GB_M - 1) / GB_M);
     const int64_t tiles_n = (a.n + GB_N - 1) / GB_N;
     dim3 grid((unsigned)(p.tiles_m * tiles_n), 1, (unsigned)batch);
+    double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch;
+    if (a.lower) flops *= 0.5;
+    prof_before(PH_GEMM, st);
     hipLaunchKernelGGL(cgemm_kernel<R>, grid, dim3(G_THREADS), 0, st, p);
+    prof_after(PH_GEMM, st, 0.0, flops);
     return hipGetLastError();
 }
 

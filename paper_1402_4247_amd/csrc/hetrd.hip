@@ -331,7 +331,9 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int NB = (m + ZT - 1) / ZT;
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
+            prof_before(PH_HEMV, st);
             hipLaunchKernelGGL(hetrd_zhemv<R>, dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i, p);
+            prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             hipLaunchKernelGGL(hetrd_reduce<R>, dim3((unsigned)NB, (unsigned)nk), dim3(64), 0, st, ws, i, p);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             dim3 g4((unsigned)((n - o + RB - 1) / RB), (unsigned)nk);

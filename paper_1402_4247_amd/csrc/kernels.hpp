@@ -9,6 +9,13 @@
 namespace kgev {
 
 // ---------------------------------------------------------------------------
+// launch timing (profile.cpp): while a phase is being profiled on this host
+// thread, its launch sites bracket each launch with two events.
+enum Phase { PH_NONE = 0, PH_HEMV = 1, PH_GEMM = 2 };
+void prof_before(int phase, hipStream_t st);
+void prof_after(int phase, hipStream_t st, double bytes, double flops);
+
+// ---------------------------------------------------------------------------
 // matrix products (gemm.hip)
 template <typename R>
 hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,

@@ -40,7 +40,9 @@ class Opts(ctypes.Structure):
 
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
-           "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device"]
+           "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
+           "kgev_profile_begin", "kgev_profile_end"]
+PHASE_HEMV, PHASE_GEMM = 1, 2
 
 
 def _load():
@@ -79,6 +81,11 @@ def _load():
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
+    lib.kgev_profile_begin.argtypes = [P, I32]
+    lib.kgev_profile_begin.restype = I32
+    lib.kgev_profile_end.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D),
+                                     ctypes.POINTER(D)]
+    lib.kgev_profile_end.restype = I32
     return lib
 
 
@@ -201,3 +208,16 @@ def zgemm_device(ctx, transa, transb, m, n, k, alpha, dA, lda, sA, dB, ldb, sB, 
     return lib.kgev_zgemm_device(ctx.handle, transa.encode(), transb.encode(), m, n, k, Z(al.real, al.imag),
                                  _ptr(dA), lda, sA, _ptr(dB), ldb, sB, Z(be.real, be.imag), _ptr(dC), ldc, sC,
                                  batch, 1 if lower else 0, _stream(stream))
+
+
+def profile_begin(ctx, phase) -> None:
+    _check("kgev_profile_begin", lib.kgev_profile_begin(ctx.handle, int(phase)))
+
+
+def profile_end(ctx):
+    """Returns dict(launches, ms, bytes, flops) for the profiled phase."""
+    n = ctypes.c_int64()
+    ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check("kgev_profile_end", lib.kgev_profile_end(ctx.handle, ctypes.byref(n), ctypes.byref(ms),
+                                                    ctypes.byref(by), ctypes.byref(fl)))
+    return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
