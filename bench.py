@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--nk", type=int, default=16)
     ap.add_argument("--seed", type=int, default=2002)
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
-    ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--latency-reps", type=int, default=20, help="0 skips the latency measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -117,9 +117,10 @@ def main():
 
     # latency of single-k-point calls
     lat = []
+    reps_total = args.latency_reps + 2 if args.latency_reps > 0 else 0
     w1 = torch.zeros((1, n), dtype=torch.float64, device=dev)
     C1 = torch.zeros((1, n, n), dtype=torch.complex128, device=dev)
-    for r in range(args.latency_reps + 2):
+    for r in range(reps_total):
         torch.cuda.synchronize()
         a = time.perf_counter()
         st = K.solve_k_device(ctx, dH[:1], dS[:1], n, n, 1, w1, C1, n, opts=opts)
@@ -128,7 +129,7 @@ def main():
             raise RuntimeError(f"latency call returned {st}")
         if r >= 2:
             lat.append(1e3 * (time.perf_counter() - a))
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.array([float("nan")])
     log(f"[bench] latency p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
 
     # accuracy of k-point 0 of the timed batch
@@ -160,8 +161,8 @@ def main():
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed},
         "roofline": roof, "cpu_baseline": cpu,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "reps": int(lat.size), "nk": 1},
+        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,
     }
     ctx.close()

@@ -78,7 +78,7 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb)
     p.kb = UNMTR_KB;
     p.NBmax = hetrd_nbmax(n);
     p.CHmax = hetrd_chmax(n);
-    p.PN = (int)((n + 255) / 256);
+    p.PN = hetrd_pn(n);
     Layout L;
     const size_t z = sizeof(double2), r = sizeof(double), i4 = sizeof(int);
     const size_t nn = (size_t)n * n;

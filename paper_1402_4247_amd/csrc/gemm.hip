@@ -7,6 +7,8 @@
 // two terms s (two terms give the Hermitian rank-2k update V W^H + W V^H in
 // one pass).  A complex tile product is four real MFMA products on planar
 // (re, im) LDS tiles; op(A) = A^H is folded into the global->LDS copy.
+#include <stdlib.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -14,8 +16,6 @@ namespace kgev {
 
 namespace {
 
-constexpr int GB_M = 64;   // workgroup tile rows
-constexpr int GB_N = 64;   // workgroup tile cols
 constexpr int GB_K = 16;   // K step per LDS stage
 constexpr int G_THREADS = 256;
 
@@ -31,170 +31,183 @@ struct CGemmArgs {
     cx<R>* C;
     int64_t ldc, sC;
     int lower;
-    int tiles_m;
-    const int* dm;     // optional device-side sizes per batch entry (m, n, k) x batch; may be null
+    int tiles_m, tiles_n;
+    int64_t batch;
 };
 
-// global -> registers: this thread's 4 elements of the op(A) tile (GB_M x GB_K)
-template <typename R>
-__device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int ta, int64_t m, int64_t K,
-                              int64_t i0, int64_t k0, int tid, cx<R> (&ra)[4])
+// Work item of this workgroup.  Consecutive workgroups are dispatched round
+// robin over the 8 XCDs, so the 1-D id is remapped to give each XCD a
+// contiguous range of tiles (one L2 sees neighbouring tiles); inside a
+// problem tiles go in groups of 4 tile-rows so the tiles running together
+// share A row panels and B column panels.
+__device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_n, int64_t& b, int& tm, int& tn)
 {
-    if (ta == 0) {
-        const int r = tid & 63, kq = tid >> 6;
-        const int64_t gi = i0 + r;
+    const int64_t logical = (total % 8 == 0) ? (L % 8) * (total / 8) + L / 8 : L;
+    const int64_t T = (int64_t)tiles_m * tiles_n;
+    b = logical / T;
+    const int t = (int)(logical % T);
+    const int g = t / (4 * tiles_n);
+    const int rows_g = min(4, tiles_m - 4 * g);
+    const int local = t - 4 * g * tiles_n;
+    tm = 4 * g + local % rows_g;
+    tn = local / rows_g;
+}
+
+// global -> registers: this thread's elements of the op(A) tile (BM x GB_K)
+template <typename R, int BM>
+__device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int ta, int64_t m, int64_t K, int64_t i0,
+                              int64_t k0, int tid, cx<R> (&ra)[BM * GB_K / G_THREADS])
+{
+    constexpr int NE = BM * GB_K / G_THREADS;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t gk = k0 + kq + 4 * q;
-            ra[q] = (gi < m && gk < K) ? A[gi + gk * lda] : czero<cx<R>>();
-        }
-    } else {
-        const int kk = tid & 15, rq = tid >> 4;
-        const int64_t gk = k0 + kk;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t gi = i0 + rq + 16 * q;
-            ra[q] = (gi < m && gk < K) ? cconj(A[gk + gi * lda]) : czero<cx<R>>();
-        }
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + G_THREADS * q;
+        int r, kk;
+        if (ta == 0) { r = e % BM; kk = e / BM; } else { kk = e % GB_K; r = e / GB_K; }
+        const int64_t gi = i0 + r, gk = k0 + kk;
+        const bool ok = gi < m && gk < K;
+        const int64_t gic = ok ? gi : 0, gkc = ok ? gk : 0;
+        cx<R> v = (ta == 0) ? A[gic + gkc * lda] : cconj(A[gkc + gic * lda]);
+        ra[q] = ok ? v : czero<cx<R>>();
     }
 }
 
-template <typename R>
-__device__ inline void store_a(R (*sr)[GB_M + 1], R (*si)[GB_M + 1], int ta, int tid, const cx<R> (&ra)[4])
+template <typename R, int BM>
+__device__ inline void store_a(R (*sr)[BM + 1], R (*si)[BM + 1], int ta, int tid, const cx<R> (&ra)[BM * GB_K / G_THREADS])
 {
-    if (ta == 0) {
-        const int r = tid & 63, kq = tid >> 6;
+    constexpr int NE = BM * GB_K / G_THREADS;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { sr[kq + 4 * q][r] = ra[q].x; si[kq + 4 * q][r] = ra[q].y; }
-    } else {
-        const int kk = tid & 15, rq = tid >> 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { sr[kk][rq + 16 * q] = ra[q].x; si[kk][rq + 16 * q] = ra[q].y; }
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + G_THREADS * q;
+        int r, kk;
+        if (ta == 0) { r = e % BM; kk = e / BM; } else { kk = e % GB_K; r = e / GB_K; }
+        sr[kk][r] = ra[q].x;
+        si[kk][r] = ra[q].y;
     }
 }
 
-// op(B) tile (GB_K x GB_N)
-template <typename R>
-__device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int tb, int64_t n, int64_t K,
-                              int64_t j0, int64_t k0, int tid, cx<R> (&rb)[4])
+// op(B) tile (GB_K x BN)
+template <typename R, int BN>
+__device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int tb, int64_t n, int64_t K, int64_t j0,
+                              int64_t k0, int tid, cx<R> (&rb)[BN * GB_K / G_THREADS])
 {
-    if (tb == 0) {
-        const int kk = tid & 15, jq = tid >> 4;
-        const int64_t gk = k0 + kk;
+    constexpr int NE = BN * GB_K / G_THREADS;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t gj = j0 + jq + 16 * q;
-            rb[q] = (gj < n && gk < K) ? B[gk + gj * ldb] : czero<cx<R>>();
-        }
-    } else {
-        const int j = tid & 63, kq = tid >> 6;
-        const int64_t gj = j0 + j;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t gk = k0 + kq + 4 * q;
-            rb[q] = (gj < n && gk < K) ? cconj(B[gj + gk * ldb]) : czero<cx<R>>();
-        }
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + G_THREADS * q;
+        int c, kk;
+        if (tb == 0) { kk = e % GB_K; c = e / GB_K; } else { c = e % BN; kk = e / BN; }
+        const int64_t gj = j0 + c, gk = k0 + kk;
+        const bool ok = gj < n && gk < K;
+        const int64_t gjc = ok ? gj : 0, gkc = ok ? gk : 0;
+        cx<R> v = (tb == 0) ? B[gkc + gjc * ldb] : cconj(B[gjc + gkc * ldb]);
+        rb[q] = ok ? v : czero<cx<R>>();
     }
 }
 
-template <typename R>
-__device__ inline void store_b(R (*sr)[GB_N + 1], R (*si)[GB_N + 1], int tb, int tid, const cx<R> (&rb)[4])
+template <typename R, int BN>
+__device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tb, int tid, const cx<R> (&rb)[BN * GB_K / G_THREADS])
 {
-    if (tb == 0) {
-        const int kk = tid & 15, jq = tid >> 4;
+    constexpr int NE = BN * GB_K / G_THREADS;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { sr[kk][jq + 16 * q] = rb[q].x; si[kk][jq + 16 * q] = rb[q].y; }
-    } else {
-        const int j = tid & 63, kq = tid >> 6;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { sr[kq + 4 * q][j] = rb[q].x; si[kq + 4 * q][j] = rb[q].y; }
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + G_THREADS * q;
+        int c, kk;
+        if (tb == 0) { kk = e % GB_K; c = e / GB_K; } else { c = e % BN; kk = e / BN; }
+        sr[kk][c] = rb[q].x;
+        si[kk][c] = rb[q].y;
     }
 }
 
-template <typename R>
+// BM x BN workgroup tile, four waves in a 2 x 2 arrangement, each owning a
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  One LDS stage; the next K
+// step is fetched into registers while the current one is multiplied.
+template <typename R, int BM, int BN>
 __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
 {
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
-    __shared__ R sAr[2][GB_K][GB_M + 1], sAi[2][GB_K][GB_M + 1];
-    __shared__ R sBr[2][GB_K][GB_N + 1], sBi[2][GB_K][GB_N + 1];
+    constexpr int TM = BM / 32, TN = BN / 32;      // MFMA tiles per wave
+    __shared__ R sAr[GB_K][BM + 1], sAi[GB_K][BM + 1];
+    __shared__ R sBr[GB_K][BN + 1], sBi[GB_K][BN + 1];
 
-    const int64_t bz = blockIdx.z;
+    const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
+    int64_t bz;
+    int tm, tn;
+    tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, bz, tm, tn);
     const int64_t m = p.m, n = p.n, K = p.k;
-    const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
-    const int64_t i0 = (int64_t)tm * GB_M, j0 = (int64_t)tn * GB_N;
-    if (i0 >= m || j0 >= n) return;
-    if (p.lower && i0 + GB_M <= j0) return;   // tile entirely above the diagonal
+    const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
+    if (p.lower && i0 + BM <= j0) return;   // tile entirely above the diagonal
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     const int li = lane & 15, lk = lane >> 4;
 
-    acc_t accR[2][2], accI[2][2];
+    acc_t accR[TM][TN], accI[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
 
     const int nkt = (int)((K + GB_K - 1) / GB_K);
-    const int total = nkt * p.nseg;
-    cx<R> ra[4], rb[4];
-    int cur = 0;
-    if (total > 0) {
-        load_a<R>(p.A[0] + bz * p.sA[0], p.lda[0], p.ta[0], m, K, i0, 0, tid, ra);
-        load_b<R>(p.B[0] + bz * p.sB[0], p.ldb[0], p.tb[0], n, K, j0, 0, tid, rb);
-        store_a<R>(sAr[0], sAi[0], p.ta[0], tid, ra);
-        store_b<R>(sBr[0], sBi[0], p.tb[0], tid, rb);
+    const int total_k = nkt * p.nseg;
+    cx<R> ra[BM * GB_K / G_THREADS], rb[BN * GB_K / G_THREADS];
+    if (total_k > 0) {
+        load_a<R, BM>(p.A[0] + bz * p.sA[0], p.lda[0], p.ta[0], m, K, i0, 0, tid, ra);
+        load_b<R, BN>(p.B[0] + bz * p.sB[0], p.ldb[0], p.tb[0], n, K, j0, 0, tid, rb);
     }
-    __syncthreads();
-    for (int it = 0; it < total; ++it) {
+    for (int it = 0; it < total_k; ++it) {
+        const int sg = it / nkt;
+        store_a<R, BM>(sAr, sAi, p.ta[sg], tid, ra);
+        store_b<R, BN>(sBr, sBi, p.tb[sg], tid, rb);
+        __syncthreads();
         const int nx = it + 1;
-        const int sgn = nx / nkt, kt = nx % nkt;
-        if (nx < total) {
-            load_a<R>(p.A[sgn] + bz * p.sA[sgn], p.lda[sgn], p.ta[sgn], m, K, i0, (int64_t)kt * GB_K, tid, ra);
-            load_b<R>(p.B[sgn] + bz * p.sB[sgn], p.ldb[sgn], p.tb[sgn], n, K, j0, (int64_t)kt * GB_K, tid, rb);
+        if (nx < total_k) {
+            const int sn = nx / nkt, kt = nx % nkt;
+            load_a<R, BM>(p.A[sn] + bz * p.sA[sn], p.lda[sn], p.ta[sn], m, K, i0, (int64_t)kt * GB_K, tid, ra);
+            load_b<R, BN>(p.B[sn] + bz * p.sB[sn], p.ldb[sn], p.tb[sn], n, K, j0, (int64_t)kt * GB_K, tid, rb);
         }
 #pragma unroll
         for (int ks = 0; ks < GB_K; ks += 4) {
-            R ar[2], ai[2], br[2], bi[2];
+            R ar[TM], ai[TM], br[TN], bi[TN];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                ar[t] = sAr[cur][ks + lk][wm * 32 + t * 16 + li];
-                ai[t] = sAi[cur][ks + lk][wm * 32 + t * 16 + li];
-                br[t] = sBr[cur][ks + lk][wn * 32 + t * 16 + li];
-                bi[t] = sBi[cur][ks + lk][wn * 32 + t * 16 + li];
+            for (int t = 0; t < TM; ++t) {
+                ar[t] = sAr[ks + lk][wm * (BM / 2) + t * 16 + li];
+                ai[t] = sAi[ks + lk][wm * (BM / 2) + t * 16 + li];
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int t = 0; t < TN; ++t) {
+                br[t] = sBr[ks + lk][wn * (BN / 2) + t * 16 + li];
+                bi[t] = sBi[ks + lk][wn * (BN / 2) + t * 16 + li];
+            }
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+            for (int a = 0; a < TM; ++a) {
+                const R nai = -ai[a];
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
                     accR[a][b] = M::mma(ar[a], br[b], accR[a][b]);
-                    accR[a][b] = M::mma(-ai[a], bi[b], accR[a][b]);
+                    accR[a][b] = M::mma(nai, bi[b], accR[a][b]);
                     accI[a][b] = M::mma(ar[a], bi[b], accI[a][b]);
                     accI[a][b] = M::mma(ai[a], br[b], accI[a][b]);
                 }
-        }
-        if (nx < total) {
-            store_a<R>(sAr[cur ^ 1], sAi[cur ^ 1], p.ta[sgn], tid, ra);
-            store_b<R>(sBr[cur ^ 1], sBi[cur ^ 1], p.tb[sgn], tid, rb);
+            }
         }
         __syncthreads();
-        cur ^= 1;
     }
 
     cx<R>* C = p.C + bz * p.sC;
     const bool rb0 = (p.beta.x != 0 || p.beta.y != 0);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + wm * 32 + a * 16 + M::row(lk, r);
-                const int64_t j = j0 + wn * 32 + b * 16 + li;
+                const int64_t i = i0 + wm * (BM / 2) + a * 16 + M::row(lk, r);
+                const int64_t j = j0 + wn * (BN / 2) + b * 16 + li;
                 if (i < m && j < n && (!p.lower || i >= j)) {
                     cx<R> v = mk<R>(accR[a][b][r], accI[a][b][r]);
                     cx<R> out = cmul(p.alpha, v);
@@ -204,20 +217,37 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
             }
 }
 
+template <typename R, int BM, int BN>
+hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st)
+{
+    p.tiles_m = (int)((p.m + BM - 1) / BM);
+    p.tiles_n = (int)((p.n + BN - 1) / BN);
+    const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
+    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
 {
     if (a.m <= 0 || a.n <= 0 || batch <= 0) return hipSuccess;
     CGemmArgs<R> p = a;
-    p.tiles_m = (int)((a.m + GB_M - 1) / GB_M);
-    const int64_t tiles_n = (a.n + GB_N - 1) / GB_N;
-    dim3 grid((unsigned)(p.tiles_m * tiles_n), 1, (unsigned)batch);
+    p.batch = batch;
     double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch;
     if (a.lower) flops *= 0.5;
+    // large outputs take 128 x 128 tiles (half the operand traffic per flop);
+    // skinny ones keep 64 x 64 so that enough workgroups exist
+    // KGEV_GEMM_TILE=64|128 overrides the choice (tuning experiments)
+    static const int forced = [] {
+        const char* v = getenv("KGEV_GEMM_TILE");
+        return v ? atoi(v) : 0;
+    }();
+    const int64_t big_tiles = ((a.m + 127) / 128) * ((a.n + 63) / 64) * batch;
+    const bool big = forced ? forced == 128 : (a.m >= 128 && big_tiles >= 256);
     prof_before(PH_GEMM, st);
-    hipLaunchKernelGGL(cgemm_kernel<R>, grid, dim3(G_THREADS), 0, st, p);
+    hipError_t e = big ? launch_tiles<R, 128, 64>(p, st) : launch_tiles<R, 64, 64>(p, st);
     prof_after(PH_GEMM, st, 0.0, flops);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace

@@ -27,23 +27,10 @@ namespace kgev {
 namespace {
 
 constexpr int ZT = 64;          // ZHEMV tile edge
-constexpr int ZCH = 4;          // tiles per ZHEMV chunk (one workgroup)
-constexpr int RB = 256;         // rows per workgroup in the column kernels
+constexpr int ZCH = 4;          // tiles per ZHEMV chunk: one per wave of the workgroup
+constexpr int RB = 64;          // rows per workgroup in the column kernels
 
 __device__ __host__ inline int nchunks(int NB, int C) { return (NB - C + ZCH - 1) / ZCH; }
-
-// block-wide sum of one real value per thread (blockDim.x == 256)
-template <typename R>
-__device__ inline R block_sum256(R v, R* sh)
-{
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    R s = sh[0] + sh[1] + sh[2] + sh[3];
-    return s;
-}
 
 // Reflector from the partial norms: returns tau and the scale applied to x.
 template <typename R>
@@ -78,12 +65,52 @@ __device__ inline cx<R> vval(const HetrdWs<R>& ws, int64_t b, int i, int64_t r, 
     return cmul(ws.A[b * ws.sA + r + (int64_t)i * ws.lda], scale);
 }
 
+// One halving step of the transposing reduction: lanes with the MASK bit set
+// keep values HALF..2HALF-1 (moved down to 0..HALF-1), the others keep
+// 0..HALF-1; each adds its partner's copy of the values it keeps.
+template <int MASK, int HALF, int NV, typename R>
+__device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV], bool up)
+{
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+        const cx<R> send = up ? t[q] : t[q + HALF];
+        const cx<R> keep = up ? t[q + HALF] : t[q];
+        cx<R> rcv;
+        rcv.x = __shfl_xor(send.x, MASK, WAVE);
+        rcv.y = __shfl_xor(send.y, MASK, WAVE);
+        t[q] = cadd(keep, rcv);
+    }
+}
+
+template <int MASK, typename R>
+__device__ __attribute__((always_inline)) inline cx<R> xor_add(cx<R> r)
+{
+    r.x += __shfl_xor(r.x, MASK, WAVE);
+    r.y += __shfl_xor(r.y, MASK, WAVE);
+    return r;
+}
+
+// 8 complex values per lane -> lane l holds the sum over the wave of value
+// (l >> 3) & 7 (three halving steps over lane bits 5..3, then plain xor sums
+// over bits 2..0).
+template <typename R>
+__device__ __attribute__((always_inline)) inline cx<R> transpose_sum8(cx<R> (&t)[8], int lane)
+{
+    halve_step<32, 4, 8, R>(t, (lane & 32) != 0);
+    halve_step<16, 2, 8, R>(t, (lane & 16) != 0);
+    halve_step<8, 1, 8, R>(t, (lane & 8) != 0);
+    cx<R> r = t[0];
+    r = xor_add<4, R>(r);
+    r = xor_add<2, R>(r);
+    r = xor_add<1, R>(r);
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // First column of a panel: d_c and partial norms of rows c+2..n-1.
 template <typename R>
 __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 {
-    __shared__ R sh[4];
     const int64_t b = blockIdx.y;
     const int64_t r = (int64_t)c + (int64_t)blockIdx.x * RB + threadIdx.x;
     R acc = 0;
@@ -92,17 +119,21 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
         if (r == c) ws.d[b * ws.n + c] = a.x;
         if (r >= c + 2) acc = a.x * a.x + a.y * a.y;
     }
-    const R s = block_sum256(acc, sh);
-    if (threadIdx.x == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = s;
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------
-// Reflector + one chunk of the Hermitian product A22 v.
+// Reflector + one chunk of the Hermitian product A22 v.  A chunk is up to four
+// 64x64 tiles (R0..R0+3, C) of one block column of the lower triangle; wave w
+// owns tile R0 + w whole: the direct part y_R += A_RC v_C comes out complete
+// per row, the transposed part y_C += A_RC^H v_R per column after a
+// transposing wave reduction, and the four waves' column sums are added once.
 template <typename R>
 __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
 {
     __shared__ cx<R> svC[ZT];
-    __shared__ cx<R> sy[4][ZT];
+    __shared__ cx<R> sT[ZCH][ZT];
     const int64_t b = blockIdx.y;
     const int n = ws.n;
     const int o = i + 1;
@@ -120,75 +151,69 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
     if (C >= NB) return;
     const int ch = bid;
 
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const cx<R>* A = ws.A + b * ws.sA;
+    const int64_t lda = ws.lda;
+    const int Rb = C + ch * ZCH + w;
+    const bool have_tile = Rb < NB;
+    const int64_t gr = (int64_t)o + (int64_t)(have_tile ? Rb : C) * ZT + lane;
+    const bool row_ok = gr < n;
+    // Loads are unconditional from a clamped (in-bounds) address and the value
+    // is masked afterwards, so no branch guards them; the first group of the
+    // tile is requested before the reflector is derived, and each later group
+    // one step ahead of its use.
+    const cx<R>* Arow = A + (row_ok ? gr : (int64_t)n - 1);
+    const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
+    auto load_group = [&](int g, cx<R> (&a)[8]) {
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int64_t gc = gcb + g * 8 + cc;
+            a[cc] = Arow[(gc < n ? gc : (int64_t)n - 1) * lda];
+        }
+    };
+    cx<R> a[8], an[8];
+    if (have_tile) load_group(0, a);
+
     cx<R> tau, scale;
     R beta;
     reflector(ws, b, i, tau, scale, beta);
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid < ZT) svC[tid] = vval(ws, b, i, (int64_t)o + C * ZT + tid, scale);
+    if (tid < ZT) svC[tid] = vval(ws, b, i, gcb + tid, scale);
     __syncthreads();
 
-    const cx<R>* A = ws.A + b * ws.sA;
-    const int64_t lda = ws.lda;
-    cx<R> vC[16];
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) vC[cc] = svC[w * 16 + cc];
-
-    cx<R> yT = czero<cx<R>>();
-    const int R0 = C + ch * ZCH;
-    const int R1 = min(R0 + ZCH, NB);
-    const int64_t gcol0 = (int64_t)o + (int64_t)C * ZT + w * 16;
-    for (int Rb = R0; Rb < R1; ++Rb) {
-        const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
+    if (have_tile) {
         const cx<R> vR = vval(ws, b, i, gr, scale);
-        cx<R> a[16];
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            const int64_t gc = gcol0 + cc;
-            const bool ok = gr < n && gc < n && (Rb != C || gr >= gc);
-            a[cc] = ok ? A[gr + gc * lda] : czero<cx<R>>();
-        }
-        // direct part: y_R += A_RC v_C (diagonal entries real)
+        const bool diag_tile = (Rb == C);
         cx<R> yd = czero<cx<R>>();
-        cx<R> t[16];
+#pragma unroll 1
+        for (int g = 0; g < 8; ++g) {
+            if (g + 1 < 8) load_group(g + 1, an);
+            const int64_t gc0 = gcb + g * 8;
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            const bool diag = (gr == gcol0 + cc);
-            if (diag) a[cc].y = 0;
-            yd = cfma(a[cc], vC[cc], yd);
-            // transposed part: y_C += A_RC^H v_R (the diagonal counted once)
-            t[cc] = diag ? czero<cx<R>>() : cmulc(a[cc], vR);
-        }
-        // butterfly: lane l ends with column (l >> 2) of this wave's 16
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int mask = 32 >> s, half = 8 >> s;
-            const bool up = (lane & mask) != 0;
-#pragma unroll
-            for (int q = 0; q < half; ++q) {
-                const cx<R> send = up ? t[q] : t[q + half];
-                const cx<R> keep = up ? t[q + half] : t[q];
-                cx<R> rcv;
-                rcv.x = __shfl_xor(send.x, mask, WAVE);
-                rcv.y = __shfl_xor(send.y, mask, WAVE);
-                t[q] = cadd(keep, rcv);
+            for (int cc = 0; cc < 8; ++cc) {
+                const int64_t gc = gc0 + cc;
+                const bool ok = row_ok && gc < n && (!diag_tile || gr >= gc);
+                const bool diag = diag_tile && (gr == gc);
+                cx<R> x;
+                x.x = ok ? a[cc].x : (R)0;
+                x.y = (ok && !diag) ? a[cc].y : (R)0;
+                yd = cfma(x, svC[g * 8 + cc], yd);
+                // the diagonal entry is counted once (direct part only)
+                a[cc] = diag ? czero<cx<R>>() : cmulc(x, vR);
             }
+            const cx<R> r = transpose_sum8<R>(a, lane);
+            if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) a[cc] = an[cc];
         }
-        t[0].x += __shfl_xor(t[0].x, 2, WAVE);
-        t[0].y += __shfl_xor(t[0].y, 2, WAVE);
-        t[0].x += __shfl_xor(t[0].x, 1, WAVE);
-        t[0].y += __shfl_xor(t[0].y, 1, WAVE);
-        yT = cadd(yT, t[0]);
-        sy[w][lane] = yd;
-        __syncthreads();
-        if (tid < ZT) {
-            cx<R> s = cadd(cadd(sy[0][tid], sy[1][tid]), cadd(sy[2][tid], sy[3][tid]));
-            ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + tid] = s;
-        }
-        __syncthreads();
+        ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
+    } else {
+        sT[w][lane] = czero<cx<R>>();
     }
-    if ((lane & 3) == 0)
-        ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + w * 16 + (lane >> 2)] = yT;
+    __syncthreads();
+    if (tid < ZT) {
+        const cx<R> s = cadd(cadd(sT[0][tid], sT[1][tid]), cadd(sT[2][tid], sT[3][tid]));
+        ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
+    }
 
     if (ch == 0) {
         // this workgroup owns rows of block C: store v and the panel dots
@@ -218,104 +243,138 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
 }
 
 // ---------------------------------------------------------------------------
-// y = tau (sum of partials - V (W^H v) - W (V^H v)) for one 64-row block.
+// y = tau (sum of partials - V (W^H v) - W (V^H v)) for one 64-row block; the
+// four waves split every sum (wave w takes the terms with index = w mod 4).
 template <typename R>
-__global__ __launch_bounds__(64) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
+__global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
 {
+    __shared__ cx<R> s1[4][64], s2[4][64], sy[4][64];
     __shared__ cx<R> swv[64], svv[64];
     const int64_t b = blockIdx.y;
     const int n = ws.n, o = i + 1, m = n - o;
     const int NB = (m + ZT - 1) / ZT;
     const int Rb = blockIdx.x;
     const int j = i - p;
-    const int t = threadIdx.x;
-    if (t < j) {
-        cx<R> s1 = czero<cx<R>>(), s2 = czero<cx<R>>();
-        for (int C = 0; C < NB; ++C) {
-            s1 = cadd(s1, ws.pvw[b * ws.s_pdot + (int64_t)C * ws.nb + t]);
-            s2 = cadd(s2, ws.pvv[b * ws.s_pdot + (int64_t)C * ws.nb + t]);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // panel dots W^H v, V^H v (lane = panel column)
+    {
+        cx<R> a1 = czero<cx<R>>(), a2 = czero<cx<R>>();
+        if (lane < j) {
+            for (int C = w; C < NB; C += 4) {
+                a1 = cadd(a1, ws.pvw[b * ws.s_pdot + (int64_t)C * ws.nb + lane]);
+                a2 = cadd(a2, ws.pvv[b * ws.s_pdot + (int64_t)C * ws.nb + lane]);
+            }
         }
-        swv[t] = s1;
-        svv[t] = s2;
+        s1[w][lane] = a1;
+        s2[w][lane] = a2;
+    }
+    // partial sums of A22 v for these rows
+    {
+        cx<R> y = czero<cx<R>>();
+        const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + lane;
+        for (int C = w; C <= Rb; C += 4) y = cadd(y, yp[(int64_t)C * ZT]);
+        const int nc = nchunks(NB, Rb);
+        const cx<R>* yq = ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT + lane;
+        for (int ch = w; ch < nc; ch += 4) y = cadd(y, yq[(int64_t)ch * ZT]);
+        sy[w][lane] = y;
     }
     __syncthreads();
-    const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + t;
-    cx<R> y = czero<cx<R>>();
-    for (int C = 0; C <= Rb; ++C) y = cadd(y, ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + t]);
-    const int nc = nchunks(NB, Rb);
-    for (int ch = 0; ch < nc; ++ch) y = cadd(y, ws.ypartT[b * ws.s_ypartT + ((int64_t)Rb * ws.CHmax + ch) * ZT + t]);
-    cx<R> part = czero<cx<R>>();
-    if (gr < n) {
-        const cx<R>* V = ws.V + b * ws.sV;
-        const cx<R>* W = ws.W + b * ws.sW;
-        for (int jj = 0; jj < j; ++jj) {
-            y = csub(y, cmul(V[gr + (int64_t)(p + jj) * n], swv[jj]));
-            y = csub(y, cmul(W[gr + (int64_t)jj * n], svv[jj]));
-        }
-        y = cmul(ws.tau[b * n + i], y);
-        ws.ybuf[b * n + gr] = y;
-        part = cmulc(y, V[gr + (int64_t)i * n]);
+    if (tid < 64) {
+        swv[tid] = cadd(cadd(s1[0][tid], s1[1][tid]), cadd(s1[2][tid], s1[3][tid]));
+        svv[tid] = cadd(cadd(s2[0][tid], s2[1][tid]), cadd(s2[2][tid], s2[3][tid]));
     }
-    part.x = wave_sum(part.x);
-    part.y = wave_sum(part.y);
-    if (t == 0) ws.pyv[b * ws.NBmax + Rb] = part;
+    __syncthreads();
+    const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
+    const cx<R>* V = ws.V + b * ws.sV;
+    const cx<R>* W = ws.W + b * ws.sW;
+    cx<R> corr = czero<cx<R>>();
+    if (gr < n) {
+        for (int jj = w; jj < j; jj += 4) {
+            corr = cfma(V[gr + (int64_t)(p + jj) * n], swv[jj], corr);
+            corr = cfma(W[gr + (int64_t)jj * n], svv[jj], corr);
+        }
+    }
+    s1[w][lane] = corr;     // s1 is free again (read before the last barrier)
+    __syncthreads();
+    if (w == 0) {
+        cx<R> part = czero<cx<R>>();
+        if (gr < n) {
+            cx<R> y = cadd(cadd(sy[0][lane], sy[1][lane]), cadd(sy[2][lane], sy[3][lane]));
+            const cx<R> c = cadd(cadd(s1[0][lane], s1[1][lane]), cadd(s1[2][lane], s1[3][lane]));
+            y = cmul(ws.tau[b * n + i], csub(y, c));
+            ws.ybuf[b * n + gr] = y;
+            part = cmulc(y, V[gr + (int64_t)i * n]);
+        }
+        part.x = wave_sum(part.x);
+        part.y = wave_sum(part.y);
+        if (lane == 0) ws.pyv[b * ws.NBmax + Rb] = part;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // w = y + alpha2 v (alpha2 = -(tau/2) y^H v), stored as W(:, j); then, when
-// the panel continues, column i+1 is brought up to date and its partial norms
-// are reduced.
+// the panel continues, column i+1 is brought up to date (the four waves split
+// the panel columns) and its partial norm is reduced.
 template <typename R>
-__global__ __launch_bounds__(RB) void hetrd_finalize(HetrdWs<R> ws, int i, int p, int update_next)
+__global__ __launch_bounds__(256) void hetrd_finalize(HetrdWs<R> ws, int i, int p, int update_next)
 {
     __shared__ cx<R> sWr[64], sVr[64];
-    __shared__ R sh[4];
+    __shared__ cx<R> sp[4][64];
     const int64_t b = blockIdx.y;
     const int n = ws.n, o = i + 1, m = n - o;
     const int NB = (m + ZT - 1) / ZT;
     const int j = i - p;
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     cx<R> sum = czero<cx<R>>();
     for (int q = 0; q < NB; ++q) sum = cadd(sum, ws.pyv[b * ws.NBmax + q]);
     const cx<R> tau = ws.tau[b * n + i];
     const cx<R> a2 = cscale(cmul(tau, sum), (R)-0.5);
 
-    const int64_t gr = (int64_t)o + (int64_t)blockIdx.x * RB + t;
+    const int64_t gr = (int64_t)o + (int64_t)blockIdx.x * RB + lane;
     cx<R>* V = ws.V + b * ws.sV;
     cx<R>* W = ws.W + b * ws.sW;
     cx<R> wv = czero<cx<R>>();
     if (gr < n) {
         wv = cfma(a2, V[gr + (int64_t)i * n], ws.ybuf[b * n + gr]);
-        W[gr + (int64_t)j * n] = wv;
+        if (w == 0) W[gr + (int64_t)j * n] = wv;
     }
     if (!update_next) return;
     // row o of V and W for the update of column o
-    if (t <= j) {
-        sVr[t] = V[(int64_t)o + (int64_t)(p + t) * n];
-        sWr[t] = (t < j) ? W[(int64_t)o + (int64_t)t * n] : cadd(ws.ybuf[b * n + o], a2);
+    if (tid <= j) {
+        sVr[tid] = V[(int64_t)o + (int64_t)(p + tid) * n];
+        sWr[tid] = (tid < j) ? W[(int64_t)o + (int64_t)tid * n] : cadd(ws.ybuf[b * n + o], a2);
     }
     __syncthreads();
-    R acc = 0;
+    cx<R> acc = czero<cx<R>>();
+    if (gr < n) {
+        for (int jj = w; jj <= j; jj += 4) {
+            const cx<R> wr = (jj < j) ? W[gr + (int64_t)jj * n] : wv;
+            acc = cfma(V[gr + (int64_t)(p + jj) * n], cconj(sWr[jj]), acc);
+            acc = cfma(wr, cconj(sVr[jj]), acc);
+        }
+    }
+    sp[w][lane] = acc;
+    __syncthreads();
+    if (w != 0) return;
+    R nrm = 0;
     if (gr < n) {
         cx<R>* A = ws.A + b * ws.sA;
-        cx<R> a = A[gr + (int64_t)o * ws.lda];
-        for (int jj = 0; jj <= j; ++jj) {
-            const cx<R> wr = (jj < j) ? W[gr + (int64_t)jj * n] : wv;
-            a = csub(a, cmul(V[gr + (int64_t)(p + jj) * n], cconj(sWr[jj])));
-            a = csub(a, cmul(wr, cconj(sVr[jj])));
-        }
+        const cx<R> c = cadd(cadd(sp[0][lane], sp[1][lane]), cadd(sp[2][lane], sp[3][lane]));
+        cx<R> a = csub(A[gr + (int64_t)o * ws.lda], c);
         if (gr == o) {
             a.y = 0;
             ws.d[b * n + o] = a.x;
         }
         A[gr + (int64_t)o * ws.lda] = a;
-        if (gr >= o + 2) acc = a.x * a.x + a.y * a.y;
+        if (gr >= o + 2) nrm = a.x * a.x + a.y * a.y;
     }
-    const R s = block_sum256(acc, sh);
-    if (t == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = s;
+    nrm = wave_sum(nrm);
+    if (lane == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = nrm;
 }
 
 }  // namespace
+
+int hetrd_pn(int64_t n) { return (int)((n + RB - 1) / RB); }
 
 template <typename R>
 hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
@@ -334,10 +393,10 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             prof_before(PH_HEMV, st);
             hipLaunchKernelGGL(hetrd_zhemv<R>, dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i, p);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
-            hipLaunchKernelGGL(hetrd_reduce<R>, dim3((unsigned)NB, (unsigned)nk), dim3(64), 0, st, ws, i, p);
+            hipLaunchKernelGGL(hetrd_reduce<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             dim3 g4((unsigned)((n - o + RB - 1) / RB), (unsigned)nk);
-            hipLaunchKernelGGL(hetrd_finalize<R>, g4, dim3(RB), 0, st, ws, i, p, upd);
+            hipLaunchKernelGGL(hetrd_finalize<R>, g4, dim3(256), 0, st, ws, i, p, upd);
         }
         if (p + nb <= n - 1) {
             const int t0 = p + nb;

@@ -38,7 +38,7 @@ struct HetrdWs {
     cx<R>* V; int64_t sV;      // reflectors, n x n, ld n (zero outside the reflector rows)
     cx<R>* W; int64_t sW;      // panel W, n x nb, ld n
     R* d; R* e; cx<R>* tau;    // stride n per problem
-    R* pnorm; int64_t s_pnorm; // partial squared norms, ceil(n/256)
+    R* pnorm; int64_t s_pnorm; // partial squared norms, hetrd_pn(n)
     cx<R>* ypart; int64_t s_ypart;   // NBmax x NBmax x 64
     cx<R>* ypartT; int64_t s_ypartT; // NBmax x CHmax x 64
     cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;  // NBmax x nb
@@ -48,6 +48,7 @@ struct HetrdWs {
 
 inline int hetrd_nbmax(int64_t n) { return (int)((n - 1 + 63) / 64) > 0 ? (int)((n - 1 + 63) / 64) : 1; }
 inline int hetrd_chmax(int64_t n) { return (hetrd_nbmax(n) + 3) / 4; }
+int hetrd_pn(int64_t n);   // partial norms per column (one per 64-row block)
 
 template <typename R>
 hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk);

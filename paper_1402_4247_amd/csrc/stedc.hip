@@ -16,6 +16,8 @@
 //  * Q_new = Q V as a real product on FP64 MFMA, one launch per tree level.
 // The tree over [0, n) splits segment [floor(j n / 2^t), floor((j+1) n / 2^t))
 // at depth t; every segment of size >= 2 has two non-empty children.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -86,9 +88,10 @@ __global__ __launch_bounds__(256) void dc_eye(DcWs ws)
 
 // ---------------------------------------------------------------------------
 // Deflation for one merge (one workgroup per segment and problem).
-__global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb)
+__global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb, int lds_cap)
 {
     __shared__ double sh[8];
+    extern __shared__ double dyn[];   // lds_cap doubles sd, lds_cap doubles sz, lds_cap ints perm
     const int64_t b = blockIdx.y;
     const int64_t n = ws.n;
     const Seg g = seg_of(blockIdx.x, n, t);
@@ -99,9 +102,12 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb)
     double* Qr = ws.Q[rb] + b * ws.sQ;
     int* kc = ws.kcnt + b * n;
     int* ndc = ws.ndcnt + b * n;
-    int* perm = ws.perm + b * n + s;
-    double* sd = ws.sd + b * n + s;
-    double* sz = ws.sz + b * n + s;
+    // the serial deflation scan reads these at every step: keep them in LDS
+    // when the segment fits
+    const bool in_lds = (int)(g.e - g.s) <= lds_cap;
+    int* perm = in_lds ? reinterpret_cast<int*>(dyn + 2 * lds_cap) : ws.perm + b * n + s;
+    double* sd = in_lds ? dyn : ws.sd + b * n + s;
+    double* sz = in_lds ? dyn + lds_cap : ws.sz + b * n + s;
     int* ndx = ws.ndx + b * n + s;
     double* ndd = ws.ndd + b * n + s;
     double* ndz = ws.ndz + b * n + s;
@@ -215,18 +221,35 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb)
 
 // ---------------------------------------------------------------------------
 // Secular equation: one thread per root.
+// Four lanes cooperate on one root: lane `sub` sums the terms q = sub mod 4
+// and two xor steps add the four partial sums.  Floating-point addition is
+// commutative, so all four lanes end with bitwise equal sums and take the
+// same branches.
+constexpr int SEC_LANES = 4;
+
+__device__ inline double quad_sum(double v)
+{
+    v += __shfl_xor(v, 1, WAVE);
+    v += __shfl_xor(v, 2, WAVE);
+    return v;
+}
+
 __device__ inline void secular_eval(int K, const double* dl, const double* zl, double rho, int j, double dorg,
-                                    double tau, double& f, double& psi, double& dpsi, double& phi, double& dphi)
+                                    double tau, int sub, double& f, double& psi, double& dpsi, double& phi,
+                                    double& dphi)
 {
     psi = 0.0; dpsi = 0.0; phi = 0.0; dphi = 0.0;
-    for (int q = 0; q < K; ++q) {
+    for (int q = sub; q < K; q += SEC_LANES) {
         const double del = (dl[q] - dorg) - tau;
-        const double zz = zl[q] * zl[q];
-        const double tq = zz / del;
-        if (q <= j) { psi += tq; dpsi += tq / del; }
-        else { phi += tq; dphi += tq / del; }
+        const double r = 1.0 / del;
+        const double tq = zl[q] * zl[q] * r;
+        if (q <= j) { psi += tq; dpsi = fma(tq, r, dpsi); }
+        else { phi += tq; dphi = fma(tq, r, dphi); }
     }
-    psi *= rho; dpsi *= rho; phi *= rho; dphi *= rho;
+    psi = rho * quad_sum(psi);
+    dpsi = rho * quad_sum(dpsi);
+    phi = rho * quad_sum(phi);
+    dphi = rho * quad_sum(dphi);
     f = 1.0 + psi + phi;
 }
 
@@ -238,8 +261,9 @@ __global__ __launch_bounds__(64) void dc_secular(DcWs ws, int t)
     if (g.e - g.s < 2) return;
     const int64_t s = g.s;
     const int K = ws.kcnt[b * n + s];
-    const int j = blockIdx.x * 64 + threadIdx.x;
-    if (j >= K) return;
+    const int gt = blockIdx.x * 64 + threadIdx.x;
+    const int j = gt / SEC_LANES, sub = gt % SEC_LANES;
+    if (j >= K) return;          // the four lanes of a root leave together
     const double* dl = ws.ndd + b * n + s;
     const double* zl = ws.ndz + b * n + s;
     const double rho = ws.rho[b * n + s];
@@ -250,22 +274,25 @@ __global__ __launch_bounds__(64) void dc_secular(DcWs ws, int t)
     if (K == 1) {
         // one pole: lambda = d + rho z^2 exactly
         const double tau1 = rho * zl[0] * zl[0];
-        ws.orgi[b * n + s] = 0;
-        ws.tauv[b * n + s] = tau1;
-        ws.lam[b * n + s] = dl[0] + tau1;
+        if (sub == 0) {
+            ws.orgi[b * n + s] = 0;
+            ws.tauv[b * n + s] = tau1;
+            ws.lam[b * n + s] = dl[0] + tau1;
+        }
         return;
     }
     if (j < K - 1) {
         const double half = 0.5 * (dl[j + 1] - dl[j]);
-        secular_eval(K, dl, zl, rho, j, dl[j], half, f, psi, dpsi, phi, dphi);
+        secular_eval(K, dl, zl, rho, j, dl[j], half, sub, f, psi, dpsi, phi, dphi);
         if (f >= 0.0) { org = j; lo = 0.0; hi = half; }
         else { org = j + 1; lo = -half; hi = 0.0; }
     } else {
         double zz = 0.0;
-        for (int q = 0; q < K; ++q) zz += zl[q] * zl[q];
+        for (int q = sub; q < K; q += SEC_LANES) zz = fma(zl[q], zl[q], zz);
+        zz = quad_sum(zz);
         org = j; lo = 0.0; hi = rho * zz;
         for (int g2 = 0; g2 < 8; ++g2) {
-            secular_eval(K, dl, zl, rho, j, dl[org], hi, f, psi, dpsi, phi, dphi);
+            secular_eval(K, dl, zl, rho, j, dl[org], hi, sub, f, psi, dpsi, phi, dphi);
             if (f >= 0.0) break;
             lo = hi; hi *= 2.0;
         }
@@ -276,7 +303,7 @@ __global__ __launch_bounds__(64) void dc_secular(DcWs ws, int t)
     double tau = 0.5 * (lo + hi);
     bool conv = false;
     for (int it = 0; it < 400; ++it) {
-        secular_eval(K, dl, zl, rho, j, dorg, tau, f, psi, dpsi, phi, dphi);
+        secular_eval(K, dl, zl, rho, j, dorg, tau, sub, f, psi, dpsi, phi, dphi);
         if (f == 0.0) { conv = true; break; }
         if (f < 0.0) lo = tau; else hi = tau;
         if (fabs(f) <= 8.0 * EPS * (1.0 + fabs(psi) + fabs(phi)) * (double)(K > 8 ? 8 : K)) { conv = true; break; }
@@ -318,6 +345,7 @@ __global__ __launch_bounds__(64) void dc_secular(DcWs ws, int t)
         if (cand == tau) cand = 0.5 * (lo + hi);
         tau = cand;
     }
+    if (sub != 0) return;
     ws.orgi[b * n + s + j] = org;
     ws.tauv[b * n + s + j] = tau;
     ws.lam[b * n + s + j] = dorg + tau;
@@ -557,8 +585,11 @@ hipError_t stedc(hipStream_t st, const DcWs& ws0, double* w, double* Z, double* 
         const unsigned segs = 1u << t;
         const int64_t nsmax = ((n + segs - 1) / segs) + 1;
         const unsigned gx = (unsigned)((nsmax + 63) / 64);
-        hipLaunchKernelGGL(dc_deflate, dim3(segs, (unsigned)nk), dim3(256), 0, st, ws, t, rb);
-        hipLaunchKernelGGL(dc_secular, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
+        const int cap = (int)std::min<int64_t>(nsmax, 3200);
+        const size_t dyn_bytes = (size_t)cap * (2 * sizeof(double) + sizeof(int));
+        hipLaunchKernelGGL(dc_deflate, dim3(segs, (unsigned)nk), dim3(256), dyn_bytes, st, ws, t, rb, cap);
+        const unsigned gxs = (unsigned)((nsmax * SEC_LANES + 63) / 64);
+        hipLaunchKernelGGL(dc_secular, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_zhat, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_vectors, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_order, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t, wb);
