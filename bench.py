@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
     ap.add_argument("--latency-reps", type=int, default=20, help="0 skips the latency measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-steps", type=int, default=2,
+                    help="timed steps of the FP32+refine form (0 skips it)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -140,6 +142,37 @@ def main():
     r_orth = float(np.abs(C0.conj().T @ S0 @ C0 - np.eye(n)).max())
     check = {"k": 0, "r_res": r_res, "r_orth": r_orth, "status_all_ok": bool(np.all(status == 0))}
 
+    # the mixed-precision form on the same batch, same accuracy gate
+    mixed = None
+    if args.mixed_steps > 0:
+        om = K.make_opts(precision=K.PREC_FP32_REFINE)
+        wm = torch.zeros_like(dw)
+        Cm = torch.zeros_like(dC)
+        stm = torch.zeros_like(dst)
+
+        def mstep():
+            st = K.solve_k_device(ctx, dH, dS, n, n, nk, wm, Cm, n, d_status=stm, opts=om)
+            if st != 0:
+                raise RuntimeError(f"mixed solve returned {st}")
+
+        log(f"[bench] FP32+refine: warmup 1, timing {args.mixed_steps} steps")
+        mstep()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            mstep()
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - a
+        wmk = wm[0].cpu().numpy()
+        Cmk = Cm[0].cpu().numpy().T
+        mixed = {"value": nk * args.mixed_steps / tm, "unit": "solves/s",
+                 "ms_per_step": 1e3 * tm / args.mixed_steps, "steps": args.mixed_steps,
+                 "refine_sweeps": 3, "status_all_ok": bool(np.all(stm.cpu().numpy() == 0)),
+                 "r_res": float(np.linalg.norm(H0 @ Cmk - S0 @ Cmk * wmk) / np.linalg.norm(H0)),
+                 "r_orth": float(np.abs(Cmk.conj().T @ S0 @ Cmk - np.eye(n)).max()),
+                 "eig_diff_vs_fp64_rel": float(np.abs(wmk - w0).max() / np.abs(w0).max())}
+        log(f"[bench] FP32+refine {mixed['value']:.2f} solves/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -151,6 +184,8 @@ def main():
         cpu = {"value": 1.0 / t_or, "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": f"1 of the {nk} k-points (k index 0) at n={n}, all eigenpairs; {t_or:.1f} s"}
         check["eig_err_vs_oracle_rel"] = float(np.abs(w0 - wor).max() / np.abs(wor).max())
+        if mixed is not None:
+            mixed["eig_err_vs_oracle_rel"] = float(np.abs(wmk - wor).max() / np.abs(wor).max())
         check["oracle_status"] = int(st0)
 
     out = {
@@ -160,7 +195,7 @@ def main():
         "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,

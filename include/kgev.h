@@ -73,7 +73,7 @@ typedef struct {
     int32_t precision;    /* KGEV_PREC_FP64 (default) or KGEV_PREC_FP32_REFINE */
     int32_t want_vectors; /* 1 (default): eigenvalues and eigenvectors; 0: eigenvalues only */
     int32_t panel_nb;     /* Householder panel width; 0 = tuned default */
-    int32_t refine_iters; /* mixed precision: maximum refinement sweeps; 0 = default (3) */
+    int32_t refine_iters; /* mixed precision: refinement sweeps, 1..10; 0 = default (3) */
     double s_tol;         /* S(k) is rejected when s_min <= s_tol * s_max; 0 = default 1e-12 */
     int32_t reserved[8];  /* must be zero */
 } kgev_opts;
@@ -198,6 +198,58 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
                               int64_t k, kgev_z alpha, const kgev_z* dA, int64_t lda, int64_t sA,
                               const kgev_z* dB, int64_t ldb, int64_t sB, kgev_z beta, kgev_z* dC,
                               int64_t ldc, int64_t sC, int64_t batch, int32_t lower, void* stream);
+
+/*
+ * Serving: a request loop that admits eigensolves of mixed order n and k-point
+ * count as execution slots and device memory free up (continuous batching at
+ * request granularity).  Each admitted request runs the batched per-k solve
+ * (Band_DFT_Col Parts 2-4, Section III) on its own HIP stream, so requests
+ * admitted while others run overlap with them on the device.  Admission is in
+ * arrival order; a request is admitted when a slot is free and its workspace
+ * footprint (kgev_workspace_bytes + status words) fits the remaining budget.
+ * Inputs and outputs stay device-resident: the caller keeps dH, dS, dw and dC
+ * (as in kgev_solve_k_device) alive and untouched until kgev_server_wait
+ * returns for the request.  The server owns only workspaces, streams and its
+ * worker thread; all entry points are thread-safe.
+ */
+typedef struct kgev_server kgev_server;
+
+typedef struct {
+    int64_t n, nk, ld;          /* order, k-points, leading dimension of dH/dS (>= n) */
+    const kgev_z* dH;           /* device, nk matrices, lower triangles read */
+    const kgev_z* dS;
+    double* dw;                 /* device, nk*n eigenvalues */
+    kgev_z* dC;                 /* device, nk matrices (ld ldc), or NULL for eigenvalues only */
+    int64_t ldc;
+    int32_t precision;          /* KGEV_PREC_FP64 or KGEV_PREC_FP32_REFINE */
+    int32_t reserved;           /* must be zero */
+} kgev_request;
+
+typedef struct {
+    kgev_status status;         /* first nonzero per-k status, KGEV_ENOMEM if it can never fit, or 0 */
+    int64_t bad_k;              /* k index of that status, or -1 */
+    double t_submit, t_admit, t_done;   /* seconds on a monotonic clock */
+    size_t footprint;           /* device bytes the request held while running */
+} kgev_result;
+
+/*
+ * Start a server on HIP device `device` with `max_slots` (1..64) concurrent
+ * requests and a device-memory budget in bytes (0 = free memory minus a 4 GiB
+ * reserve).  Returns -1 (out NULL), -2 (device), -4 (slots) or KGEV_EDEVICE.
+ */
+kgev_status kgev_server_create(kgev_server** out, int device, size_t hbm_budget, int32_t max_slots);
+
+/* Queue a request; *ticket identifies it.  -2: invalid request fields. */
+kgev_status kgev_server_submit(kgev_server* srv, const kgev_request* req, uint64_t* ticket);
+
+/* *done = 1 once the request has completed (results valid), else 0. */
+kgev_status kgev_server_poll(kgev_server* srv, uint64_t ticket, int32_t* done);
+
+/* Block until the request completes, fill *result and forget the ticket. */
+kgev_status kgev_server_wait(kgev_server* srv, uint64_t ticket, kgev_result* result);
+
+/* Drain queued and running requests, then stop the worker and free the server. */
+void kgev_server_destroy(kgev_server* srv);
 
 /*
  * Kernel timing for measurement.  Between kgev_profile_begin and

@@ -66,12 +66,18 @@ struct SolvePlan {
         dc_lam, dc_zhat;
     size_t dc_kcnt, dc_ndcnt, dc_nrot, dc_perm, dc_ndx, dc_dfx, dc_rota, dc_rotb, dc_orgi, dc_cmap;
     size_t status;
+    // mixed precision: complex64 tridiagonalisation / back-transformation
+    // buffers and the FP64 refinement scratch (size 0 in the FP64 form)
+    bool mixed;
+    size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_pvv, f_pyv, f_ybuf, f_uwork, f_d, f_e, f_pnorm;
+    size_t r_Ynext, r_G, r_S, r_F, r_pS, r_pR, r_delta;
     size_t total;
 };
 
-SolvePlan make_plan(int64_t n, int64_t nk, int nb)
+SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
 {
     SolvePlan p{};
+    p.mixed = mixed;
     p.n = n;
     p.nk = nk;
     p.nb = nb;
@@ -111,8 +117,56 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb)
                     &p.dc_orgi, &p.dc_cmap};
     for (size_t* q : iv) *q = L.add(i4 * n * nk);
     p.status = L.add(i4 * nk);
+    const size_t m = mixed ? 1 : 0;
+    const size_t c = sizeof(float2), f = sizeof(float);
+    p.f_A = L.add(m * c * nn * nk);
+    p.f_V = L.add(m * c * nn * nk);
+    p.f_Y = L.add(m * c * nn * nk);
+    p.f_W = L.add(m * c * n * nb * nk);
+    p.f_tau = L.add(m * c * n * nk);
+    p.f_ypart = L.add(m * c * (size_t)p.NBmax * p.NBmax * 64 * nk);
+    p.f_ypartT = L.add(m * c * (size_t)p.NBmax * p.CHmax * 64 * nk);
+    p.f_pvw = L.add(m * c * (size_t)p.NBmax * nb * nk);
+    p.f_pvv = L.add(m * c * (size_t)p.NBmax * nb * nk);
+    p.f_pyv = L.add(m * c * (size_t)p.NBmax * nk);
+    p.f_ybuf = L.add(m * c * n * nk);
+    p.f_uwork = L.add(m * c * (size_t)unmtr_work_elems(n, p.kb) * nk);
+    p.f_d = L.add(m * f * n * nk);
+    p.f_e = L.add(m * f * n * nk);
+    p.f_pnorm = L.add(m * f * p.PN * nk);
+    p.r_Ynext = L.add(m * z * nn * nk);
+    p.r_G = L.add(m * z * nn * nk);
+    p.r_S = L.add(m * z * nn * nk);
+    p.r_F = L.add(m * z * nn * nk);
+    p.r_pS = L.add(m * r * n * nk);
+    p.r_pR = L.add(m * r * n * nk);
+    p.r_delta = L.add(m * r * nk);
     p.total = L.total;
     return p;
+}
+
+HetrdWs<float> hetrd_ws32(const SolvePlan& p, void* w)
+{
+    HetrdWs<float> h{};
+    h.n = (int)p.n;
+    h.nb = p.nb;
+    h.NBmax = p.NBmax;
+    h.CHmax = p.CHmax;
+    h.A = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_A); h.lda = p.n; h.sA = p.n * p.n;
+    h.V = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_V); h.sV = p.n * p.n;
+    h.W = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_W); h.sW = p.n * p.nb;
+    h.d = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_d);
+    h.e = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_e);
+    h.tau = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_tau);
+    h.pnorm = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_pnorm); h.s_pnorm = p.PN;
+    h.ypart = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
+    h.ypartT = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
+    h.pvw = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvw);
+    h.pvv = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvv);
+    h.s_pdot = (int64_t)p.NBmax * p.nb;
+    h.pyv = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pyv);
+    h.ybuf = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ybuf);
+    return h;
 }
 
 template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
@@ -177,7 +231,8 @@ kgev_opts resolve_opts(const kgev_opts* o)
 
 bool opts_valid(const kgev_opts& o)
 {
-    if (o.precision != KGEV_PREC_FP64) return false;   // the mixed form is not built yet
+    if (o.precision != KGEV_PREC_FP64 && o.precision != KGEV_PREC_FP32_REFINE) return false;
+    if (o.refine_iters < 1 || o.refine_iters > 10) return false;
     if (o.want_vectors != 0 && o.want_vectors != 1) return false;
     if (o.panel_nb < 1 || o.panel_nb > 64) return false;
     if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
@@ -255,6 +310,48 @@ kgev_status eigen_hh(const SolvePlan& p, void* w, hipStream_t st, double* wout, 
     return KGEV_OK;
 }
 
+// Part 4 in the mixed-precision form: A (FP64, lower, in Aw) is rounded to
+// complex64, tridiagonalised and back-transformed on FP32 MFMA; the
+// tridiagonal eigensolve runs in FP64 on the promoted d, e; the eigenpairs are
+// then refined against the FP64 A (refine.hip).  Y (ld n) receives the
+// refined vectors, wout the refined eigenvalues.
+kgev_status eigen_hh_mixed(const SolvePlan& p, void* w, hipStream_t st, double* wout, double2* Y, int* status,
+                           int iters)
+{
+    const int64_t n = p.n, nk = p.nk, nn = n * n;
+    double2* Aw = at<double2>(w, p.Aw);
+    HetrdWs<float> h = hetrd_ws32(p, w);
+    KCHECK(copy_lower_check<float>(st, n, Aw, n, nn, h.A, n, nn, nullptr, nk));
+    KCHECK(fill_zero(st, h.V, sizeof(float2) * (size_t)nn * nk));
+    KCHECK(hetrd<float>(st, h, nk));
+    double* d = at<double>(w, p.d);
+    double* e = at<double>(w, p.e);
+    KCHECK(float_to_double(st, h.d, d, n * nk));
+    KCHECK(float_to_double(st, h.e, e, n * nk));
+    double* Zr = at<double>(w, p.Zr);
+    KCHECK(stedc(st, dc_ws(p, w, d, e, status), wout, Zr, at<double>(w, p.Qs), nk));
+    float2* Y32 = at<float2>(w, p.f_Y);
+    KCHECK(real_to_complex<float>(st, n, Zr, nn, Y32, n, nn, nk));
+    KCHECK(unmtr<float>(st, n, h.V, nn, h.tau, n, Y32, n, nn, at<float2>(w, p.f_uwork), p.kb, nk));
+    KCHECK(c64_to_c128(st, Y32, Y, nn * nk));
+    double2* Af = at<double2>(w, p.Vs);
+    KCHECK(hermitian_full(st, n, Aw, n, nn, Af, n, nn, nk));
+    RefineWs rw{};
+    rw.n = n;
+    rw.Af = Af;
+    rw.Y = Y;
+    rw.Ynext = at<double2>(w, p.r_Ynext);
+    rw.G = at<double2>(w, p.r_G);
+    rw.P = Aw;                       // A itself is no longer needed
+    rw.S = at<double2>(w, p.r_S);
+    rw.F = at<double2>(w, p.r_F);
+    rw.pS = at<double>(w, p.r_pS);
+    rw.pR = at<double>(w, p.r_pR);
+    rw.delta = at<double>(w, p.r_delta);
+    KCHECK(refine(st, rw, nk, iters, wout));
+    return KGEV_OK;
+}
+
 kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStream_t st, const double2* H,
                          const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status)
 {
@@ -279,7 +376,11 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, Vs, n, nn, X, n, nn, zero, G, n, nn, nk, false));
     KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, Aw, n, nn, nk, true));
     // Part 4: A = Y diag(lambda) Y^H, C = X Y
-    r = eigen_hh(p, w, st, dw, o.want_vectors ? G : nullptr, status);
+    if (o.precision == KGEV_PREC_FP32_REFINE) {
+        r = eigen_hh_mixed(p, w, st, dw, G, status, o.refine_iters);
+    } else {
+        r = eigen_hh(p, w, st, dw, o.want_vectors ? G : nullptr, status);
+    }
     if (r != KGEV_OK) return r;
     if (o.want_vectors) {
         KCHECK(normalize_cols(st, n, G, n, nn, nullptr, 0, 0.0, nullptr, nk));
@@ -354,7 +455,7 @@ size_t kgev_workspace_bytes(int64_t n, int64_t nk, const kgev_opts* opts)
 {
     if (n < 1 || nk < 1) return 0;
     kgev_opts o = resolve_opts(opts);
-    return make_plan(n, nk, o.panel_nb).total;
+    return make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE).total;
 }
 
 kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
@@ -369,10 +470,10 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     if (nk < 1) return -6;
     if (!dw) return -7;
     kgev_opts o = resolve_opts(opts);
-    if (!opts_valid(o)) return (opts && opts->precision != KGEV_PREC_FP64) ? KGEV_EUNSUPPORTED : -10;
+    if (!opts_valid(o)) return -10;
     if (o.want_vectors && (!dC || ldc < n)) return -8;
     DevGuard g(ctx->device);
-    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    SolvePlan p = make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
     void* w = dwork;
     if (w) {
         if (work_bytes < p.total) return -9;
@@ -396,7 +497,7 @@ kgev_status kgev_solve_k(kgev_ctx* ctx, const kgev_z* H, const kgev_z* S, int64_
     if (nk < 1) return -5;
     if (!w) return -6;
     kgev_opts o = resolve_opts(opts);
-    if (!opts_valid(o)) return (opts && opts->precision != KGEV_PREC_FP64) ? KGEV_EUNSUPPORTED : -8;
+    if (!opts_valid(o)) return -8;
     if (o.want_vectors && !C) return -7;
     DevGuard g(ctx->device);
     const size_t mb = sizeof(double2) * (size_t)n * n * nk;

@@ -107,6 +107,21 @@ hipError_t status_init(hipStream_t st, int* status, int64_t nk);
 constexpr int ST_NOTPD = 1, ST_NOCONV = 2, ST_NONFINITE = 4;
 hipError_t status_finish(hipStream_t st, const int* bits, int32_t* codes, int64_t nk);
 
+// mixed precision (refine.hip)
+hipError_t float_to_double(hipStream_t st, const float* src, double* dst, int64_t count);
+hipError_t c64_to_c128(hipStream_t st, const float2* src, double2* dst, int64_t count);
+struct RefineWs {
+    int64_t n;
+    const double2* Af;        // full Hermitian FP64 matrix, n x n per problem
+    double2* Y;               // in: eigenvector estimate; out: refined
+    double2* Ynext;           // n x n scratch
+    double2* G; double2* P; double2* S; double2* F;   // n x n scratch each
+    double* pS; double* pR;   // n per problem
+    double* delta;            // one per problem
+};
+// `iters` refinement sweeps; lam_out (n per problem) gets the refined eigenvalues
+hipError_t refine(hipStream_t st, const RefineWs& ws, int64_t nk, int iters, double* lam_out);
+
 // back-transformation U <- Q U (unmtr.hip); work: see unmtr_work_elems
 template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,

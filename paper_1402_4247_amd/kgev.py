@@ -32,6 +32,18 @@ class Z(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nk", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("dH", ctypes.c_void_p), ("dS", ctypes.c_void_p), ("dw", ctypes.c_void_p),
+                ("dC", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("bad_k", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
                 ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
@@ -41,7 +53,8 @@ class Opts(ctypes.Structure):
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
-           "kgev_profile_begin", "kgev_profile_end"]
+           "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
+           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 
 
@@ -86,6 +99,15 @@ def _load():
     lib.kgev_profile_end.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D),
                                      ctypes.POINTER(D)]
     lib.kgev_profile_end.restype = I32
+    lib.kgev_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
+    lib.kgev_server_create.restype = I32
+    lib.kgev_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.kgev_server_submit.restype = I32
+    lib.kgev_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32)]
+    lib.kgev_server_poll.restype = I32
+    lib.kgev_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    lib.kgev_server_wait.restype = I32
+    lib.kgev_server_destroy.argtypes = [P]
     return lib
 
 
@@ -221,3 +243,46 @@ def profile_end(ctx):
     _check("kgev_profile_end", lib.kgev_profile_end(ctx.handle, ctypes.byref(n), ctypes.byref(ms),
                                                     ctypes.byref(by), ctypes.byref(fl)))
     return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+
+
+class Server:
+    """kgev_server: continuous-batching request loop on one device."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, max_slots: int = 4):
+        h = ctypes.c_void_p()
+        _check("kgev_server_create", lib.kgev_server_create(ctypes.byref(h), int(device), int(hbm_budget),
+                                                            int(max_slots)))
+        self.handle = h
+
+    def submit(self, dH, dS, n, nk, dw, dC=None, ld=None, ldc=None, precision=PREC_FP64) -> int:
+        rq = Request(n, nk, ld or n, _ptr(dH), _ptr(dS), _ptr(dw), _ptr(dC), ldc or n, precision, 0)
+        t = ctypes.c_uint64()
+        _check("kgev_server_submit", lib.kgev_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket) -> bool:
+        d = ctypes.c_int32()
+        _check("kgev_server_poll", lib.kgev_server_poll(self.handle, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket) -> Result:
+        r = Result()
+        _check("kgev_server_wait", lib.kgev_server_wait(self.handle, ticket, ctypes.byref(r)))
+        return r
+
+    def close(self):
+        if self.handle:
+            lib.kgev_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

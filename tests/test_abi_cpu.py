@@ -23,6 +23,7 @@ def test_every_declared_symbol_is_exported():
     for name in names:
         assert hasattr(K.lib, name), name
     assert set(names) == set(K.EXPORTS)
+    assert "kgev_server_submit" in names
 
 
 def test_library_is_the_in_tree_build():

@@ -1,0 +1,62 @@
+"""Mixed-precision form (complex64 tridiagonalisation and back-transformation
+of Part 4 on FP32 MFMA, FP64 tridiagonal solve, FP64 Ogita-Aishima
+refinement) against the FP64 oracle, to the same bar as the FP64 path:
+eigenvalues within 1e-10 relative, residual and S-orthonormality <= 1e-12."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_helpers import DEV, K, check, dev, host, residuals, vec_mismatch
+from paper_1402_4247_amd import inputs as G
+
+pytestmark = pytest.mark.gpu
+
+
+def solve(Hs, Ss, iters=0, vectors=True, precision=1):
+    kg = K()
+    nk, n = Hs.shape[0], Hs.shape[1]
+    dH, dS = dev(Hs), dev(Ss)
+    dw = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+    dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV) if vectors else None
+    st = torch.full((nk,), -7, dtype=torch.int32, device=DEV)
+    with kg.Context(0) as ctx:
+        o = kg.make_opts(precision=precision, want_vectors=vectors, refine_iters=iters)
+        check(kg.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=st, opts=o), "solve mixed")
+        torch.cuda.synchronize()
+    return dw.cpu().numpy(), (host(dC) if vectors else None), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("gen,n,nk", [("config1", 128, 2), ("lcao", 300, 2), ("config1", 65, 3), ("lcao", 1, 1)])
+def test_mixed_matches_oracle(gen, n, nk):
+    if gen == "config1":
+        Hs, Ss = G.config1_batch(n, nk, 1001)
+    else:
+        Hs, Ss = G.config2(n, nk, 2002)
+    w, C, st = solve(Hs, Ss)
+    assert np.all(st == 0)
+    for q in range(nk):
+        s0, w0, C0 = O.solve_k(Hs[q], Ss[q])
+        assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+        r_res, r_orth = residuals(Hs[q], Ss[q], w[q], C[q])
+        assert r_res <= 1e-12 and r_orth <= 1e-12, (r_res, r_orth)
+        assert vec_mismatch(C0, C[q], Ss[q], w0) <= 1e-10
+
+
+def test_refinement_sweeps_reduce_the_residual():
+    Hs, Ss = G.config2(200, 1, 2002)
+    res = []
+    for it in (1, 2, 3):
+        w, C, st = solve(Hs, Ss, iters=it)
+        res.append(residuals(Hs[0], Ss[0], w[0], C[0])[0])
+    # one sweep from FP32 vectors is not enough, three reach FP64 accuracy
+    assert res[0] > res[2] and res[2] <= 1e-12
+
+
+def test_mixed_eigenvalues_only():
+    Hs, Ss = G.config1_batch(96, 2, 77)
+    w, _, st = solve(Hs, Ss, vectors=False)
+    assert np.all(st == 0)
+    for q in range(2):
+        _, w0, _ = O.solve_k(Hs[q], Ss[q], vectors=False)
+        assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()

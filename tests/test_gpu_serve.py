@@ -1,0 +1,91 @@
+"""Serving loop on the GPU: requests of mixed n and k-count admitted while
+others run give exactly the result the same request gives alone (bitwise),
+match the oracle, respect the memory budget, and fail independently."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_helpers import DEV, K, check, dev, host, residuals
+from paper_1402_4247_amd import inputs as G
+
+pytestmark = pytest.mark.gpu
+
+
+def make_req(n, nk, seed, bad=False):
+    Hs, Ss = G.config1_batch(n, nk, seed)
+    if bad:
+        Ss[nk - 1] = np.eye(n)
+        Ss[nk - 1][0, 0] = -1.0
+    return dict(n=n, nk=nk, Hs=Hs, Ss=Ss, dH=dev(Hs), dS=dev(Ss),
+                dw=torch.zeros((nk, n), dtype=torch.float64, device=DEV),
+                dC=torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV))
+
+
+def solve_alone(r):
+    kg = K()
+    n, nk = r["n"], r["nk"]
+    w = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+    C = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV)
+    with kg.Context(0) as ctx:
+        check(kg.solve_k_device(ctx, r["dH"], r["dS"], n, n, nk, w, C, n), "alone")
+        torch.cuda.synchronize()
+    return w.cpu().numpy(), C.cpu().numpy()
+
+
+def test_mix_equals_alone_and_oracle():
+    kg = K()
+    torch.cuda.synchronize()
+    sizes = [(64, 1), (200, 3), (100, 2), (150, 1), (64, 3), (257, 2), (90, 1), (130, 2)]
+    reqs = [make_req(n, nk, 7000 + q) for q, (n, nk) in enumerate(sizes)]
+    with kg.Server(0, 0, 4) as srv:
+        tickets = [srv.submit(r["dH"], r["dS"], r["n"], r["nk"], r["dw"], r["dC"]) for r in reqs]
+        results = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    # some requests ran while others were still running (overlap on the device)
+    overlaps = sum(1 for a in results for b in results
+                   if a is not b and a.t_admit < b.t_done and b.t_admit < a.t_done)
+    assert overlaps > 0
+    for r, res in zip(reqs, results):
+        assert res.status == 0 and res.t_submit <= res.t_admit <= res.t_done
+        w_alone, C_alone = solve_alone(r)
+        assert np.array_equal(r["dw"].cpu().numpy(), w_alone)
+        assert np.array_equal(r["dC"].cpu().numpy(), C_alone)
+    for r in reqs[:3]:
+        w = r["dw"].cpu().numpy()
+        C = host(r["dC"])
+        for q in range(r["nk"]):
+            _, w0, _ = O.solve_k(r["Hs"][q], r["Ss"][q])
+            assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+            rr, ro = residuals(r["Hs"][q], r["Ss"][q], w[q], C[q])
+            assert rr <= 1e-12 and ro <= 1e-12
+
+
+def test_budget_limits_and_rejection():
+    kg = K()
+    small = make_req(80, 1, 11)
+    big = make_req(160, 2, 12)
+    fp_small = kg.workspace_bytes(80, 1)
+    budget = fp_small + 4096          # one small request at a time; the big one never fits
+    with kg.Server(0, budget, 4) as srv:
+        t1 = srv.submit(small["dH"], small["dS"], 80, 1, small["dw"], small["dC"])
+        t2 = srv.submit(big["dH"], big["dS"], 160, 2, big["dw"], big["dC"])
+        t3 = srv.submit(small["dH"], small["dS"], 80, 1, small["dw"], small["dC"])
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+    assert r1.status == 0 and r3.status == 0
+    assert r2.status == K().ENOMEM
+    assert r3.t_admit >= r1.t_done - 1e-3      # serialised by the budget
+
+
+def test_failures_are_isolated():
+    kg = K()
+    good = make_req(70, 2, 21)
+    bad = make_req(70, 3, 22, bad=True)
+    with kg.Server(0, 0, 2) as srv:
+        tg = srv.submit(good["dH"], good["dS"], 70, 2, good["dw"], good["dC"])
+        tb = srv.submit(bad["dH"], bad["dS"], 70, 3, bad["dw"], bad["dC"])
+        rg, rb = srv.wait(tg), srv.wait(tb)
+    assert rg.status == 0
+    assert rb.status == 1 and rb.bad_k == 2
+    w_alone, C_alone = solve_alone(good)
+    assert np.array_equal(good["dw"].cpu().numpy(), w_alone)
