@@ -37,6 +37,59 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def serve_stream(args, K, G, torch, dev):
+    """Serving workload: requests with n log-uniform in [256, nmax] (drawn from
+    a pool of 6 log-spaced orders) and 1..16 k-points, arriving as a Poisson
+    process at 80% of the closed-loop saturation rate of the same mix.  Each
+    pool order has one seeded LCAO pencil, replicated over the request's
+    k-points (the cost of a k-point does not depend on which k it is)."""
+    import math
+    rng = np.random.default_rng(5005)
+    sizes = sorted({int(round(math.exp(x))) for x in np.linspace(math.log(256), math.log(args.serve_nmax), 6)})
+    log(f"[serve] pool orders {sizes}")
+    pool = {}
+    for n in sizes:
+        Hs, Ss = G.lcao_batch(n, G.mp_grid(4)[:1], 5005 + n)
+        dH = torch.from_numpy(G.colmajor(Hs)).to(dev).expand(16, n, n).contiguous()
+        dS = torch.from_numpy(G.colmajor(Ss)).to(dev).expand(16, n, n).contiguous()
+        pool[n] = (dH, dS)
+    reqs = [(sizes[int(rng.integers(0, len(sizes)))], int(rng.integers(1, 17))) for _ in range(args.serve)]
+
+    def run(arrivals):
+        with K.Server(0, 0, args.serve_slots) as srv:
+            t0 = time.perf_counter()
+            tickets, outs = [], []
+            for (n, nk), ta in zip(reqs, arrivals):
+                delay = t0 + ta - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                w = torch.empty((nk, n), dtype=torch.float64, device=dev)
+                C = torch.empty((nk, n, n), dtype=torch.complex128, device=dev)
+                dH, dS = pool[n]
+                tickets.append(srv.submit(dH, dS, n, nk, w, C))
+                outs.append((w, C))
+            res = [srv.wait(t) for t in tickets]
+            t1 = time.perf_counter()
+        return res, t1 - t0
+
+    # closed loop (everything queued at t = 0) gives the saturation rate
+    log(f"[serve] closed loop, {len(reqs)} requests")
+    res, span = run([0.0] * len(reqs))
+    sat = len(reqs) / span
+    lam = 0.8 * sat
+    gaps = rng.exponential(1.0 / lam, len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    log(f"[serve] open loop at {lam:.2f} requests/s")
+    res, span = run(list(arrivals))
+    lat = np.array([1e3 * (r.t_done - r.t_submit) for r in res])
+    solves = sum(nk for _, nk in reqs)
+    return {"requests": len(reqs), "slots": args.serve_slots, "orders": sizes,
+            "saturation_requests_per_s": sat, "arrival_rate_requests_per_s": lam,
+            "solves_per_s": solves / span, "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "status_all_ok": all(r.status == 0 for r in res)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +103,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed steps of the FP32+refine form (0 skips it)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run the serving stream with this many requests (0 skips it)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-nmax", type=int, default=6000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -173,6 +230,8 @@ def main():
                  "eig_diff_vs_fp64_rel": float(np.abs(wmk - w0).max() / np.abs(w0).max())}
         log(f"[bench] FP32+refine {mixed['value']:.2f} solves/s")
 
+    serving = serve_stream(args, K, G, torch, dev) if args.serve > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -195,7 +254,7 @@ def main():
         "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed},
-        "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed,
+        "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,

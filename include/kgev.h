@@ -75,7 +75,10 @@ typedef struct {
     int32_t panel_nb;     /* Householder panel width; 0 = tuned default */
     int32_t refine_iters; /* mixed precision: refinement sweeps, 1..10; 0 = default (3) */
     double s_tol;         /* S(k) is rejected when s_min <= s_tol * s_max; 0 = default 1e-12 */
-    int32_t reserved[8];  /* must be zero */
+    int32_t use_graph;    /* 1: capture the whole batched solve as one HIP graph on the first call with
+                             these sizes, buffers and stream, and replay it afterwards (the stream must
+                             not be the null stream); 0 (default): launch kernel by kernel */
+    int32_t reserved[7];  /* must be zero */
 } kgev_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -91,6 +94,18 @@ const char* kgev_status_str(kgev_status st);
  * Returns KGEV_OK, -1 (ctx NULL), -2 (no such device) or KGEV_EDEVICE.
  */
 kgev_status kgev_create(kgev_ctx** ctx, int device);
+
+/*
+ * Panel-width autotuner.  Times the blocked Householder reduction of
+ * synthetic Hermitian matrices of order n for the candidate panel widths
+ * 16, 24, 32, 48 and 64 and records the fastest in the context for (n,
+ * precision); later calls through this context with opts->panel_nb == 0 use
+ * it.  The choice depends only on n and precision, never on the batch, so a
+ * k-point's result does not depend on which other k-points share its call.
+ * *best_nb (optional) receives the choice.  Synchronous; uses the context's
+ * internal workspace.
+ */
+kgev_status kgev_autotune(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* best_nb);
 
 /* Release a context and everything it owns.  NULL is allowed. */
 void kgev_destroy(kgev_ctx* ctx);

@@ -13,6 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -27,9 +29,20 @@ Profiler* prof_start(int phase, size_t reserve);
 bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double* flops);
 }  // namespace kgev
 
+// Everything that identifies a captured solve: sizes, options, buffers, stream.
+struct GraphKey {
+    int64_t n, ld, nk, ldc;
+    int32_t precision, want_vectors, panel_nb, refine_iters;
+    double s_tol;
+    const void *H, *S, *w, *C, *work, *status, *stream;
+    bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
 struct kgev_ctx {
     int device;
     kgev::Profiler* prof;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // most recent last
+    std::map<std::pair<int64_t, int>, int> tuned_nb;            // (n, precision) -> panel width
     void* work;
     size_t work_bytes;
     // host-pointer API staging buffers
@@ -92,12 +105,15 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.Vs = L.add(z * nn * nk);
     p.X = L.add(z * nn * nk);
     p.G = L.add(z * nn * nk);
-    p.Wp = L.add(z * n * nb * nk);
+    // nb-dependent arrays are sized for the widest panel (64), so a tuned
+    // width never outgrows a workspace sized by kgev_workspace_bytes
+    const size_t nbA = 64;
+    p.Wp = L.add(z * n * nbA * nk);
     p.tau = L.add(z * n * nk);
     p.ypart = L.add(z * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.ypartT = L.add(z * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.pvw = L.add(z * (size_t)p.NBmax * nb * nk);
-    p.pvv = L.add(z * (size_t)p.NBmax * nb * nk);
+    p.pvw = L.add(z * (size_t)p.NBmax * nbA * nk);
+    p.pvv = L.add(z * (size_t)p.NBmax * nbA * nk);
     p.pyv = L.add(z * (size_t)p.NBmax * nk);
     p.ybuf = L.add(z * n * nk);
     p.uwork = L.add(z * (size_t)unmtr_work_elems(n, p.kb) * nk);
@@ -122,12 +138,12 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.f_A = L.add(m * c * nn * nk);
     p.f_V = L.add(m * c * nn * nk);
     p.f_Y = L.add(m * c * nn * nk);
-    p.f_W = L.add(m * c * n * nb * nk);
+    p.f_W = L.add(m * c * n * nbA * nk);
     p.f_tau = L.add(m * c * n * nk);
     p.f_ypart = L.add(m * c * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.f_ypartT = L.add(m * c * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.f_pvw = L.add(m * c * (size_t)p.NBmax * nb * nk);
-    p.f_pvv = L.add(m * c * (size_t)p.NBmax * nb * nk);
+    p.f_pvw = L.add(m * c * (size_t)p.NBmax * nbA * nk);
+    p.f_pvv = L.add(m * c * (size_t)p.NBmax * nbA * nk);
     p.f_pyv = L.add(m * c * (size_t)p.NBmax * nk);
     p.f_ybuf = L.add(m * c * n * nk);
     p.f_uwork = L.add(m * c * (size_t)unmtr_work_elems(n, p.kb) * nk);
@@ -236,7 +252,8 @@ bool opts_valid(const kgev_opts& o)
     if (o.want_vectors != 0 && o.want_vectors != 1) return false;
     if (o.panel_nb < 1 || o.panel_nb > 64) return false;
     if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
-    for (int q = 0; q < 8; ++q)
+    if (o.use_graph != 0 && o.use_graph != 1) return false;
+    for (int q = 0; q < 7; ++q)
         if (o.reserved[q] != 0) return false;
     return true;
 }
@@ -445,6 +462,7 @@ void kgev_destroy(kgev_ctx* ctx)
     DevGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
+    for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.second);
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -469,6 +487,15 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     if (ld < n) return -5;
     if (nk < 1) return -6;
     if (!dw) return -7;
+    if ((!opts || opts->panel_nb == 0)) {
+        kgev_opts t = resolve_opts(opts);
+        auto it = ctx->tuned_nb.find({n, t.precision});
+        if (it != ctx->tuned_nb.end()) {
+            kgev_opts o2 = t;
+            o2.panel_nb = it->second;
+            return kgev_solve_k_device(ctx, dH, dS, n, ld, nk, dw, dC, ldc, dwork, work_bytes, d_status, &o2, stream);
+        }
+    }
     kgev_opts o = resolve_opts(opts);
     if (!opts_valid(o)) return -10;
     if (o.want_vectors && (!dC || ldc < n)) return -8;
@@ -482,8 +509,46 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
         if (r != KGEV_OK) return r;
         w = ctx->work;
     }
-    return solve_device(p, o, w, (hipStream_t)stream, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC,
-                        ldc, d_status);
+    hipStream_t st = (hipStream_t)stream;
+    if (!o.use_graph || st == nullptr)
+        return solve_device(p, o, w, st, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC, ldc, d_status);
+
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.n = n; key.ld = ld; key.nk = nk; key.ldc = o.want_vectors ? ldc : 0;
+    key.precision = o.precision; key.want_vectors = o.want_vectors; key.panel_nb = o.panel_nb;
+    key.refine_iters = o.refine_iters; key.s_tol = o.s_tol;
+    key.H = dH; key.S = dS; key.w = dw; key.C = o.want_vectors ? dC : nullptr; key.work = w; key.status = d_status;
+    key.stream = stream;
+    for (size_t q = 0; q < ctx->graphs.size(); ++q)
+        if (ctx->graphs[q].first == key) {
+            auto e = ctx->graphs[q];
+            ctx->graphs.erase(ctx->graphs.begin() + q);
+            ctx->graphs.push_back(e);
+            KCHECK(hipGraphLaunch(e.second, st));
+            return KGEV_OK;
+        }
+    KCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    kgev_status r = solve_device(p, o, w, st, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC, ldc,
+                                 d_status);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (r != KGEV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (ec != hipSuccess) return KGEV_EDEVICE;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return KGEV_EDEVICE;
+    if (ctx->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().second);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, exec});
+    KCHECK(hipGraphLaunch(exec, st));
+    return KGEV_OK;
 }
 
 kgev_status kgev_solve_k(kgev_ctx* ctx, const kgev_z* H, const kgev_z* S, int64_t n, int64_t nk, double* w,
@@ -676,6 +741,62 @@ kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms,
     const bool ok = prof_stop(ctx->prof, launches, total_ms, alg_bytes, alg_flops);
     ctx->prof = nullptr;
     return ok ? KGEV_OK : KGEV_EDEVICE;
+}
+
+kgev_status kgev_autotune(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* best_nb)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (precision != KGEV_PREC_FP64 && precision != KGEV_PREC_FP32_REFINE) return -3;
+    DevGuard g(ctx->device);
+    const int64_t nk = 4;
+    const bool mixed = precision == KGEV_PREC_FP32_REFINE;
+    SolvePlan base = make_plan(n, nk, 64, mixed);
+    kgev_status r = ensure_work(ctx, base.total);
+    if (r != KGEV_OK) return r;
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    KCHECK(hipEventCreate(&e0));
+    KCHECK(hipEventCreate(&e1));
+    const int cands[] = {16, 24, 32, 48, 64};
+    int best = DEFAULT_NB;
+    float best_ms = 1e30f;
+    const int64_t nn = n * n;
+    for (int rep = 0; rep < 2; ++rep) {          // first pass warms up, second pass decides
+        for (int nb : cands) {
+            SolvePlan p = make_plan(n, nk, nb, mixed);
+            void* w = ctx->work;
+            if (mixed) {
+                HetrdWs<float> h = hetrd_ws32(p, w);
+                KCHECK(fill_test_matrix<float>(st, n, h.A, nk, 17));
+                KCHECK(fill_zero(st, h.V, sizeof(float2) * (size_t)nn * nk));
+                KCHECK(hipEventRecord(e0, st));
+                KCHECK(hetrd<float>(st, h, nk));
+            } else {
+                double2* Aw = at<double2>(w, p.Aw);
+                double2* Vs = at<double2>(w, p.Vs);
+                KCHECK(fill_test_matrix<double>(st, n, Aw, nk, 17));
+                KCHECK(fill_zero(st, Vs, sizeof(double2) * (size_t)nn * nk));
+                KCHECK(hipEventRecord(e0, st));
+                KCHECK(hetrd<double>(st, hetrd_ws(p, w, Aw, n, nn, Vs, at<double>(w, p.d), at<double>(w, p.e),
+                                                  at<double2>(w, p.tau)),
+                                     nk));
+            }
+            KCHECK(hipEventRecord(e1, st));
+            KCHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            KCHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 1 && ms < best_ms) {
+                best_ms = ms;
+                best = nb;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned_nb[{n, precision}] = best;
+    if (best_nb) *best_nb = best;
+    return KGEV_OK;
 }
 
 }  // extern "C"

@@ -33,6 +33,7 @@ struct CGemmArgs {
     int lower;
     int tiles_m, tiles_n;
     int64_t batch;
+    int remap;
 };
 
 // Work item of this workgroup.  Consecutive workgroups are dispatched round
@@ -40,9 +41,10 @@ struct CGemmArgs {
 // contiguous range of tiles (one L2 sees neighbouring tiles); inside a
 // problem tiles go in groups of 4 tile-rows so the tiles running together
 // share A row panels and B column panels.
-__device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_n, int64_t& b, int& tm, int& tn)
+__device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_n, int remap, int64_t& b, int& tm,
+                               int& tn)
 {
-    const int64_t logical = (total % 8 == 0) ? (L % 8) * (total / 8) + L / 8 : L;
+    const int64_t logical = (remap && total % 8 == 0) ? (L % 8) * (total / 8) + L / 8 : L;
     const int64_t T = (int64_t)tiles_m * tiles_n;
     b = logical / T;
     const int t = (int)(logical % T);
@@ -120,21 +122,22 @@ __device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tb, int tid
 }
 
 // BM x BN workgroup tile, four waves in a 2 x 2 arrangement, each owning a
-// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  One LDS stage; the next K
-// step is fetched into registers while the current one is multiplied.
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  Two LDS stages: while stage
+// s is multiplied, the next K step is fetched into registers and then stored
+// into stage s^1, so one barrier per K step suffices.
 template <typename R, int BM, int BN>
 __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
 {
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
     constexpr int TM = BM / 32, TN = BN / 32;      // MFMA tiles per wave
-    __shared__ R sAr[GB_K][BM + 1], sAi[GB_K][BM + 1];
-    __shared__ R sBr[GB_K][BN + 1], sBi[GB_K][BN + 1];
+    __shared__ R sAr[2][GB_K][BM + 1], sAi[2][GB_K][BM + 1];
+    __shared__ R sBr[2][GB_K][BN + 1], sBi[2][GB_K][BN + 1];
 
     const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
     int64_t bz;
     int tm, tn;
-    tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, bz, tm, tn);
+    tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, p.remap, bz, tm, tn);
     const int64_t m = p.m, n = p.n, K = p.k;
     const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
     if (p.lower && i0 + BM <= j0) return;   // tile entirely above the diagonal
@@ -155,18 +158,18 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
     const int nkt = (int)((K + GB_K - 1) / GB_K);
     const int total_k = nkt * p.nseg;
     cx<R> ra[BM * GB_K / G_THREADS], rb[BN * GB_K / G_THREADS];
+    int cur = 0;
     if (total_k > 0) {
         load_a<R, BM>(p.A[0] + bz * p.sA[0], p.lda[0], p.ta[0], m, K, i0, 0, tid, ra);
         load_b<R, BN>(p.B[0] + bz * p.sB[0], p.ldb[0], p.tb[0], n, K, j0, 0, tid, rb);
+        store_a<R, BM>(sAr[0], sAi[0], p.ta[0], tid, ra);
+        store_b<R, BN>(sBr[0], sBi[0], p.tb[0], tid, rb);
     }
+    __syncthreads();
     for (int it = 0; it < total_k; ++it) {
-        const int sg = it / nkt;
-        store_a<R, BM>(sAr, sAi, p.ta[sg], tid, ra);
-        store_b<R, BN>(sBr, sBi, p.tb[sg], tid, rb);
-        __syncthreads();
         const int nx = it + 1;
+        const int sn = nx / nkt, kt = nx % nkt;
         if (nx < total_k) {
-            const int sn = nx / nkt, kt = nx % nkt;
             load_a<R, BM>(p.A[sn] + bz * p.sA[sn], p.lda[sn], p.ta[sn], m, K, i0, (int64_t)kt * GB_K, tid, ra);
             load_b<R, BN>(p.B[sn] + bz * p.sB[sn], p.ldb[sn], p.tb[sn], n, K, j0, (int64_t)kt * GB_K, tid, rb);
         }
@@ -175,13 +178,13 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
             R ar[TM], ai[TM], br[TN], bi[TN];
 #pragma unroll
             for (int t = 0; t < TM; ++t) {
-                ar[t] = sAr[ks + lk][wm * (BM / 2) + t * 16 + li];
-                ai[t] = sAi[ks + lk][wm * (BM / 2) + t * 16 + li];
+                ar[t] = sAr[cur][ks + lk][wm * (BM / 2) + t * 16 + li];
+                ai[t] = sAi[cur][ks + lk][wm * (BM / 2) + t * 16 + li];
             }
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                br[t] = sBr[ks + lk][wn * (BN / 2) + t * 16 + li];
-                bi[t] = sBi[ks + lk][wn * (BN / 2) + t * 16 + li];
+                br[t] = sBr[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
+                bi[t] = sBi[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
             }
 #pragma unroll
             for (int a = 0; a < TM; ++a) {
@@ -195,7 +198,12 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
                 }
             }
         }
+        if (nx < total_k) {
+            store_a<R, BM>(sAr[cur ^ 1], sAi[cur ^ 1], p.ta[sn], tid, ra);
+            store_b<R, BN>(sBr[cur ^ 1], sBi[cur ^ 1], p.tb[sn], tid, rb);
+        }
         __syncthreads();
+        cur ^= 1;
     }
 
     cx<R>* C = p.C + bz * p.sC;
@@ -237,13 +245,22 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
     if (a.lower) flops *= 0.5;
     // large outputs take 128 x 128 tiles (half the operand traffic per flop);
     // skinny ones keep 64 x 64 so that enough workgroups exist
-    // KGEV_GEMM_TILE=64|128 overrides the choice (tuning experiments)
+    // KGEV_GEMM_TILE=64|128 and KGEV_GEMM_REMAP=0|1 override the defaults
+    // (tuning experiments)
     static const int forced = [] {
         const char* v = getenv("KGEV_GEMM_TILE");
         return v ? atoi(v) : 0;
     }();
+    static const int remap = [] {
+        const char* v = getenv("KGEV_GEMM_REMAP");
+        return v ? atoi(v) : 1;
+    }();
+    p.remap = remap;
     const int64_t big_tiles = ((a.m + 127) / 128) * ((a.n + 63) / 64) * batch;
-    const bool big = forced ? forced == 128 : (a.m >= 128 && big_tiles >= 256);
+    // measured on gfx950: the 64 x 64 tile with two LDS stages beats 128 x 64
+    // at every shape of this path, so the wider tile is only used on request
+    (void)big_tiles;
+    const bool big = forced == 128;
     prof_before(PH_GEMM, st);
     hipError_t e = big ? launch_tiles<R, 128, 64>(p, st) : launch_tiles<R, 64, 64>(p, st);
     prof_after(PH_GEMM, st, 0.0, flops);

@@ -101,6 +101,9 @@ template <typename R>
 hipError_t larft(hipStream_t st, int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau, int c0,
                  cx<R>* T, int64_t sT, int64_t nk);
 hipError_t status_init(hipStream_t st, int* status, int64_t nk);
+// nk synthetic matrices (entries in [-1, 1), real diagonal) for timing runs
+template <typename R>
+hipError_t fill_test_matrix(hipStream_t st, int64_t n, cx<R>* A, int64_t nk, uint64_t seed);
 // Per-k status words are bit sets while the solve runs; status_finish turns
 // them into the ABI codes, the input condition taking precedence:
 // non-finite input > S not positive definite > no convergence.

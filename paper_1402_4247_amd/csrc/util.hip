@@ -154,6 +154,39 @@ hipError_t fill_zero(hipStream_t st, void* p, size_t bytes)
 hipError_t status_init(hipStream_t st, int* status, int64_t nk) { return fill_zero(st, status, sizeof(int) * nk); }
 
 namespace {
+// deterministic pseudo-random value in [-1, 1) from an index (splitmix64 finaliser)
+__device__ inline double hash_unit(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fill_test(int64_t n, cx<R>* A, uint64_t seed)
+{
+    const int64_t b = blockIdx.z, j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = ((seed * 1315423911ull + (uint64_t)b) * 2654435761ull + (uint64_t)j) * 40503ull + (uint64_t)i;
+    const double re = hash_unit(2 * key), im = (i == j) ? 0.0 : hash_unit(2 * key + 1);
+    A[b * n * n + i + j * n] = mk<R>((R)re, (R)im);
+}
+}  // namespace
+
+template <typename R>
+hipError_t fill_test_matrix(hipStream_t st, int64_t n, cx<R>* A, int64_t nk, uint64_t seed)
+{
+    dim3 g((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nk);
+    hipLaunchKernelGGL(k_fill_test<R>, g, dim3(256), 0, st, n, A, seed);
+    return hipGetLastError();
+}
+template hipError_t fill_test_matrix<double>(hipStream_t, int64_t, double2*, int64_t, uint64_t);
+template hipError_t fill_test_matrix<float>(hipStream_t, int64_t, float2*, int64_t, uint64_t);
+
+namespace {
 __global__ __launch_bounds__(256) void k_status_finish(const int* bits, int32_t* codes, int64_t nk)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;

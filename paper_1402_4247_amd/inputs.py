@@ -144,10 +144,13 @@ class LcaoSystem:
         # bound rho(|W|) <= max_i (|W| x)_i / x_i, so lambda(S(k)) is inside
         # [0.5, 1.5] for every k.
         x = np.ones(n)
-        for _ in range(60):
-            y = magW @ x
-            x = y / y.max()
-        self.c = 0.5 / float(((magW @ x) / x).max())
+        if magW.max() > 0.0:
+            for _ in range(60):
+                y = magW @ x
+                x = y / y.max()
+            self.c = 0.5 / float(((magW @ x) / x).max())
+        else:
+            self.c = 0.5                      # a single orbital: W = 0
 
     def hs(self, kfrac):
         """(H(k), S(k)) for k = kfrac * 2 pi / a."""

@@ -47,14 +47,14 @@ class Result(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
                 ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("s_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+                ("s_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
-           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy"]
+           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 
 
@@ -108,6 +108,8 @@ def _load():
     lib.kgev_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     lib.kgev_server_wait.restype = I32
     lib.kgev_server_destroy.argtypes = [P]
+    lib.kgev_autotune.argtypes = [P, I64, I32, ctypes.POINTER(I32)]
+    lib.kgev_autotune.restype = I32
     return lib
 
 
@@ -123,9 +125,11 @@ def _check(fn, st):
         raise KgevError(fn, st)
 
 
-def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0) -> Opts:
+def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0,
+              use_graph=False) -> Opts:
     o = Opts()
     lib.kgev_opts_default(ctypes.byref(o))
+    o.use_graph = 1 if use_graph else 0
     o.precision = precision
     o.want_vectors = 1 if want_vectors else 0
     o.panel_nb = panel_nb
@@ -286,3 +290,9 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+def autotune(ctx, n, precision=PREC_FP64) -> int:
+    best = ctypes.c_int32()
+    _check("kgev_autotune", lib.kgev_autotune(ctx.handle, int(n), int(precision), ctypes.byref(best)))
+    return best.value
