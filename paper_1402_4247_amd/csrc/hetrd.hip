@@ -2,19 +2,21 @@
 // (lower storage): Section III, Procedures 1-6 of Eigen_HH, arXiv:1402.4247,
 // reorganised in panels of nb columns.
 //
-// Per column i of a panel starting at p (j = i - p):
-//   colstart / finalize : the column is brought up to date with the panel's
-//       reflectors, A(i:n, i) -= V(i:n, 0:j) conj(W(i, 0:j))^T
-//                                + W(i:n, 0:j) conj(V(i, 0:j))^T,
-//       and its squared norm below the sub-diagonal is reduced in partials;
-//   zhemv    : every workgroup derives the reflector (Procedure 2, stable
-//       sign, real beta) from the partial norms, then forms one chunk of the
-//       Hermitian product A22 v (Procedure 4) from the lower triangle only,
-//       leaving deterministic partial sums;
-//   reduce   : sums the partials per row and applies the panel corrections
-//       y = tau (A22 v - V (W^H v) - W (V^H v));
+// Per column i of a panel starting at p (j = i - p, o = i + 1):
+//   zhemv    : one chunk of the Hermitian product z = A22 u (Procedure 4) from
+//       the lower triangle only, with u the column below the sub-diagonal as
+//       it stands (u_o = 0, u_r = A(r, i)): it needs nothing derived in this
+//       step, so the workgroups only stream their tiles;
+//   reduce   : derives the reflector (Procedure 2, stable sign, real beta)
+//       from the partial norms, v = (1, scale * A(o+1:n, i)), stores v, and
+//       forms y = tau (A22(:, o) + scale z - V (W^H v) - W (V^H v)), where
+//       A22 v = A22(:, o) + scale A22 u by linearity;
 //   finalize : w = y - (tau/2)(y^H v) v (Procedure 5), stored as column j of
-//       W, then the next column of the panel is updated (above).
+//       W; then the next column of the panel is brought up to date,
+//       A(o:n, o) -= V(o:n, 0:j) conj(W(o, 0:j))^T + W(o:n, 0:j) conj(V(o, 0:j))^T,
+//       and its squared norm below the sub-diagonal and its products with
+//       the panel columns (the pieces of W^H v and V^H v for the next
+//       reflector) are reduced in per-block partials.
 // After the panel the trailing matrix takes the rank-2nb update
 // A22 -= V W^H + W V^H (Procedure 6, on MFMA).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
@@ -55,14 +57,6 @@ __device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& 
     const R dr = alpha.x - beta, di = alpha.y;
     const R den = dr * dr + di * di;
     scale = mk<R>(dr / den, -di / den);
-}
-
-template <typename R>
-__device__ inline cx<R> vval(const HetrdWs<R>& ws, int64_t b, int i, int64_t r, cx<R> scale)
-{
-    if (r == i + 1) return mk<R>(1, 0);
-    if (r >= ws.n) return czero<cx<R>>();
-    return cmul(ws.A[b * ws.sA + r + (int64_t)i * ws.lda], scale);
 }
 
 // One halving step of the transposing reduction: lanes with the MASK bit set
@@ -124,13 +118,13 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 }
 
 // ---------------------------------------------------------------------------
-// Reflector + one chunk of the Hermitian product A22 v.  A chunk is up to four
-// 64x64 tiles (R0..R0+3, C) of one block column of the lower triangle; wave w
-// owns tile R0 + w whole: the direct part y_R += A_RC v_C comes out complete
-// per row, the transposed part y_C += A_RC^H v_R per column after a
-// transposing wave reduction, and the four waves' column sums are added once.
+// One chunk of z = A22 u.  A chunk is up to four 64x64 tiles (R0..R0+3, C) of
+// one block column of the lower triangle; wave w owns tile R0 + w whole: the
+// direct part z_R += A_RC u_C comes out complete per row, the transposed part
+// z_C += A_RC^H u_R per column after a transposing wave reduction, and the
+// four waves' column sums are added once.
 template <typename R>
-__global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
+__global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
 {
     __shared__ cx<R> svC[ZT];
     __shared__ cx<R> sT[ZCH][ZT];
@@ -139,7 +133,6 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
     const int o = i + 1;
     const int m = n - o;
     const int NB = (m + ZT - 1) / ZT;
-    const int j = i - p;
 
     // which (block column C, chunk ch) is ours
     int bid = blockIdx.x, C = 0;
@@ -153,15 +146,15 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const cx<R>* A = ws.A + b * ws.sA;
+    const cx<R>* Ai = A + (int64_t)i * ws.lda;
     const int64_t lda = ws.lda;
     const int Rb = C + ch * ZCH + w;
     const bool have_tile = Rb < NB;
     const int64_t gr = (int64_t)o + (int64_t)(have_tile ? Rb : C) * ZT + lane;
     const bool row_ok = gr < n;
     // Loads are unconditional from a clamped (in-bounds) address and the value
-    // is masked afterwards, so no branch guards them; the first group of the
-    // tile is requested before the reflector is derived, and each later group
-    // one step ahead of its use.
+    // is masked afterwards, so no branch guards them; each group of 8 columns
+    // is requested one step ahead of its use.
     const cx<R>* Arow = A + (row_ok ? gr : (int64_t)n - 1);
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     auto load_group = [&](int g, cx<R> (&a)[8]) {
@@ -172,16 +165,17 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
         }
     };
     cx<R> a[8], an[8];
-    if (have_tile) load_group(0, a);
-
-    cx<R> tau, scale;
-    R beta;
-    reflector(ws, b, i, tau, scale, beta);
-    if (tid < ZT) svC[tid] = vval(ws, b, i, gcb + tid, scale);
+    load_group(0, a);
+    if (tid < ZT) {
+        const int64_t gc = gcb + tid;
+        const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
+        svC[tid] = (gc > o && gc < n) ? u : czero<cx<R>>();
+    }
+    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
+    if (!(row_ok && gr > o)) uR = czero<cx<R>>();
     __syncthreads();
 
     if (have_tile) {
-        const cx<R> vR = vval(ws, b, i, gr, scale);
         const bool diag_tile = (Rb == C);
         cx<R> yd = czero<cx<R>>();
 #pragma unroll 1
@@ -198,7 +192,7 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
                 x.y = (ok && !diag) ? a[cc].y : (R)0;
                 yd = cfma(x, svC[g * 8 + cc], yd);
                 // the diagonal entry is counted once (direct part only)
-                a[cc] = diag ? czero<cx<R>>() : cmulc(x, vR);
+                a[cc] = diag ? czero<cx<R>>() : cmulc(x, uR);
             }
             const cx<R> r = transpose_sum8<R>(a, lane);
             if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
@@ -214,37 +208,15 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i, int p)
         const cx<R> s = cadd(cadd(sT[0][tid], sT[1][tid]), cadd(sT[2][tid], sT[3][tid]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
     }
-
-    if (ch == 0) {
-        // this workgroup owns rows of block C: store v and the panel dots
-        cx<R>* V = ws.V + b * ws.sV;
-        const int64_t gr = (int64_t)o + (int64_t)C * ZT + lane;
-        if (tid < ZT && gr < n) V[gr + (int64_t)i * n] = svC[tid];
-        const cx<R> vl = svC[lane];
-        const cx<R>* W = ws.W + b * ws.sW;
-        for (int jj = w; jj < j; jj += 4) {
-            cx<R> t1 = czero<cx<R>>(), t2 = czero<cx<R>>();
-            if (gr < n) {
-                t1 = cmulc(W[gr + (int64_t)jj * n], vl);
-                t2 = cmulc(V[gr + (int64_t)(p + jj) * n], vl);
-            }
-            t1.x = wave_sum(t1.x); t1.y = wave_sum(t1.y);
-            t2.x = wave_sum(t2.x); t2.y = wave_sum(t2.y);
-            if (lane == 0) {
-                ws.pvw[b * ws.s_pdot + (int64_t)C * ws.nb + jj] = t1;
-                ws.pvv[b * ws.s_pdot + (int64_t)C * ws.nb + jj] = t2;
-            }
-        }
-        if (C == 0 && tid == 0) {
-            ws.e[b * n + i] = beta;
-            ws.tau[b * n + i] = tau;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
-// y = tau (sum of partials - V (W^H v) - W (V^H v)) for one 64-row block; the
-// four waves split every sum (wave w takes the terms with index = w mod 4).
+// Reflector of column i, v stored, and
+// y = tau (A22(:, o) + scale z - V (W^H v) - W (V^H v)) for one 64-row block.
+// The panel dots come as partials of the unscaled column, W^H v =
+// conj(W(o, :)) + scale * sum_r conj(W(r, :)) A(r, i) over r > o (likewise
+// V^H v).  The four waves split every sum (wave w takes the terms with
+// index = w mod 4).
 template <typename R>
 __global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
 {
@@ -256,19 +228,31 @@ __global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
     const int Rb = blockIdx.x;
     const int j = i - p;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // panel dots W^H v, V^H v (lane = panel column)
+    const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
+    const cx<R>* A = ws.A + b * ws.sA;
+    cx<R>* V = ws.V + b * ws.sV;
+    const cx<R>* W = ws.W + b * ws.sW;
+    // loads that do not depend on the reflector go first
+    cx<R> ai = czero<cx<R>>(), h = czero<cx<R>>();
+    if (w == 0 && gr < n) {
+        ai = A[gr + (int64_t)i * ws.lda];
+        h = A[gr + (int64_t)o * ws.lda];
+        if (gr == o) h.y = 0;
+    }
+    // panel dot partials (lane = panel column)
     {
         cx<R> a1 = czero<cx<R>>(), a2 = czero<cx<R>>();
         if (lane < j) {
-            for (int C = w; C < NB; C += 4) {
-                a1 = cadd(a1, ws.pvw[b * ws.s_pdot + (int64_t)C * ws.nb + lane]);
-                a2 = cadd(a2, ws.pvv[b * ws.s_pdot + (int64_t)C * ws.nb + lane]);
+            const int np = (n - i + RB - 1) / RB;
+            for (int q = w; q < np; q += 4) {
+                a1 = cadd(a1, ws.pvw[b * ws.s_pdot + (int64_t)q * ws.nb + lane]);
+                a2 = cadd(a2, ws.pvv[b * ws.s_pdot + (int64_t)q * ws.nb + lane]);
             }
         }
         s1[w][lane] = a1;
         s2[w][lane] = a2;
     }
-    // partial sums of A22 v for these rows
+    // partial sums of A22 u for these rows
     {
         cx<R> y = czero<cx<R>>();
         const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + lane;
@@ -278,15 +262,19 @@ __global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
         for (int ch = w; ch < nc; ch += 4) y = cadd(y, yq[(int64_t)ch * ZT]);
         sy[w][lane] = y;
     }
+    cx<R> tau, scale;
+    R beta;
+    reflector(ws, b, i, tau, scale, beta);
     __syncthreads();
     if (tid < 64) {
-        swv[tid] = cadd(cadd(s1[0][tid], s1[1][tid]), cadd(s1[2][tid], s1[3][tid]));
-        svv[tid] = cadd(cadd(s2[0][tid], s2[1][tid]), cadd(s2[2][tid], s2[3][tid]));
+        const cx<R> d1 = cadd(cadd(s1[0][tid], s1[1][tid]), cadd(s1[2][tid], s1[3][tid]));
+        const cx<R> d2 = cadd(cadd(s2[0][tid], s2[1][tid]), cadd(s2[2][tid], s2[3][tid]));
+        if (tid < j) {
+            swv[tid] = cfma(scale, d1, cconj(W[(int64_t)o + (int64_t)tid * n]));
+            svv[tid] = cfma(scale, d2, cconj(V[(int64_t)o + (int64_t)(p + tid) * n]));
+        }
     }
     __syncthreads();
-    const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
-    const cx<R>* V = ws.V + b * ws.sV;
-    const cx<R>* W = ws.W + b * ws.sW;
     cx<R> corr = czero<cx<R>>();
     if (gr < n) {
         for (int jj = w; jj < j; jj += 4) {
@@ -299,22 +287,28 @@ __global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
     if (w == 0) {
         cx<R> part = czero<cx<R>>();
         if (gr < n) {
-            cx<R> y = cadd(cadd(sy[0][lane], sy[1][lane]), cadd(sy[2][lane], sy[3][lane]));
+            const cx<R> z = cadd(cadd(sy[0][lane], sy[1][lane]), cadd(sy[2][lane], sy[3][lane]));
             const cx<R> c = cadd(cadd(s1[0][lane], s1[1][lane]), cadd(s1[2][lane], s1[3][lane]));
-            y = cmul(ws.tau[b * n + i], csub(y, c));
+            const cx<R> v = (gr == o) ? mk<R>(1, 0) : cmul(ai, scale);
+            V[gr + (int64_t)i * n] = v;
+            const cx<R> y = cmul(tau, csub(cfma(scale, z, h), c));
             ws.ybuf[b * n + gr] = y;
-            part = cmulc(y, V[gr + (int64_t)i * n]);
+            part = cmulc(y, v);
         }
         part.x = wave_sum(part.x);
         part.y = wave_sum(part.y);
         if (lane == 0) ws.pyv[b * ws.NBmax + Rb] = part;
+        if (Rb == 0 && lane == 0) {
+            ws.e[b * n + i] = beta;
+            ws.tau[b * n + i] = tau;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // w = y + alpha2 v (alpha2 = -(tau/2) y^H v), stored as W(:, j); then, when
 // the panel continues, column i+1 is brought up to date (the four waves split
-// the panel columns) and its partial norm is reduced.
+// the panel columns), and its partial norm and partial panel dots are reduced.
 template <typename R>
 __global__ __launch_bounds__(256) void hetrd_finalize(HetrdWs<R> ws, int i, int p, int update_next)
 {
@@ -355,21 +349,45 @@ __global__ __launch_bounds__(256) void hetrd_finalize(HetrdWs<R> ws, int i, int 
     }
     sp[w][lane] = acc;
     __syncthreads();
-    if (w != 0) return;
-    R nrm = 0;
-    if (gr < n) {
-        cx<R>* A = ws.A + b * ws.sA;
-        const cx<R> c = cadd(cadd(sp[0][lane], sp[1][lane]), cadd(sp[2][lane], sp[3][lane]));
-        cx<R> a = csub(A[gr + (int64_t)o * ws.lda], c);
-        if (gr == o) {
-            a.y = 0;
-            ws.d[b * n + o] = a.x;
+    if (w == 0) {
+        R nrm = 0;
+        cx<R> an = czero<cx<R>>();
+        if (gr < n) {
+            cx<R>* A = ws.A + b * ws.sA;
+            const cx<R> c = cadd(cadd(sp[0][lane], sp[1][lane]), cadd(sp[2][lane], sp[3][lane]));
+            cx<R> a = csub(A[gr + (int64_t)o * ws.lda], c);
+            if (gr == o) {
+                a.y = 0;
+                ws.d[b * n + o] = a.x;
+            }
+            A[gr + (int64_t)o * ws.lda] = a;
+            if (gr >= o + 2) {
+                nrm = a.x * a.x + a.y * a.y;
+                an = a;
+            }
         }
-        A[gr + (int64_t)o * ws.lda] = a;
-        if (gr >= o + 2) nrm = a.x * a.x + a.y * a.y;
+        nrm = wave_sum(nrm);
+        if (lane == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = nrm;
+        sp[0][lane] = an;
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = nrm;
+    __syncthreads();
+    // products of the panel columns 0..j with the updated column below its
+    // sub-diagonal: this block's share of the next reflector's panel dots
+    const cx<R> an = sp[0][lane];
+    for (int jj = w; jj <= j; jj += 4) {
+        cx<R> t1 = czero<cx<R>>(), t2 = czero<cx<R>>();
+        if (gr < n) {
+            const cx<R> wr = (jj < j) ? W[gr + (int64_t)jj * n] : wv;
+            t1 = cmulc(wr, an);
+            t2 = cmulc(V[gr + (int64_t)(p + jj) * n], an);
+        }
+        t1.x = wave_sum(t1.x); t1.y = wave_sum(t1.y);
+        t2.x = wave_sum(t2.x); t2.y = wave_sum(t2.y);
+        if (lane == 0) {
+            ws.pvw[b * ws.s_pdot + (int64_t)blockIdx.x * ws.nb + jj] = t1;
+            ws.pvv[b * ws.s_pdot + (int64_t)blockIdx.x * ws.nb + jj] = t2;
+        }
+    }
 }
 
 }  // namespace
@@ -391,7 +409,7 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
             prof_before(PH_HEMV, st);
-            hipLaunchKernelGGL(hetrd_zhemv<R>, dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i, p);
+            hipLaunchKernelGGL(hetrd_zhemv<R>, dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             hipLaunchKernelGGL(hetrd_reduce<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
