@@ -58,6 +58,8 @@ def _L():
         lib.or_solve_k.argtypes = [I, P, I, P, I, D, P, P, I, P, P, P, P, P, P, P]
         lib.or_zgemm_ri.argtypes = [ctypes.c_char, ctypes.c_char, I, I, I, D, D, P, I, P, I, D, D,
                                     P, I]
+        lib.or_fermi.argtypes = [I, I, P, I, P, D, D, D, P, P, I]
+        lib.or_density.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, P, P]
         lib.or_max_threads.restype = I
         lib.or_set_threads.argtypes = [I]
         _lib = lib
@@ -210,3 +212,43 @@ def solve_k(H, S, vectors: bool = True, s_tol: float = 1e-12, stages: bool = Fal
         st_arr["eA"] = st_arr["eA"][: n - 1]
         return st, w, C, st_arr
     return st, w, C
+
+
+def fermi(w, wk, nelec: float, kT: float, g: float = 2.0):
+    """Band_DFT_Col Part 5: chemical potential and band energy.
+
+    ``w`` is (nk, n) eigenvalues, ``wk`` the k-point weights, ``g`` the
+    electrons one state holds.  Occupations are Fermi-Dirac at temperature
+    ``kT``; mu is found by bisection on the electron count.  Returns
+    (mu, e_band, n_count, occ) with occ (nk, n) the unweighted occupations.
+    """
+    w = np.ascontiguousarray(np.atleast_2d(np.asarray(w, dtype=np.float64)))
+    nk, n = w.shape
+    wk = np.ascontiguousarray(np.asarray(wk, dtype=np.float64).reshape(nk))
+    out = np.zeros(3)
+    occ = np.zeros((nk, n))
+    st = _L().or_fermi(nk, n, _p(w), n, _p(wk), float(nelec), float(kT), float(g), _p(out), _p(occ), n)
+    if st != 0:
+        raise ValueError("or_fermi: invalid arguments")
+    return float(out[0]), float(out[1]), float(out[2]), occ
+
+
+def density(C, w, occ, wk, g: float = 2.0, nocc=None, edm: bool = True):
+    """Band_DFT_Col Part 6: charge density matrix and energy density matrix,
+    rho = g sum_k wk_k sum_j f_kj c_kj c_kj^H and the same with weights
+    f_kj lambda_kj, over the first ``nocc`` columns of each C_k.
+
+    ``C`` is (nk, n, n) with C[k] the mathematical eigenvector matrix of
+    k-point k (column j = eigenvector j).  Returns (rho, edm or None).
+    """
+    C = np.asarray(C, dtype=np.complex128)
+    nk, n, _ = C.shape
+    nocc = n if nocc is None else int(nocc)
+    Cc = np.ascontiguousarray(np.transpose(C, (0, 2, 1)))      # column-major per k
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(nk, n))
+    occ = np.ascontiguousarray(np.asarray(occ, dtype=np.float64).reshape(nk, n))
+    wk = np.ascontiguousarray(np.asarray(wk, dtype=np.float64).reshape(nk))
+    rho = np.zeros((n, n), dtype=np.complex128, order="F")
+    E = np.zeros((n, n), dtype=np.complex128, order="F") if edm else None
+    _L().or_density(nk, n, nocc, _p(Cc), n, n * n, _p(w), n, _p(occ), n, _p(wk), float(g), _p(rho), _p(E))
+    return rho, E

@@ -517,3 +517,108 @@ out:
     free(s); free(X); free(Hf); free(G); free(A); free(Y);
     return st;
 }
+
+/* ------------------------------------------------------------------------
+ * Band_DFT_Col Part 5: chemical potential and band energy.
+ * The paper names the step only; the reading followed here is the usual one
+ * for a finite electronic temperature: occupation of state j at k-point k is
+ * f_kj = 1 / (1 + exp((lambda_kj - mu) / kT)); mu is the root of
+ *   N(mu) = g * sum_k wk_k * sum_j f_kj  =  nelec
+ * (g = electrons per state), found by bisection on a bracket whose ends
+ * are 50 kT beyond the extreme eigenvalues; the band energy is
+ *   E_band = g * sum_k wk_k * sum_j f_kj lambda_kj.
+ * Plain loops in the order written; sums in index order.
+ * ---------------------------------------------------------------------- */
+static double or_fd(double x, double mu, double kT)
+{
+    const double t = (x - mu) / kT;
+    if (t > 0.0) {
+        const double e = exp(-t);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + exp(t));
+}
+
+static double or_count(int nk, int n, const double* w, int ldw, const double* wk, double g, double mu, double kT)
+{
+    double N = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += or_fd(w[(size_t)k * ldw + j], mu, kT);
+        N += wk[k] * s;
+    }
+    return g * N;
+}
+
+/* returns 0, or -1 for invalid arguments (kT <= 0, nelec outside (0, g n sum wk)) */
+int or_fermi(int nk, int n, const double* w, int ldw, const double* wk, double nelec, double kT, double g,
+             double* out3, double* occ, int ldo)
+{
+    if (nk < 1 || n < 1 || !(kT > 0.0) || !(g > 0.0)) return -1;
+    double wsum = 0.0, lo = w[0], hi = w[0];
+    for (int k = 0; k < nk; ++k) {
+        wsum += wk[k];
+        for (int j = 0; j < n; ++j) {
+            const double x = w[(size_t)k * ldw + j];
+            if (x < lo) lo = x;
+            if (x > hi) hi = x;
+        }
+    }
+    if (!(nelec > 0.0) || !(nelec < g * n * wsum)) return -1;
+    lo -= 50.0 * kT;
+    hi += 50.0 * kT;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (or_count(nk, n, w, ldw, wk, g, mid, kT) < nelec) lo = mid;
+        else hi = mid;
+    }
+    const double mu = 0.5 * (lo + hi);
+    double eb = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double x = w[(size_t)k * ldw + j];
+            const double f = or_fd(x, mu, kT);
+            s += f * x;
+            if (occ) occ[(size_t)k * ldo + j] = f;
+        }
+        eb += wk[k] * s;
+    }
+    out3[0] = mu;
+    out3[1] = g * eb;
+    out3[2] = or_count(nk, n, w, ldw, wk, g, mu, kT);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Band_DFT_Col Part 6: charge density matrix and energy density matrix,
+ *   rho = g * sum_k wk_k * sum_{j < nocc} f_kj c_kj c_kj^H,
+ *   edm = g * sum_k wk_k * sum_{j < nocc} f_kj lambda_kj c_kj c_kj^H,
+ * with c_kj column j of the k-th eigenvector matrix (C_k, column-major, ld
+ * ldc, k-stride sc).  Full n x n results, column-major with ld n; edm may be
+ * NULL.  Triple loops, sums in index order (k outer, then j).
+ * ---------------------------------------------------------------------- */
+void or_density(int nk, int n, int nocc, const zc* C, int ldc, long sc, const double* w, int ldw, const double* occ,
+                int ldo, const double* wk, double g, zc* rho, zc* edm)
+{
+#pragma omp parallel for schedule(static)
+    for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+            zc sr = 0.0, se = 0.0;
+            for (int k = 0; k < nk; ++k) {
+                const zc* Ck = C + (size_t)k * sc;
+                zc tr = 0.0, te = 0.0;
+                for (int j = 0; j < nocc; ++j) {
+                    const zc t = Ck[IX(a, j, ldc)] * conj(Ck[IX(b, j, ldc)]);
+                    const double f = occ[(size_t)k * ldo + j];
+                    tr += f * t;
+                    te += f * w[(size_t)k * ldw + j] * t;
+                }
+                sr += wk[k] * tr;
+                se += wk[k] * te;
+            }
+            rho[IX(a, b, n)] = g * sr;
+            if (edm) edm[IX(a, b, n)] = g * se;
+        }
+}
