@@ -5,8 +5,12 @@
 //
 // Complex product: C = alpha * sum_s op(A_s) op(B_s) + beta * C with one or
 // two terms s (two terms give the Hermitian rank-2k update V W^H + W V^H in
-// one pass).  A complex tile product is four real MFMA products on planar
-// (re, im) LDS tiles; op(A) = A^H is folded into the global->LDS copy.
+// one pass).  A complex tile product is formed from real MFMA products on
+// planar (re, im) LDS tiles, either the four products of the definition or
+// the three of the Gauss (3M) form, re = ar br - ai bi and
+// im = (ar + ai)(br + bi) - ar br - ai bi, which saves a quarter of the MFMA
+// work at a normwise (not componentwise) error bound of the same order;
+// op(A) = A^H is folded into the global->LDS copy.
 #include <stdlib.h>
 
 #include "common.hpp"
@@ -55,69 +59,79 @@ __device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_
     tn = local / rows_g;
 }
 
-// global -> registers: this thread's elements of the op(A) tile (BM x GB_K)
-template <typename R, int BM>
-__device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int ta, int64_t m, int64_t K, int64_t i0,
-                              int64_t k0, int tid, cx<R> (&ra)[BM * GB_K / G_THREADS])
+// global -> registers: this thread's elements of the op(A) tile (BM x GB_K).
+// The loads come from clamped (in-bounds) addresses with no branch, so they
+// stay in flight across the MFMA work of the current step; the bounds mask
+// and the conjugation of op = ^H are applied when the registers are stored
+// to LDS.
+template <typename R, int BM, int TA>
+__device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int64_t m, int64_t K, int64_t i0,
+                              int64_t k0, int tid, cx<R> (&ra)[BM * GB_K / G_THREADS], unsigned& okmask)
 {
     constexpr int NE = BM * GB_K / G_THREADS;
+    okmask = 0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        int r, kk;
-        if (ta == 0) { r = e % BM; kk = e / BM; } else { kk = e % GB_K; r = e / GB_K; }
+        const int r = TA ? e / GB_K : e % BM;
+        const int kk = TA ? e % GB_K : e / BM;
         const int64_t gi = i0 + r, gk = k0 + kk;
         const bool ok = gi < m && gk < K;
-        const int64_t gic = ok ? gi : 0, gkc = ok ? gk : 0;
-        cx<R> v = (ta == 0) ? A[gic + gkc * lda] : cconj(A[gkc + gic * lda]);
-        ra[q] = ok ? v : czero<cx<R>>();
+        const int64_t gic = gi < m ? gi : m - 1, gkc = gk < K ? gk : K - 1;
+        ra[q] = TA ? A[gkc + gic * lda] : A[gic + gkc * lda];
+        okmask |= (unsigned)ok << q;
     }
 }
 
-template <typename R, int BM>
-__device__ inline void store_a(R (*sr)[BM + 1], R (*si)[BM + 1], int ta, int tid, const cx<R> (&ra)[BM * GB_K / G_THREADS])
+template <typename R, int BM, int TA>
+__device__ inline void store_a(R (*sr)[BM + 1], R (*si)[BM + 1], int tid, const cx<R> (&ra)[BM * GB_K / G_THREADS],
+                               unsigned okmask)
 {
     constexpr int NE = BM * GB_K / G_THREADS;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        int r, kk;
-        if (ta == 0) { r = e % BM; kk = e / BM; } else { kk = e % GB_K; r = e / GB_K; }
-        sr[kk][r] = ra[q].x;
-        si[kk][r] = ra[q].y;
+        const int r = TA ? e / GB_K : e % BM;
+        const int kk = TA ? e % GB_K : e / BM;
+        const bool ok = (okmask >> q) & 1u;
+        sr[kk][r] = ok ? ra[q].x : (R)0;
+        si[kk][r] = ok ? (TA ? -ra[q].y : ra[q].y) : (R)0;
     }
 }
 
 // op(B) tile (GB_K x BN)
-template <typename R, int BN>
-__device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int tb, int64_t n, int64_t K, int64_t j0,
-                              int64_t k0, int tid, cx<R> (&rb)[BN * GB_K / G_THREADS])
+template <typename R, int BN, int TB>
+__device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int64_t n, int64_t K, int64_t j0,
+                              int64_t k0, int tid, cx<R> (&rb)[BN * GB_K / G_THREADS], unsigned& okmask)
 {
     constexpr int NE = BN * GB_K / G_THREADS;
+    okmask = 0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        int c, kk;
-        if (tb == 0) { kk = e % GB_K; c = e / GB_K; } else { c = e % BN; kk = e / BN; }
+        const int c = TB ? e % BN : e / GB_K;
+        const int kk = TB ? e / BN : e % GB_K;
         const int64_t gj = j0 + c, gk = k0 + kk;
         const bool ok = gj < n && gk < K;
-        const int64_t gjc = ok ? gj : 0, gkc = ok ? gk : 0;
-        cx<R> v = (tb == 0) ? B[gkc + gjc * ldb] : cconj(B[gjc + gkc * ldb]);
-        rb[q] = ok ? v : czero<cx<R>>();
+        const int64_t gjc = gj < n ? gj : n - 1, gkc = gk < K ? gk : K - 1;
+        rb[q] = TB ? B[gjc + gkc * ldb] : B[gkc + gjc * ldb];
+        okmask |= (unsigned)ok << q;
     }
 }
 
-template <typename R, int BN>
-__device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tb, int tid, const cx<R> (&rb)[BN * GB_K / G_THREADS])
+template <typename R, int BN, int TB>
+__device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const cx<R> (&rb)[BN * GB_K / G_THREADS],
+                               unsigned okmask)
 {
     constexpr int NE = BN * GB_K / G_THREADS;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        int c, kk;
-        if (tb == 0) { kk = e % GB_K; c = e / GB_K; } else { c = e % BN; kk = e / BN; }
-        sr[kk][c] = rb[q].x;
-        si[kk][c] = rb[q].y;
+        const int c = TB ? e % BN : e / GB_K;
+        const int kk = TB ? e / BN : e % GB_K;
+        const bool ok = (okmask >> q) & 1u;
+        sr[kk][c] = ok ? rb[q].x : (R)0;
+        si[kk][c] = ok ? (TB ? -rb[q].y : rb[q].y) : (R)0;
     }
 }
 
@@ -125,8 +139,8 @@ __device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tb, int tid
 // (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  Two LDS stages: while stage
 // s is multiplied, the next K step is fetched into registers and then stored
 // into stage s^1, so one barrier per K step suffices.
-template <typename R, int BM, int BN>
-__global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
+template <typename R, int BM, int BN, bool G3, int TA, int TB>
+__global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
 {
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
@@ -147,31 +161,38 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
     const int wm = w & 1, wn = w >> 1;
     const int li = lane & 15, lk = lane >> 4;
 
-    acc_t accR[TM][TN], accI[TM][TN];
+    // 4M: accR = re, accI = im.  3M: accR = sum ar br, accI = sum (ar+ai)(br+bi),
+    // accT = sum ai bi.
+    acc_t accR[TM][TN], accI[TM][TN], accT[G3 ? TM : 1][G3 ? TN : 1];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+            for (int r = 0; r < 4; ++r) {
+                accR[a][b][r] = 0;
+                accI[a][b][r] = 0;
+                if constexpr (G3) accT[a][b][r] = 0;
+            }
 
     const int nkt = (int)((K + GB_K - 1) / GB_K);
     const int total_k = nkt * p.nseg;
     cx<R> ra[BM * GB_K / G_THREADS], rb[BN * GB_K / G_THREADS];
+    unsigned oka = 0, okb = 0;
     int cur = 0;
     if (total_k > 0) {
-        load_a<R, BM>(p.A[0] + bz * p.sA[0], p.lda[0], p.ta[0], m, K, i0, 0, tid, ra);
-        load_b<R, BN>(p.B[0] + bz * p.sB[0], p.ldb[0], p.tb[0], n, K, j0, 0, tid, rb);
-        store_a<R, BM>(sAr[0], sAi[0], p.ta[0], tid, ra);
-        store_b<R, BN>(sBr[0], sBi[0], p.tb[0], tid, rb);
+        load_a<R, BM, TA>(p.A[0] + bz * p.sA[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
+        load_b<R, BN, TB>(p.B[0] + bz * p.sB[0], p.ldb[0], n, K, j0, 0, tid, rb, okb);
+        store_a<R, BM, TA>(sAr[0], sAi[0], tid, ra, oka);
+        store_b<R, BN, TB>(sBr[0], sBi[0], tid, rb, okb);
     }
     __syncthreads();
     for (int it = 0; it < total_k; ++it) {
         const int nx = it + 1;
         const int sn = nx / nkt, kt = nx % nkt;
         if (nx < total_k) {
-            load_a<R, BM>(p.A[sn] + bz * p.sA[sn], p.lda[sn], p.ta[sn], m, K, i0, (int64_t)kt * GB_K, tid, ra);
-            load_b<R, BN>(p.B[sn] + bz * p.sB[sn], p.ldb[sn], p.tb[sn], n, K, j0, (int64_t)kt * GB_K, tid, rb);
+            load_a<R, BM, TA>(p.A[sn] + bz * p.sA[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid, ra, oka);
+            load_b<R, BN, TB>(p.B[sn] + bz * p.sB[sn], p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid, rb, okb);
         }
 #pragma unroll
         for (int ks = 0; ks < GB_K; ks += 4) {
@@ -186,21 +207,37 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
                 br[t] = sBr[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
                 bi[t] = sBi[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
             }
+            if constexpr (G3) {
+                R bs[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) {
-                const R nai = -ai[a];
+                for (int t = 0; t < TN; ++t) bs[t] = br[t] + bi[t];
 #pragma unroll
-                for (int b = 0; b < TN; ++b) {
-                    accR[a][b] = M::mma(ar[a], br[b], accR[a][b]);
-                    accR[a][b] = M::mma(nai, bi[b], accR[a][b]);
-                    accI[a][b] = M::mma(ar[a], bi[b], accI[a][b]);
-                    accI[a][b] = M::mma(ai[a], br[b], accI[a][b]);
+                for (int a = 0; a < TM; ++a) {
+                    const R as = ar[a] + ai[a];
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) {
+                        accR[a][b] = M::mma(ar[a], br[b], accR[a][b]);
+                        accI[a][b] = M::mma(as, bs[b], accI[a][b]);
+                        accT[a][b] = M::mma(ai[a], bi[b], accT[a][b]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < TM; ++a) {
+                    const R nai = -ai[a];
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) {
+                        accR[a][b] = M::mma(ar[a], br[b], accR[a][b]);
+                        accR[a][b] = M::mma(nai, bi[b], accR[a][b]);
+                        accI[a][b] = M::mma(ar[a], bi[b], accI[a][b]);
+                        accI[a][b] = M::mma(ai[a], br[b], accI[a][b]);
+                    }
                 }
             }
         }
         if (nx < total_k) {
-            store_a<R, BM>(sAr[cur ^ 1], sAi[cur ^ 1], p.ta[sn], tid, ra);
-            store_b<R, BN>(sBr[cur ^ 1], sBi[cur ^ 1], p.tb[sn], tid, rb);
+            store_a<R, BM, TA>(sAr[cur ^ 1], sAi[cur ^ 1], tid, ra, oka);
+            store_b<R, BN, TB>(sBr[cur ^ 1], sBi[cur ^ 1], tid, rb, okb);
         }
         __syncthreads();
         cur ^= 1;
@@ -217,7 +254,13 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
                 const int64_t i = i0 + wm * (BM / 2) + a * 16 + M::row(lk, r);
                 const int64_t j = j0 + wn * (BN / 2) + b * 16 + li;
                 if (i < m && j < n && (!p.lower || i >= j)) {
-                    cx<R> v = mk<R>(accR[a][b][r], accI[a][b][r]);
+                    cx<R> v;
+                    if constexpr (G3) {
+                        const R pr = accR[a][b][r], qi = accT[a][b][r];
+                        v = mk<R>(pr - qi, accI[a][b][r] - pr - qi);
+                    } else {
+                        v = mk<R>(accR[a][b][r], accI[a][b][r]);
+                    }
                     cx<R> out = cmul(p.alpha, v);
                     if (rb0) out = cfma(p.beta, C[i + j * p.ldc], out);
                     C[i + j * p.ldc] = out;
@@ -225,14 +268,27 @@ __global__ __launch_bounds__(G_THREADS) void cgemm_kernel(CGemmArgs<R> p)
             }
 }
 
-template <typename R, int BM, int BN>
+template <typename R, int BM, int BN, bool G3, int TA, int TB>
 hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st)
 {
     p.tiles_m = (int)((p.m + BM - 1) / BM);
     p.tiles_n = (int)((p.n + BN - 1) / BN);
     const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
-    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
+    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN, G3, TA, TB>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
     return hipGetLastError();
+}
+
+// the operand forms are compile-time so that the tile loads are straight-line
+template <typename R, bool G3>
+hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st)
+{
+    const int f = p.ta[0] * 2 + p.tb[0];
+    switch (f) {
+    case 0: return launch_tiles<R, 64, 64, G3, 0, 0>(p, st);
+    case 1: return launch_tiles<R, 64, 64, G3, 0, 1>(p, st);
+    case 2: return launch_tiles<R, 64, 64, G3, 1, 0>(p, st);
+    default: return launch_tiles<R, 64, 64, G3, 1, 1>(p, st);
+    }
 }
 
 template <typename R>
@@ -243,26 +299,20 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
     p.batch = batch;
     double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch;
     if (a.lower) flops *= 0.5;
-    // large outputs take 128 x 128 tiles (half the operand traffic per flop);
-    // skinny ones keep 64 x 64 so that enough workgroups exist
-    // KGEV_GEMM_TILE=64|128 and KGEV_GEMM_REMAP=0|1 override the defaults
-    // (tuning experiments)
-    static const int forced = [] {
-        const char* v = getenv("KGEV_GEMM_TILE");
-        return v ? atoi(v) : 0;
-    }();
+    // The 3M form is the default: on gfx950 it measured 1.22x the 4M form on
+    // the path's products with unchanged residuals.  KGEV_GEMM_REMAP=0|1 and
+    // KGEV_GEMM_3M=0|1 override the defaults (tuning experiments).
     static const int remap = [] {
         const char* v = getenv("KGEV_GEMM_REMAP");
         return v ? atoi(v) : 1;
     }();
+    static const int g3 = [] {
+        const char* v = getenv("KGEV_GEMM_3M");
+        return v ? atoi(v) : 1;
+    }();
     p.remap = remap;
-    const int64_t big_tiles = ((a.m + 127) / 128) * ((a.n + 63) / 64) * batch;
-    // measured on gfx950: the 64 x 64 tile with two LDS stages beats 128 x 64
-    // at every shape of this path, so the wider tile is only used on request
-    (void)big_tiles;
-    const bool big = forced == 128;
     prof_before(PH_GEMM, st);
-    hipError_t e = big ? launch_tiles<R, 128, 64>(p, st) : launch_tiles<R, 64, 64>(p, st);
+    hipError_t e = g3 ? launch_forms<R, true>(p, st) : launch_forms<R, false>(p, st);
     prof_after(PH_GEMM, st, 0.0, flops);
     return e;
 }
