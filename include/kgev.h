@@ -59,6 +59,7 @@ typedef int32_t kgev_status;
 #define KGEV_ENOTPD        1    /* S(k) not positive definite: s_min <= s_tol * s_max */
 #define KGEV_ENOCONV       2    /* tridiagonal eigensolver did not converge */
 #define KGEV_ENONFINITE    3    /* NaN or Inf in the lower triangle of H(k) or S(k) */
+#define KGEV_ERANGE        4    /* kgev_fermi_device: nelec not inside (0, g n sum(wk)) */
 #define KGEV_ENOMEM     (-100)  /* device or host allocation failed */
 #define KGEV_EDEVICE    (-101)  /* a HIP runtime call failed */
 #define KGEV_EUNSUPPORTED (-102)/* option combination not supported */
@@ -78,7 +79,9 @@ typedef struct {
     int32_t use_graph;    /* 1: capture the whole batched solve as one HIP graph on the first call with
                              these sizes, buffers and stream, and replay it afterwards (the stream must
                              not be the null stream); 0 (default): launch kernel by kernel */
-    int32_t reserved[7];  /* must be zero */
+    int32_t streams;      /* k-point groups solved concurrently, each on its own stream forked from
+                             (and joined back into) the caller's stream: 0 = default, 1..8 */
+    int32_t reserved[6];  /* must be zero */
 } kgev_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -281,6 +284,55 @@ void kgev_server_destroy(kgev_server* srv);
  * bytes and flops, and stops recording.  Timing adds two event records per
  * launch of the chosen phase and nothing else.
  */
+/*
+ * Band_DFT_Col Part 5 (arXiv:1402.4247, the routine's outline in the
+ * section applying the method to OpenMX: chemical potential and band energy),
+ * on the device.  The paper names the step only; the occupation of state j
+ * of k-point k is the Fermi-Dirac function at temperature kT,
+ *   f_kj = 1 / (1 + exp((w_kj - mu) / kT)),
+ * and mu is the root of  g sum_k wk[k] sum_j f_kj = nelec  (g = electrons
+ * per state: 2 without spin, 1 per spin channel), found by bisection on a
+ * bracket 50 kT beyond the extreme eigenvalues until the midpoint no longer
+ * separates from its ends.  Then
+ *   e_band = g sum_k wk[k] sum_j f_kj w_kj.
+ *   dw      : device, nk x n eigenvalues, k-point k at dw + k * ldw (ldw >= n)
+ *   d_wk    : device, nk k-point weights
+ *   d_occ   : device, nk x n occupations f_kj written at d_occ + k * ldo
+ *             (ldo >= n), or NULL
+ *   d_result: device, 3 doubles {mu, e_band, electron count at mu}
+ *   d_status: device, one int32: KGEV_OK, or KGEV_ERANGE when nelec is not
+ *             inside (0, g n sum(wk)) (then nothing else is written)
+ * One workgroup; asynchronous on `stream`.  Returns an argument error at once
+ * (-1 ctx, -2 dw, -3 ldw, -4 n, -5 nk, -6 d_wk, -8 kT <= 0 or not finite,
+ * -9 g <= 0, -11 ldo, -12 d_result, -13 d_status), else KGEV_OK.
+ */
+kgev_status kgev_fermi_device(kgev_ctx* ctx, const double* dw, int64_t ldw, int64_t n, int64_t nk,
+                              const double* d_wk, double nelec, double kT, double g, double* d_occ, int64_t ldo,
+                              double* d_result, int32_t* d_status, void* stream);
+
+/*
+ * Band_DFT_Col Part 6 (same outline: charge density matrix and energy density
+ * matrix), on the device, over the first nocc eigenvectors of each k-point:
+ *   rho = g sum_k wk[k] sum_{j < nocc} f_kj c_kj c_kj^H
+ *   edm = g sum_k wk[k] sum_{j < nocc} f_kj w_kj c_kj c_kj^H
+ * with c_kj column j of C_k (dC + k * ldc * n, column-major, ldc >= n: the
+ * layout kgev_solve_k_device writes).  Only the lower triangles (i >= j) of
+ * rho and edm are written (ld ldr >= n); edm may be NULL.  The products run
+ * as batched MFMA products (one per k-point, lower half) into the workspace,
+ * then a fixed-order sum over k.
+ *   dwork : device workspace of at least kgev_density_workspace_bytes(n, nk,
+ *           nocc) bytes, or NULL to use the context's internal workspace.
+ * Asynchronous on `stream`.  Returns an argument error at once (-1 ctx, -2 dC,
+ * -3 ldc, -4 n, -5 nk, -6 nocc not in [0, n], -7 dw, -8 ldw, -9 d_occ,
+ * -10 ldo, -11 d_wk, -12 g <= 0, -13 d_rho, -15 ldr, -17 work_bytes too
+ * small), KGEV_ENOMEM / KGEV_EDEVICE, else KGEV_OK.
+ */
+size_t kgev_density_workspace_bytes(int64_t n, int64_t nk, int64_t nocc);
+kgev_status kgev_density_device(kgev_ctx* ctx, const kgev_z* dC, int64_t ldc, int64_t n, int64_t nk, int64_t nocc,
+                                const double* dw, int64_t ldw, const double* d_occ, int64_t ldo, const double* d_wk,
+                                double g, kgev_z* d_rho, kgev_z* d_edm, int64_t ldr, void* dwork, size_t work_bytes,
+                                void* stream);
+
 #define KGEV_PHASE_HEMV 1
 #define KGEV_PHASE_GEMM 2
 kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase);

@@ -60,6 +60,7 @@ def _L():
                                     P, I]
         lib.or_fermi.argtypes = [I, I, P, I, P, D, D, D, P, P, I]
         lib.or_density.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, P, P]
+        lib.or_density_entries.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, I, P, P, P]
         lib.or_max_threads.restype = I
         lib.or_set_threads.argtypes = [I]
         _lib = lib
@@ -252,3 +253,21 @@ def density(C, w, occ, wk, g: float = 2.0, nocc=None, edm: bool = True):
     E = np.zeros((n, n), dtype=np.complex128, order="F") if edm else None
     _L().or_density(nk, n, nocc, _p(Cc), n, n * n, _p(w), n, _p(occ), n, _p(wk), float(g), _p(rho), _p(E))
     return rho, E
+
+
+def density_entries(Ccol, w, occ, wk, g, pairs, nocc=None):
+    """Part 6 at the listed (a, b) entries.  ``Ccol`` is (nk, n, n) holding
+    each C_k in column-major order (Ccol[k, j, i] = C_k[i, j]), as the device
+    layout is.  Returns (rho_entries, edm_entries)."""
+    Ccol = np.ascontiguousarray(np.asarray(Ccol, dtype=np.complex128))
+    nk, n, _ = Ccol.shape
+    nocc = n if nocc is None else int(nocc)
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(nk, n))
+    occ = np.ascontiguousarray(np.asarray(occ, dtype=np.float64).reshape(nk, n))
+    wk = np.ascontiguousarray(np.asarray(wk, dtype=np.float64).reshape(nk))
+    ab = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    r = np.zeros(len(ab), dtype=np.complex128)
+    e = np.zeros(len(ab), dtype=np.complex128)
+    _L().or_density_entries(nk, n, nocc, _p(Ccol), n, n * n, _p(w), n, _p(occ), n, _p(wk), float(g), len(ab),
+                            _p(ab), _p(r), _p(e))
+    return r, e

@@ -622,3 +622,31 @@ void or_density(int nk, int n, int nocc, const zc* C, int ldc, long sc, const do
             if (edm) edm[IX(a, b, n)] = g * se;
         }
 }
+
+/* Part 6 at selected entries (a_q, b_q), q < npairs: the same sums as
+ * or_density, for sizes where the full matrices are too costly here. */
+void or_density_entries(int nk, int n, int nocc, const zc* C, int ldc, long sc, const double* w, int ldw,
+                        const double* occ, int ldo, const double* wk, double g, int npairs, const int* ab,
+                        zc* rho, zc* edm)
+{
+    (void)n;
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < npairs; ++q) {
+        const int a = ab[2 * q], b = ab[2 * q + 1];
+        zc sr = 0.0, se = 0.0;
+        for (int k = 0; k < nk; ++k) {
+            const zc* Ck = C + (size_t)k * sc;
+            zc tr = 0.0, te = 0.0;
+            for (int j = 0; j < nocc; ++j) {
+                const zc t = Ck[IX(a, j, ldc)] * conj(Ck[IX(b, j, ldc)]);
+                const double f = occ[(size_t)k * ldo + j];
+                tr += f * t;
+                te += f * w[(size_t)k * ldw + j] * t;
+            }
+            sr += wk[k] * tr;
+            se += wk[k] * te;
+        }
+        rho[q] = g * sr;
+        edm[q] = g * se;
+    }
+}

@@ -32,7 +32,7 @@ bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double
 // Everything that identifies a captured solve: sizes, options, buffers, stream.
 struct GraphKey {
     int64_t n, ld, nk, ldc;
-    int32_t precision, want_vectors, panel_nb, refine_iters;
+    int32_t precision, want_vectors, panel_nb, refine_iters, streams;
     double s_tol;
     const void *H, *S, *w, *C, *work, *status, *stream;
     bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
@@ -40,6 +40,8 @@ struct GraphKey {
 
 struct kgev_ctx {
     int device;
+    std::vector<hipStream_t> aux;      // streams of the concurrent k-point groups 1..
+    std::vector<hipEvent_t> ev;        // ev[0]: fork, ev[q]: join of group q
     kgev::Profiler* prof;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // most recent last
     std::map<std::pair<int64_t, int>, int> tuned_nb;            // (n, precision) -> panel width
@@ -54,6 +56,7 @@ struct kgev_ctx {
 namespace {
 
 constexpr int DEFAULT_NB = 32;
+constexpr int DEFAULT_STREAMS = 1;
 constexpr int UNMTR_KB = 64;
 
 struct Layout {
@@ -72,7 +75,7 @@ struct SolvePlan {
     int nb, kb;
     int NBmax, CHmax, PN;
     // complex128 arrays
-    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, pyv, ybuf, uwork;
+    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, qpart, uwork;
     // real / int arrays
     size_t d, e, sS, wA, pnorm, Zr, Qs, Vsec;
     size_t dc_es, dc_onrm, dc_D0, dc_D1, dc_sd, dc_sz, dc_ndd, dc_ndz, dc_dfd, dc_rotc, dc_rots, dc_rho, dc_tauv,
@@ -82,7 +85,7 @@ struct SolvePlan {
     // mixed precision: complex64 tridiagonalisation / back-transformation
     // buffers and the FP64 refinement scratch (size 0 in the FP64 form)
     bool mixed;
-    size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_pvv, f_pyv, f_ybuf, f_uwork, f_d, f_e, f_pnorm;
+    size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_pvv, f_qpart, f_uwork, f_d, f_e, f_pnorm;
     size_t r_Ynext, r_G, r_S, r_F, r_pS, r_pR, r_delta;
     size_t total;
 };
@@ -112,16 +115,15 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.tau = L.add(z * n * nk);
     p.ypart = L.add(z * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.ypartT = L.add(z * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.pvw = L.add(z * (size_t)p.NBmax * nbA * nk);
-    p.pvv = L.add(z * (size_t)p.NBmax * nbA * nk);
-    p.pyv = L.add(z * (size_t)p.NBmax * nk);
-    p.ybuf = L.add(z * n * nk);
+    p.pvw = L.add(z * 2 * (size_t)p.NBmax * nbA * nk);
+    p.pvv = L.add(z * 2 * (size_t)p.NBmax * nbA * nk);
+    p.qpart = L.add(r * (size_t)p.NBmax * p.CHmax * nk);
     p.uwork = L.add(z * (size_t)unmtr_work_elems(n, p.kb) * nk);
     p.d = L.add(r * n * nk);
     p.e = L.add(r * n * nk);
     p.sS = L.add(r * n * nk);
     p.wA = L.add(r * n * nk);
-    p.pnorm = L.add(r * p.PN * nk);
+    p.pnorm = L.add(r * 2 * p.PN * nk);
     p.Zr = L.add(r * nn * nk);
     p.Qs = L.add(r * nn * nk);
     p.Vsec = L.add(r * nn * nk);
@@ -142,14 +144,13 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.f_tau = L.add(m * c * n * nk);
     p.f_ypart = L.add(m * c * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.f_ypartT = L.add(m * c * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.f_pvw = L.add(m * c * (size_t)p.NBmax * nbA * nk);
-    p.f_pvv = L.add(m * c * (size_t)p.NBmax * nbA * nk);
-    p.f_pyv = L.add(m * c * (size_t)p.NBmax * nk);
-    p.f_ybuf = L.add(m * c * n * nk);
+    p.f_pvw = L.add(m * c * 2 * (size_t)p.NBmax * nbA * nk);
+    p.f_pvv = L.add(m * c * 2 * (size_t)p.NBmax * nbA * nk);
+    p.f_qpart = L.add(m * f * (size_t)p.NBmax * p.CHmax * nk);
     p.f_uwork = L.add(m * c * (size_t)unmtr_work_elems(n, p.kb) * nk);
     p.f_d = L.add(m * f * n * nk);
     p.f_e = L.add(m * f * n * nk);
-    p.f_pnorm = L.add(m * f * p.PN * nk);
+    p.f_pnorm = L.add(m * f * 2 * p.PN * nk);
     p.r_Ynext = L.add(m * z * nn * nk);
     p.r_G = L.add(m * z * nn * nk);
     p.r_S = L.add(m * z * nn * nk);
@@ -174,14 +175,13 @@ HetrdWs<float> hetrd_ws32(const SolvePlan& p, void* w)
     h.d = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_d);
     h.e = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_e);
     h.tau = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_tau);
-    h.pnorm = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_pnorm); h.s_pnorm = p.PN;
+    h.pnorm = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_pnorm); h.s_pnorm = 2 * p.PN;
     h.ypart = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
     h.ypartT = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
     h.pvw = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvw);
     h.pvv = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvv);
-    h.s_pdot = (int64_t)p.NBmax * p.nb;
-    h.pyv = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pyv);
-    h.ybuf = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ybuf);
+    h.s_pdot = 2 * (int64_t)p.NBmax * p.nb;
+    h.qpart = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_qpart); h.s_qpart = (int64_t)p.NBmax * p.CHmax;
     return h;
 }
 
@@ -199,12 +199,11 @@ HetrdWs<double> hetrd_ws(const SolvePlan& p, void* w, double2* A, int64_t lda, i
     h.V = V; h.sV = p.n * p.n;
     h.W = at<double2>(w, p.Wp); h.sW = p.n * p.nb;
     h.d = d; h.e = e; h.tau = tau;
-    h.pnorm = at<double>(w, p.pnorm); h.s_pnorm = p.PN;
+    h.pnorm = at<double>(w, p.pnorm); h.s_pnorm = 2 * p.PN;
     h.ypart = at<double2>(w, p.ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
     h.ypartT = at<double2>(w, p.ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
-    h.pvw = at<double2>(w, p.pvw); h.pvv = at<double2>(w, p.pvv); h.s_pdot = (int64_t)p.NBmax * p.nb;
-    h.pyv = at<double2>(w, p.pyv);
-    h.ybuf = at<double2>(w, p.ybuf);
+    h.pvw = at<double2>(w, p.pvw); h.pvv = at<double2>(w, p.pvv); h.s_pdot = 2 * (int64_t)p.NBmax * p.nb;
+    h.qpart = at<double>(w, p.qpart); h.s_qpart = (int64_t)p.NBmax * p.CHmax;
     return h;
 }
 
@@ -242,6 +241,7 @@ kgev_opts resolve_opts(const kgev_opts* o)
     if (r.panel_nb == 0) r.panel_nb = DEFAULT_NB;
     if (r.s_tol == 0.0) r.s_tol = 1e-12;
     if (r.refine_iters == 0) r.refine_iters = 3;
+    if (r.streams == 0) r.streams = DEFAULT_STREAMS;
     return r;
 }
 
@@ -253,7 +253,8 @@ bool opts_valid(const kgev_opts& o)
     if (o.panel_nb < 1 || o.panel_nb > 64) return false;
     if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
     if (o.use_graph != 0 && o.use_graph != 1) return false;
-    for (int q = 0; q < 7; ++q)
+    if (o.streams < 1 || o.streams > 8) return false;
+    for (int q = 0; q < 6; ++q)
         if (o.reserved[q] != 0) return false;
     return true;
 }
@@ -407,6 +408,67 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     return KGEV_OK;
 }
 
+// Concurrent k-point groups: G = min(streams, nk) groups of ceil(nk / G)
+// k-points, each with its own workspace region; group 0 runs on the caller's
+// stream, group q > 0 on a context stream forked from it and joined back, so
+// the latency-bound phases of one group overlap the streaming and MFMA phases
+// of the others.
+struct Groups {
+    int G;
+    int64_t gsz;
+    size_t region;
+    SolvePlan p;
+};
+
+Groups make_groups(int64_t n, int64_t nk, const kgev_opts& o)
+{
+    Groups g;
+    g.G = (int)std::min<int64_t>(o.streams, nk);
+    g.gsz = (nk + g.G - 1) / g.G;
+    g.G = (int)((nk + g.gsz - 1) / g.gsz);
+    g.p = make_plan(n, g.gsz, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+    g.region = (g.p.total + 255) & ~(size_t)255;
+    return g;
+}
+
+kgev_status ensure_aux(kgev_ctx* ctx, int G)
+{
+    while ((int)ctx->aux.size() < G - 1) {
+        hipStream_t s = nullptr;
+        KCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ctx->aux.push_back(s);
+    }
+    while ((int)ctx->ev.size() < G) {
+        hipEvent_t e = nullptr;
+        KCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->ev.push_back(e);
+    }
+    return KGEV_OK;
+}
+
+kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, void* w, hipStream_t st,
+                          const double2* H, const double2* S, int64_t ld, int64_t nk, double* dw, double2* dC,
+                          int64_t ldc, int32_t* d_status)
+{
+    const int64_t n = g.p.n;
+    if (g.G == 1) return solve_device(g.p, o, w, st, H, S, ld, dw, dC, ldc, d_status);
+    kgev_status r = ensure_aux(ctx, g.G);
+    if (r != KGEV_OK) return r;
+    KCHECK(hipEventRecord(ctx->ev[0], st));
+    for (int q = 0; q < g.G; ++q) {
+        const int64_t k0 = q * g.gsz, cnt = std::min<int64_t>(g.gsz, nk - k0);
+        const SolvePlan pq = (cnt == g.gsz) ? g.p : make_plan(n, cnt, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+        hipStream_t s = q == 0 ? st : ctx->aux[q - 1];
+        if (q > 0) KCHECK(hipStreamWaitEvent(s, ctx->ev[0], 0));
+        r = solve_device(pq, o, static_cast<char*>(w) + (size_t)q * g.region, s, H + k0 * ld * n, S + k0 * ld * n,
+                         ld, dw + k0 * n, dC ? dC + k0 * ldc * n : nullptr, ldc, d_status ? d_status + k0 : nullptr);
+        if (r != KGEV_OK) return r;
+        if (q > 0) KCHECK(hipEventRecord(ctx->ev[q], s));
+    }
+    for (int q = 1; q < g.G; ++q) KCHECK(hipStreamWaitEvent(st, ctx->ev[q], 0));
+    return KGEV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -429,6 +491,7 @@ const char* kgev_status_str(kgev_status st)
     case KGEV_ENOTPD: return "S(k) is not positive definite";
     case KGEV_ENOCONV: return "tridiagonal eigensolver did not converge";
     case KGEV_ENONFINITE: return "non-finite value in H(k) or S(k)";
+    case KGEV_ERANGE: return "electron count outside the range the states can hold";
     case KGEV_ENOMEM: return "out of memory";
     case KGEV_EDEVICE: return "HIP runtime error";
     case KGEV_EUNSUPPORTED: return "unsupported option";
@@ -466,6 +529,8 @@ void kgev_destroy(kgev_ctx* ctx)
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    for (hipStream_t x : ctx->aux) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : ctx->ev) (void)hipEventDestroy(x);
     delete ctx;
 }
 
@@ -473,7 +538,8 @@ size_t kgev_workspace_bytes(int64_t n, int64_t nk, const kgev_opts* opts)
 {
     if (n < 1 || nk < 1) return 0;
     kgev_opts o = resolve_opts(opts);
-    return make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE).total;
+    const Groups g = make_groups(n, nk, o);
+    return g.region * (size_t)g.G;
 }
 
 kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
@@ -500,24 +566,27 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     if (!opts_valid(o)) return -10;
     if (o.want_vectors && (!dC || ldc < n)) return -8;
     DevGuard g(ctx->device);
-    SolvePlan p = make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+    const Groups grp = make_groups(n, nk, o);
+    const size_t need = grp.region * (size_t)grp.G;
     void* w = dwork;
     if (w) {
-        if (work_bytes < p.total) return -9;
+        if (work_bytes < need) return -9;
     } else {
-        kgev_status r = ensure_work(ctx, p.total);
+        kgev_status r = ensure_work(ctx, need);
         if (r != KGEV_OK) return r;
         w = ctx->work;
     }
     hipStream_t st = (hipStream_t)stream;
+    double2* C2 = o.want_vectors ? (double2*)dC : nullptr;
     if (!o.use_graph || st == nullptr)
-        return solve_device(p, o, w, st, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC, ldc, d_status);
+        return solve_grouped(ctx, grp, o, w, st, (const double2*)dH, (const double2*)dS, ld, nk, dw, C2, ldc,
+                             d_status);
 
     GraphKey key;
     memset(&key, 0, sizeof(key));
     key.n = n; key.ld = ld; key.nk = nk; key.ldc = o.want_vectors ? ldc : 0;
     key.precision = o.precision; key.want_vectors = o.want_vectors; key.panel_nb = o.panel_nb;
-    key.refine_iters = o.refine_iters; key.s_tol = o.s_tol;
+    key.refine_iters = o.refine_iters; key.streams = o.streams; key.s_tol = o.s_tol;
     key.H = dH; key.S = dS; key.w = dw; key.C = o.want_vectors ? dC : nullptr; key.work = w; key.status = d_status;
     key.stream = stream;
     for (size_t q = 0; q < ctx->graphs.size(); ++q)
@@ -529,8 +598,8 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
             return KGEV_OK;
         }
     KCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    kgev_status r = solve_device(p, o, w, st, (const double2*)dH, (const double2*)dS, ld, dw, (double2*)dC, ldc,
-                                 d_status);
+    kgev_status r = solve_grouped(ctx, grp, o, w, st, (const double2*)dH, (const double2*)dS, ld, nk, dw, C2, ldc,
+                                  d_status);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &graph);
     if (r != KGEV_OK) {
@@ -719,6 +788,68 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
     KCHECK(cgemm<double>((hipStream_t)stream, transa, transb, m, n, k, mk<double>(alpha.re, alpha.im),
                          (const double2*)dA, lda, sA, (const double2*)dB, ldb, sB, mk<double>(beta.re, beta.im),
                          (double2*)dC, ldc, sC, batch, lower != 0));
+    return KGEV_OK;
+}
+
+kgev_status kgev_fermi_device(kgev_ctx* ctx, const double* dw, int64_t ldw, int64_t n, int64_t nk,
+                              const double* d_wk, double nelec, double kT, double g, double* d_occ, int64_t ldo,
+                              double* d_result, int32_t* d_status, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dw) return -2;
+    if (n < 1 || n > INT32_MAX) return -4;
+    if (ldw < n) return -3;
+    if (nk < 1 || nk > INT32_MAX) return -5;
+    if (!d_wk) return -6;
+    if (!(kT > 0.0) || !(kT < INFINITY)) return -8;
+    if (!(g > 0.0) || !(g < INFINITY)) return -9;
+    if (d_occ && ldo < n) return -11;
+    if (!d_result) return -12;
+    if (!d_status) return -13;
+    DevGuard gd(ctx->device);
+    KCHECK(fermi_level((hipStream_t)stream, dw, ldw, (int)n, (int)nk, d_wk, nelec, kT, g, d_occ, ldo, d_result,
+                       d_status));
+    return KGEV_OK;
+}
+
+size_t kgev_density_workspace_bytes(int64_t n, int64_t nk, int64_t nocc)
+{
+    if (n < 1 || nk < 1 || nocc < 0 || nocc > n) return 0;
+    return density_work_bytes(n, nk, nocc);
+}
+
+kgev_status kgev_density_device(kgev_ctx* ctx, const kgev_z* dC, int64_t ldc, int64_t n, int64_t nk, int64_t nocc,
+                                const double* dw, int64_t ldw, const double* d_occ, int64_t ldo, const double* d_wk,
+                                double g, kgev_z* d_rho, kgev_z* d_edm, int64_t ldr, void* dwork, size_t work_bytes,
+                                void* stream)
+{
+    if (!ctx) return -1;
+    if (!dC) return -2;
+    if (n < 1 || n > INT32_MAX) return -4;
+    if (ldc < n) return -3;
+    if (nk < 1 || nk > INT32_MAX) return -5;
+    if (nocc < 0 || nocc > n) return -6;
+    if (!dw) return -7;
+    if (ldw < n) return -8;
+    if (!d_occ) return -9;
+    if (ldo < n) return -10;
+    if (!d_wk) return -11;
+    if (!(g > 0.0) || !(g < INFINITY)) return -12;
+    if (!d_rho) return -13;
+    if (ldr < n) return -15;
+    if (n > 65535) return KGEV_EUNSUPPORTED;   // one grid row per column
+    const size_t need = density_work_bytes(n, nk, nocc);
+    DevGuard gd(ctx->device);
+    void* w = dwork;
+    if (!w) {
+        const kgev_status s = ensure_work(ctx, need);
+        if (s != KGEV_OK) return s;
+        w = ctx->work;
+    } else if (work_bytes < need) {
+        return -17;
+    }
+    KCHECK(density((hipStream_t)stream, (const double2*)dC, ldc, (int)n, (int)nk, (int)nocc, dw, ldw, d_occ, ldo,
+                   d_wk, g, (double2*)d_rho, (double2*)d_edm, ldr, w));
     return KGEV_OK;
 }
 

@@ -58,6 +58,15 @@ template <typename C> __device__ inline C cfmac(C a, C b, C acc)
 template <typename C> __device__ inline C cconj(C a) { a.y = -a.y; return a; }
 template <typename C, typename R> __device__ inline C cscale(C a, R s) { a.x *= s; a.y *= s; return a; }
 template <typename C> __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
+// Component-wise select.  A conditional expression on the vector type itself
+// can be lowered through scratch memory; selecting the components is not.
+template <typename C> __device__ inline C csel(bool c, C a, C b)
+{
+    C r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // wave reductions (64 lanes)

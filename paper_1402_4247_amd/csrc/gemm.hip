@@ -136,17 +136,20 @@ __device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const 
 }
 
 // BM x BN workgroup tile, four waves in a 2 x 2 arrangement, each owning a
-// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  Two LDS stages: while stage
-// s is multiplied, the next K step is fetched into registers and then stored
-// into stage s^1, so one barrier per K step suffices.
-template <typename R, int BM, int BN, bool G3, int TA, int TB>
-__global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  While one K step is
+// multiplied out of LDS, the next is fetched into registers.  NST = 2: two
+// LDS stages, the registers go to the other stage, one barrier per K step.
+// NST = 1: one stage (half the LDS, so twice the workgroups per CU), the
+// registers are stored after a barrier that ends the reads, two barriers
+// per K step.
+template <typename R, int BM, int BN, bool G3, int TA, int TB, int NST>
+__global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CGemmArgs<R> p)
 {
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
     constexpr int TM = BM / 32, TN = BN / 32;      // MFMA tiles per wave
-    __shared__ R sAr[2][GB_K][BM + 1], sAi[2][GB_K][BM + 1];
-    __shared__ R sBr[2][GB_K][BN + 1], sBi[2][GB_K][BN + 1];
+    __shared__ R sAr[NST][GB_K][BM + 1], sAi[NST][GB_K][BM + 1];
+    __shared__ R sBr[NST][GB_K][BN + 1], sBi[NST][GB_K][BN + 1];
 
     const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
     int64_t bz;
@@ -235,12 +238,14 @@ __global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
                 }
             }
         }
+        if constexpr (NST == 1) __syncthreads();
         if (nx < total_k) {
-            store_a<R, BM, TA>(sAr[cur ^ 1], sAi[cur ^ 1], tid, ra, oka);
-            store_b<R, BN, TB>(sBr[cur ^ 1], sBi[cur ^ 1], tid, rb, okb);
+            const int nxt = NST == 2 ? (cur ^ 1) : 0;
+            store_a<R, BM, TA>(sAr[nxt], sAi[nxt], tid, ra, oka);
+            store_b<R, BN, TB>(sBr[nxt], sBi[nxt], tid, rb, okb);
         }
         __syncthreads();
-        cur ^= 1;
+        if constexpr (NST == 2) cur ^= 1;
     }
 
     cx<R>* C = p.C + bz * p.sC;
@@ -268,26 +273,26 @@ __global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
             }
 }
 
-template <typename R, int BM, int BN, bool G3, int TA, int TB>
+template <typename R, int BM, int BN, bool G3, int TA, int TB, int NST>
 hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st)
 {
     p.tiles_m = (int)((p.m + BM - 1) / BM);
     p.tiles_n = (int)((p.n + BN - 1) / BN);
     const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
-    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN, G3, TA, TB>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
+    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN, G3, TA, TB, NST>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
     return hipGetLastError();
 }
 
 // the operand forms are compile-time so that the tile loads are straight-line
-template <typename R, bool G3>
+template <typename R, bool G3, int NST>
 hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st)
 {
     const int f = p.ta[0] * 2 + p.tb[0];
     switch (f) {
-    case 0: return launch_tiles<R, 64, 64, G3, 0, 0>(p, st);
-    case 1: return launch_tiles<R, 64, 64, G3, 0, 1>(p, st);
-    case 2: return launch_tiles<R, 64, 64, G3, 1, 0>(p, st);
-    default: return launch_tiles<R, 64, 64, G3, 1, 1>(p, st);
+    case 0: return launch_tiles<R, 64, 64, G3, 0, 0, NST>(p, st);
+    case 1: return launch_tiles<R, 64, 64, G3, 0, 1, NST>(p, st);
+    case 2: return launch_tiles<R, 64, 64, G3, 1, 0, NST>(p, st);
+    default: return launch_tiles<R, 64, 64, G3, 1, 1, NST>(p, st);
     }
 }
 
@@ -310,9 +315,17 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
         const char* v = getenv("KGEV_GEMM_3M");
         return v ? atoi(v) : 1;
     }();
+    static const int stages = [] {
+        const char* v = getenv("KGEV_GEMM_STAGES");
+        return v ? atoi(v) : 2;
+    }();
     p.remap = remap;
     prof_before(PH_GEMM, st);
-    hipError_t e = g3 ? launch_forms<R, true>(p, st) : launch_forms<R, false>(p, st);
+    hipError_t e;
+    if (stages == 1)
+        e = g3 ? launch_forms<R, true, 1>(p, st) : launch_forms<R, false, 1>(p, st);
+    else
+        e = g3 ? launch_forms<R, true, 2>(p, st) : launch_forms<R, false, 2>(p, st);
     prof_after(PH_GEMM, st, 0.0, flops);
     return e;
 }

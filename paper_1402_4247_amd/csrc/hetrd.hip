@@ -2,25 +2,33 @@
 // (lower storage): Section III, Procedures 1-6 of Eigen_HH, arXiv:1402.4247,
 // reorganised in panels of nb columns.
 //
-// Per column i of a panel starting at p (j = i - p, o = i + 1):
-//   zhemv    : one chunk of the Hermitian product z = A22 u (Procedure 4) from
+// Per column i of a panel starting at p (j = i - p, o = i + 1), two kernels:
+//   zhemv  : one chunk of the Hermitian product z = A22 u (Procedure 4) from
 //       the lower triangle only, with u the column below the sub-diagonal as
-//       it stands (u_o = 0, u_r = A(r, i)): it needs nothing derived in this
-//       step, so the workgroups only stream their tiles;
-//   reduce   : derives the reflector (Procedure 2, stable sign, real beta)
-//       from the partial norms, v = (1, scale * A(o+1:n, i)), stores v, and
-//       forms y = tau (A22(:, o) + scale z - V (W^H v) - W (V^H v)), where
-//       A22 v = A22(:, o) + scale A22 u by linearity;
-//   finalize : w = y - (tau/2)(y^H v) v (Procedure 5), stored as column j of
-//       W; then the next column of the panel is brought up to date,
+//       it stands (u_o = 0, u_r = A(r, i)), plus the chunk's share of
+//       q = Re(u^H z).  It needs nothing derived in this step, so the
+//       workgroups only stream their tiles.
+//   update : every workgroup derives the reflector (Procedure 2, stable sign,
+//       real beta) from the partial norms, v = (1, scale * A(o+1:n, i)), and
+//       forms for its rows y = tau (A22(:, o) + scale z - V (W^H v) - W (V^H v))
+//       (A22 v = A22(:, o) + scale A22 u by linearity) and
+//       w = y - (tau/2)(y^H v) v (Procedure 5).  y^H v needs no reduction over
+//       y: with h = A22(:, o), v^H A22 v = h_o + 2 Re(scale z_o) + |scale|^2 q
+//       and y^H v = conj(tau) (v^H A22 v - 2 Re((V^H v)^H (W^H v))), so
+//       alpha2 = -(tau/2) y^H v = -|tau|^2 / 2 (...) is real and every
+//       workgroup computes it, and row o of w, from the same partials.
+//       Then the next column of the panel is brought up to date,
 //       A(o:n, o) -= V(o:n, 0:j) conj(W(o, 0:j))^T + W(o:n, 0:j) conj(V(o, 0:j))^T,
 //       and its squared norm below the sub-diagonal and its products with
 //       the panel columns (the pieces of W^H v and V^H v for the next
-//       reflector) are reduced in per-block partials.
+//       reflector, taken on the unscaled column) are reduced in per-block
+//       partials.
 // After the panel the trailing matrix takes the rank-2nb update
 // A22 -= V W^H + W V^H (Procedure 6, on MFMA).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible run to run.
+#include <stdlib.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -39,8 +47,8 @@ template <typename R>
 __device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& tau, cx<R>& scale, R& beta)
 {
     const int n = ws.n;
-    const R* pn = ws.pnorm + b * ws.s_pnorm;
     const int np = (n - i + RB - 1) / RB;
+    const R* pn = ws.pnorm + b * ws.s_pnorm + (i & 1) * ((n + RB - 1) / RB);
     R sig2 = 0;
     for (int q = 0; q < np; ++q) sig2 += pn[q];
     const cx<R> alpha = ws.A[b * ws.sA + (int64_t)(i + 1) + (int64_t)i * ws.lda];
@@ -67,8 +75,8 @@ __device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV],
 {
 #pragma unroll
     for (int q = 0; q < HALF; ++q) {
-        const cx<R> send = up ? t[q] : t[q + HALF];
-        const cx<R> keep = up ? t[q + HALF] : t[q];
+        const cx<R> send = csel(up, t[q], t[q + HALF]);
+        const cx<R> keep = csel(up, t[q + HALF], t[q]);
         cx<R> rcv;
         rcv.x = __shfl_xor(send.x, MASK, WAVE);
         rcv.y = __shfl_xor(send.y, MASK, WAVE);
@@ -114,7 +122,7 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
         if (r >= c + 2) acc = a.x * a.x + a.y * a.y;
     }
     acc = wave_sum(acc);
-    if (threadIdx.x == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = acc;
+    if (threadIdx.x == 0) ws.pnorm[b * ws.s_pnorm + (c & 1) * ((ws.n + RB - 1) / RB) + blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -123,8 +131,8 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // direct part z_R += A_RC u_C comes out complete per row, the transposed part
 // z_C += A_RC^H u_R per column after a transposing wave reduction, and the
 // four waves' column sums are added once.
-template <typename R>
-__global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
+template <typename R, int MINW>
+__global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
 {
     __shared__ cx<R> svC[ZT];
     __shared__ cx<R> sT[ZCH][ZT];
@@ -155,13 +163,16 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
     // Loads are unconditional from a clamped (in-bounds) address and the value
     // is masked afterwards, so no branch guards them; each group of 8 columns
     // is requested one step ahead of its use.
-    const cx<R>* Arow = A + (row_ok ? gr : (int64_t)n - 1);
+    // the column base is wave-uniform (scalar registers); the row is one
+    // 32-bit offset per lane shared by every load of the tile
+    const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     auto load_group = [&](int g, cx<R> (&a)[8]) {
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
             const int64_t gc = gcb + g * 8 + cc;
-            a[cc] = Arow[(gc < n ? gc : (int64_t)n - 1) * lda];
+            const cx<R>* col = A + (gc < n ? gc : (int64_t)n - 1) * lda;
+            a[cc] = col[rowc];
         }
     };
     cx<R> a[8], an[8];
@@ -169,12 +180,14 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
     if (tid < ZT) {
         const int64_t gc = gcb + tid;
         const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
-        svC[tid] = (gc > o && gc < n) ? u : czero<cx<R>>();
+        svC[tid] = csel(gc > o && gc < n, u, czero<cx<R>>());
     }
     cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
     if (!(row_ok && gr > o)) uR = czero<cx<R>>();
     __syncthreads();
 
+    __shared__ R sq[ZCH];
+    R qd = 0;
     if (have_tile) {
         const bool diag_tile = (Rb == C);
         cx<R> yd = czero<cx<R>>();
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
                 x.y = (ok && !diag) ? a[cc].y : (R)0;
                 yd = cfma(x, svC[g * 8 + cc], yd);
                 // the diagonal entry is counted once (direct part only)
-                a[cc] = diag ? czero<cx<R>>() : cmulc(x, uR);
+                a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
             }
             const cx<R> r = transpose_sum8<R>(a, lane);
             if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
@@ -200,28 +213,63 @@ __global__ __launch_bounds__(256) void hetrd_zhemv(HetrdWs<R> ws, int i)
             for (int cc = 0; cc < 8; ++cc) a[cc] = an[cc];
         }
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
+        qd = uR.x * yd.x + uR.y * yd.y;
     } else {
         sT[w][lane] = czero<cx<R>>();
     }
+    qd = wave_sum(qd);
+    if (lane == 0) sq[w] = qd;
     __syncthreads();
     if (tid < ZT) {
         const cx<R> s = cadd(cadd(sT[0][tid], sT[1][tid]), cadd(sT[2][tid], sT[3][tid]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
+        R qt = svC[tid].x * s.x + svC[tid].y * s.y;
+        qt = wave_sum(qt);
+        if (tid == 0) ws.qpart[b * ws.s_qpart + blockIdx.x] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Reflector of column i, v stored, and
-// y = tau (A22(:, o) + scale z - V (W^H v) - W (V^H v)) for one 64-row block.
-// The panel dots come as partials of the unscaled column, W^H v =
-// conj(W(o, :)) + scale * sum_r conj(W(r, :)) A(r, i) over r > o (likewise
-// V^H v).  The four waves split every sum (wave w takes the terms with
-// index = w mod 4).
+// z at one row: the partial sums over the block columns and chunks that
+// touch it, split over the four waves (wave w takes the terms with index =
+// w mod 4) and combined as (w0 + w1) + (w2 + w3).  Every workgroup that
+// needs row o's value uses this same sequence, so it is bitwise equal to the
+// value the owner of row o computes.
 template <typename R>
-__global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
+__device__ inline cx<R> zpart(const HetrdWs<R>& ws, int64_t b, int Rb, int NB, int r, int w)
+{
+    cx<R> y = czero<cx<R>>();
+    const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + r;
+    for (int C = w; C <= Rb; C += 4) y = cadd(y, yp[(int64_t)C * ZT]);
+    const int nc = nchunks(NB, Rb);
+    const cx<R>* yq = ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT + r;
+    for (int ch = w; ch < nc; ch += 4) y = cadd(y, yq[(int64_t)ch * ZT]);
+    return y;
+}
+
+template <typename C>
+__device__ inline C sum4(const C (&s)[4][64], int l)
+{
+    return cadd(cadd(s[0][l], s[1][l]), cadd(s[2][l], s[3][l]));
+}
+
+// Column i: reflector, v and w for one 64-row block (rows o + 64 Rb ...),
+// then (update_next) column o brought up to date for these rows with its
+// partial norm and partial panel dots.  Every global value the block needs
+// is requested in one first phase, including this thread's rows of the panel
+// columns V(:, p + jj), W(:, jj) (the four waves take jj = w, w+4, ...; panels
+// up to 32 wide are held in registers, wider ones reload the rest), which
+// then serve the corrections, the column update and the panel dots.
+template <typename R>
+__global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p, int update_next)
 {
     __shared__ cx<R> s1[4][64], s2[4][64], sy[4][64];
-    __shared__ cx<R> swv[64], svv[64];
+    __shared__ cx<R> swv[64], svv[64];        // W^H v, V^H v (zero beyond j)
+    __shared__ cx<R> sWo[64], sVo[64];        // row o of W(:, 0:j) and V(:, p:p+j) (zero beyond j)
+    __shared__ cx<R> szo[4];
+    __shared__ R sqq[4];
+    __shared__ cx<R> sv[64], sw[64];          // this block's v and w
+    __shared__ cx<R> sc[4];                   // w_o, (alpha2, 0)
     const int64_t b = blockIdx.y;
     const int n = ws.n, o = i + 1, m = n - o;
     const int NB = (m + ZT - 1) / ZT;
@@ -229,163 +277,231 @@ __global__ __launch_bounds__(256) void hetrd_reduce(HetrdWs<R> ws, int i, int p)
     const int j = i - p;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
+    const int64_t grc = gr < n ? gr : (int64_t)n - 1;     // clamped row for unconditional loads
     const cx<R>* A = ws.A + b * ws.sA;
     cx<R>* V = ws.V + b * ws.sV;
-    const cx<R>* W = ws.W + b * ws.sW;
-    // loads that do not depend on the reflector go first
-    cx<R> ai = czero<cx<R>>(), h = czero<cx<R>>();
-    if (w == 0 && gr < n) {
-        ai = A[gr + (int64_t)i * ws.lda];
-        h = A[gr + (int64_t)o * ws.lda];
-        if (gr == o) h.y = 0;
+    cx<R>* W = ws.W + b * ws.sW;
+    const int npn = (n + RB - 1) / RB;
+    const cx<R> zero = czero<cx<R>>();
+
+    // ---- phase 1: every load that depends on nothing computed here
+    cx<R> pv[8], pw[8];       // V(gr, p + jj), W(gr, jj) for jj = w + 4q < j, else 0
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jj = w + 4 * q;
+        const int jc = jj < j ? jj : 0;
+        pv[q] = V[grc + (int64_t)(p + jc) * n];
+        pw[q] = W[grc + (int64_t)jc * n];
     }
-    // panel dot partials (lane = panel column)
+    const cx<R> ai = A[grc + (int64_t)i * ws.lda];
+    cx<R> h = A[grc + (int64_t)o * ws.lda];
+    if (w == 1) {
+        const int lc = lane < j ? lane : 0;
+        const cx<R> wv = W[(int64_t)o + (int64_t)lc * n];
+        const cx<R> vv = V[(int64_t)o + (int64_t)(p + lc) * n];
+        sWo[lane] = csel(lane < j, wv, zero);
+        sVo[lane] = csel(lane < j, vv, zero);
+    }
     {
-        cx<R> a1 = czero<cx<R>>(), a2 = czero<cx<R>>();
+        // unscaled panel-dot partials of column i (lane = panel column)
+        cx<R> a1 = zero, a2 = zero;
         if (lane < j) {
             const int np = (n - i + RB - 1) / RB;
+            const int64_t base = b * ws.s_pdot + (int64_t)(i & 1) * ws.NBmax * ws.nb + lane;
+#pragma unroll 4
             for (int q = w; q < np; q += 4) {
-                a1 = cadd(a1, ws.pvw[b * ws.s_pdot + (int64_t)q * ws.nb + lane]);
-                a2 = cadd(a2, ws.pvv[b * ws.s_pdot + (int64_t)q * ws.nb + lane]);
+                a1 = cadd(a1, ws.pvw[base + (int64_t)q * ws.nb]);
+                a2 = cadd(a2, ws.pvv[base + (int64_t)q * ws.nb]);
             }
         }
         s1[w][lane] = a1;
         s2[w][lane] = a2;
     }
-    // partial sums of A22 u for these rows
+    sy[w][lane] = zpart(ws, b, Rb, NB, lane, w);
+    if (lane == 0) szo[w] = zpart(ws, b, 0, NB, 0, w);
     {
-        cx<R> y = czero<cx<R>>();
-        const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + lane;
-        for (int C = w; C <= Rb; C += 4) y = cadd(y, yp[(int64_t)C * ZT]);
-        const int nc = nchunks(NB, Rb);
-        const cx<R>* yq = ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT + lane;
-        for (int ch = w; ch < nc; ch += 4) y = cadd(y, yq[(int64_t)ch * ZT]);
-        sy[w][lane] = y;
+        // q = Re(u^H A22 u) from the chunk shares
+        int nch = 0;
+        for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
+        R qa = 0;
+        for (int c = tid; c < nch; c += 256) qa += ws.qpart[b * ws.s_qpart + c];
+        qa = wave_sum(qa);
+        if (lane == 0) sqq[w] = qa;
     }
     cx<R> tau, scale;
     R beta;
     reflector(ws, b, i, tau, scale, beta);
+    const R hoo = A[(int64_t)o + (int64_t)o * ws.lda].x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (!(w + 4 * q < j)) {
+            pv[q] = zero;
+            pw[q] = zero;
+        }
+    if (gr == o) h.y = 0;
     __syncthreads();
+
+    // ---- panel dots W^H v = conj(W(o, :)) + scale * partials (likewise V)
     if (tid < 64) {
-        const cx<R> d1 = cadd(cadd(s1[0][tid], s1[1][tid]), cadd(s1[2][tid], s1[3][tid]));
-        const cx<R> d2 = cadd(cadd(s2[0][tid], s2[1][tid]), cadd(s2[2][tid], s2[3][tid]));
         if (tid < j) {
-            swv[tid] = cfma(scale, d1, cconj(W[(int64_t)o + (int64_t)tid * n]));
-            svv[tid] = cfma(scale, d2, cconj(V[(int64_t)o + (int64_t)(p + tid) * n]));
+            swv[tid] = cfma(scale, sum4(s1, tid), cconj(sWo[tid]));
+            svv[tid] = cfma(scale, sum4(s2, tid), cconj(sVo[tid]));
+        } else {
+            swv[tid] = zero;
+            svv[tid] = zero;
         }
     }
     __syncthreads();
-    cx<R> corr = czero<cx<R>>();
-    if (gr < n) {
-        for (int jj = w; jj < j; jj += 4) {
-            corr = cfma(V[gr + (int64_t)(p + jj) * n], swv[jj], corr);
-            corr = cfma(W[gr + (int64_t)jj * n], svv[jj], corr);
-        }
-    }
-    s1[w][lane] = corr;     // s1 is free again (read before the last barrier)
-    __syncthreads();
+
+    // ---- row o: y_o, alpha2 and w_o, identical in every workgroup (wave 0,
+    // lane = panel column, fixed-order wave sums)
     if (w == 0) {
-        cx<R> part = czero<cx<R>>();
-        if (gr < n) {
-            const cx<R> z = cadd(cadd(sy[0][lane], sy[1][lane]), cadd(sy[2][lane], sy[3][lane]));
-            const cx<R> c = cadd(cadd(s1[0][lane], s1[1][lane]), cadd(s1[2][lane], s1[3][lane]));
-            const cx<R> v = (gr == o) ? mk<R>(1, 0) : cmul(ai, scale);
-            V[gr + (int64_t)i * n] = v;
-            const cx<R> y = cmul(tau, csub(cfma(scale, z, h), c));
-            ws.ybuf[b * n + gr] = y;
-            part = cmulc(y, v);
+        cx<R> co = cfma(sVo[lane], swv[lane], cmul(sWo[lane], svv[lane]));
+        R cross = svv[lane].x * swv[lane].x + svv[lane].y * swv[lane].y;   // Re(conj(V^H v) W^H v)
+        co.x = wave_sum(co.x);
+        co.y = wave_sum(co.y);
+        cross = wave_sum(cross);
+        if (lane == 0) {
+            const cx<R> zo = cadd(cadd(szo[0], szo[1]), cadd(szo[2], szo[3]));
+            const R q = (sqq[0] + sqq[1]) + (sqq[2] + sqq[3]);
+            const cx<R> sz = cmul(scale, zo);
+            const R vav = hoo + (R)2 * sz.x + (scale.x * scale.x + scale.y * scale.y) * q;
+            const R a2 = (R)-0.5 * (tau.x * tau.x + tau.y * tau.y) * (vav - (R)2 * cross);
+            const cx<R> yo = cmul(tau, csub(cadd(mk<R>(hoo, 0), sz), co));
+            sc[0] = cadd(yo, mk<R>(a2, 0));
+            sc[1] = mk<R>(a2, 0);
         }
-        part.x = wave_sum(part.x);
-        part.y = wave_sum(part.y);
-        if (lane == 0) ws.pyv[b * ws.NBmax + Rb] = part;
+    }
+    // ---- this block's corrections V (W^H v) + W (V^H v)
+    cx<R> corr = zero;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jj = w + 4 * q;
+        corr = cfma(pv[q], swv[jj], corr);
+        corr = cfma(pw[q], svv[jj], corr);
+    }
+    for (int jj = w + 32; jj < j; jj += 4) {
+        corr = cfma(V[grc + (int64_t)(p + jj) * n], swv[jj], corr);
+        corr = cfma(W[grc + (int64_t)jj * n], svv[jj], corr);
+    }
+    s1[w][lane] = corr;
+    __syncthreads();
+    const cx<R> wo = sc[0];
+    const R a2 = sc[1].x;
+    if (w == 0) {
+        cx<R> v = zero, wv = zero;
+        if (gr < n) {
+            v = csel(gr == o, mk<R>(1, 0), cmul(ai, scale));
+            if (gr == o) {
+                wv = wo;
+            } else {
+                const cx<R> z = sum4(sy, lane);
+                const cx<R> y = cmul(tau, csub(cfma(scale, z, h), sum4(s1, lane)));
+                wv = cfma(mk<R>(a2, 0), v, y);
+            }
+            V[gr + (int64_t)i * n] = v;
+            W[gr + (int64_t)j * n] = wv;
+        }
+        sv[lane] = v;
+        sw[lane] = wv;
         if (Rb == 0 && lane == 0) {
             ws.e[b * n + i] = beta;
             ws.tau[b * n + i] = tau;
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// w = y + alpha2 v (alpha2 = -(tau/2) y^H v), stored as W(:, j); then, when
-// the panel continues, column i+1 is brought up to date (the four waves split
-// the panel columns), and its partial norm and partial panel dots are reduced.
-template <typename R>
-__global__ __launch_bounds__(256) void hetrd_finalize(HetrdWs<R> ws, int i, int p, int update_next)
-{
-    __shared__ cx<R> sWr[64], sVr[64];
-    __shared__ cx<R> sp[4][64];
-    const int64_t b = blockIdx.y;
-    const int n = ws.n, o = i + 1, m = n - o;
-    const int NB = (m + ZT - 1) / ZT;
-    const int j = i - p;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    cx<R> sum = czero<cx<R>>();
-    for (int q = 0; q < NB; ++q) sum = cadd(sum, ws.pyv[b * ws.NBmax + q]);
-    const cx<R> tau = ws.tau[b * n + i];
-    const cx<R> a2 = cscale(cmul(tau, sum), (R)-0.5);
-
-    const int64_t gr = (int64_t)o + (int64_t)blockIdx.x * RB + lane;
-    cx<R>* V = ws.V + b * ws.sV;
-    cx<R>* W = ws.W + b * ws.sW;
-    cx<R> wv = czero<cx<R>>();
-    if (gr < n) {
-        wv = cfma(a2, V[gr + (int64_t)i * n], ws.ybuf[b * n + gr]);
-        if (w == 0) W[gr + (int64_t)j * n] = wv;
-    }
     if (!update_next) return;
-    // row o of V and W for the update of column o
-    if (tid <= j) {
-        sVr[tid] = V[(int64_t)o + (int64_t)(p + tid) * n];
-        sWr[tid] = (tid < j) ? W[(int64_t)o + (int64_t)tid * n] : cadd(ws.ybuf[b * n + o], a2);
-    }
     __syncthreads();
-    cx<R> acc = czero<cx<R>>();
-    if (gr < n) {
-        for (int jj = w; jj <= j; jj += 4) {
-            const cx<R> wr = (jj < j) ? W[gr + (int64_t)jj * n] : wv;
-            acc = cfma(V[gr + (int64_t)(p + jj) * n], cconj(sWr[jj]), acc);
-            acc = cfma(wr, cconj(sVr[jj]), acc);
+
+    // ---- column o -= V(:, 0:j) conj(W(o, 0:j))^T + W(:, 0:j) conj(V(o, 0:j))^T
+    // (column j of the panel is this block's v, w, with row o = (1, w_o))
+    const cx<R> myv = sv[lane], myw = sw[lane];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (w + 4 * q == j) {
+            pv[q] = myv;
+            pw[q] = myw;
         }
+    cx<R> acc = zero;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jj = w + 4 * q;
+        const cx<R> wo_j = csel(jj < j, sWo[jj], csel(jj == j, wo, zero));
+        const cx<R> vo_j = csel(jj < j, sVo[jj], csel(jj == j, mk<R>(1, 0), zero));
+        acc = cfma(pv[q], cconj(wo_j), acc);
+        acc = cfma(pw[q], cconj(vo_j), acc);
     }
-    sp[w][lane] = acc;
+    for (int jj = w + 32; jj <= j; jj += 4) {
+        const bool old = jj < j;
+        const int jc = old ? jj : 0;
+        const cx<R> vr = csel(old, V[grc + (int64_t)(p + jc) * n], myv);
+        const cx<R> wr = csel(old, W[grc + (int64_t)jc * n], myw);
+        acc = cfma(vr, cconj(csel(old, sWo[jj], wo)), acc);
+        acc = cfma(wr, cconj(csel(old, sVo[jj], mk<R>(1, 0))), acc);
+    }
+    s2[w][lane] = acc;
     __syncthreads();
     if (w == 0) {
         R nrm = 0;
-        cx<R> an = czero<cx<R>>();
+        cx<R> an = zero;
         if (gr < n) {
-            cx<R>* A = ws.A + b * ws.sA;
-            const cx<R> c = cadd(cadd(sp[0][lane], sp[1][lane]), cadd(sp[2][lane], sp[3][lane]));
-            cx<R> a = csub(A[gr + (int64_t)o * ws.lda], c);
+            const cx<R> a = csub(h, sum4(s2, lane));
             if (gr == o) {
-                a.y = 0;
+                // the diagonal goes to d only: A(o, o) is read as it stood by
+                // every workgroup of this launch and is not needed afterwards
                 ws.d[b * n + o] = a.x;
+            } else {
+                ws.A[b * ws.sA + gr + (int64_t)o * ws.lda] = a;
             }
-            A[gr + (int64_t)o * ws.lda] = a;
             if (gr >= o + 2) {
                 nrm = a.x * a.x + a.y * a.y;
                 an = a;
             }
         }
         nrm = wave_sum(nrm);
-        if (lane == 0) ws.pnorm[b * ws.s_pnorm + blockIdx.x] = nrm;
-        sp[0][lane] = an;
+        if (lane == 0) ws.pnorm[b * ws.s_pnorm + (o & 1) * npn + Rb] = nrm;
+        s1[0][lane] = an;
     }
     __syncthreads();
     // products of the panel columns 0..j with the updated column below its
-    // sub-diagonal: this block's share of the next reflector's panel dots
-    const cx<R> an = sp[0][lane];
-    for (int jj = w; jj <= j; jj += 4) {
-        cx<R> t1 = czero<cx<R>>(), t2 = czero<cx<R>>();
-        if (gr < n) {
-            const cx<R> wr = (jj < j) ? W[gr + (int64_t)jj * n] : wv;
-            t1 = cmulc(wr, an);
-            t2 = cmulc(V[gr + (int64_t)(p + jj) * n], an);
+    // sub-diagonal: this block's share of the next reflector's panel dots,
+    // eight columns per wave per transposing reduction
+    const cx<R> an = s1[0][lane];
+    const int64_t base = b * ws.s_pdot + (int64_t)(o & 1) * ws.NBmax * ws.nb + (int64_t)Rb * ws.nb;
+    {
+        cx<R> t1[8], t2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            t1[q] = cmulc(pw[q], an);
+            t2[q] = cmulc(pv[q], an);
         }
-        t1.x = wave_sum(t1.x); t1.y = wave_sum(t1.y);
-        t2.x = wave_sum(t2.x); t2.y = wave_sum(t2.y);
-        if (lane == 0) {
-            ws.pvw[b * ws.s_pdot + (int64_t)blockIdx.x * ws.nb + jj] = t1;
-            ws.pvv[b * ws.s_pdot + (int64_t)blockIdx.x * ws.nb + jj] = t2;
+        const cx<R> r1 = transpose_sum8<R>(t1, lane);
+        const cx<R> r2 = transpose_sum8<R>(t2, lane);
+        const int jj = w + 4 * (lane >> 3);
+        if ((lane & 7) == 0 && jj <= j) {
+            ws.pvw[base + jj] = r1;
+            ws.pvv[base + jj] = r2;
+        }
+    }
+    if (j >= 32) {
+        cx<R> t1[8], t2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int jj = w + 32 + 4 * q;
+            const bool old = jj < j;
+            const int jc = old ? jj : 0;
+            cx<R> vr = V[grc + (int64_t)(p + jc) * n];
+            cx<R> wr = W[grc + (int64_t)jc * n];
+            vr = csel(old, vr, csel(jj == j, myv, zero));
+            wr = csel(old, wr, csel(jj == j, myw, zero));
+            t1[q] = cmulc(wr, an);
+            t2[q] = cmulc(vr, an);
+        }
+        const cx<R> r1 = transpose_sum8<R>(t1, lane);
+        const cx<R> r2 = transpose_sum8<R>(t2, lane);
+        const int jj = w + 32 + 4 * (lane >> 3);
+        if ((lane & 7) == 0 && jj <= j) {
+            ws.pvw[base + jj] = r1;
+            ws.pvv[base + jj] = r2;
         }
     }
 }
@@ -399,6 +515,12 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
 {
     const int n = ws.n, nb = ws.nb;
     if (n < 1 || nk < 1) return hipSuccess;
+    // KGEV_HEMV_OCC=3 selects the product kernel compiled for three
+    // workgroups per CU (tuning experiments)
+    static const bool occ3 = [] {
+        const char* v = getenv("KGEV_HEMV_OCC");
+        return v && atoi(v) == 3;
+    }();
     for (int p = 0; p <= n - 1; p += nb) {
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
         hipLaunchKernelGGL(hetrd_colstart<R>, g1, dim3(RB), 0, st, ws, p);
@@ -409,12 +531,13 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
             prof_before(PH_HEMV, st);
-            hipLaunchKernelGGL(hetrd_zhemv<R>, dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
+            if (occ3)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3>), dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
+            else
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1>), dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
-            hipLaunchKernelGGL(hetrd_reduce<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
-            dim3 g4((unsigned)((n - o + RB - 1) / RB), (unsigned)nk);
-            hipLaunchKernelGGL(hetrd_finalize<R>, g4, dim3(256), 0, st, ws, i, p, upd);
+            hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);
         }
         if (p + nb <= n - 1) {
             const int t0 = p + nb;

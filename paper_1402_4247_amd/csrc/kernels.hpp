@@ -38,12 +38,14 @@ struct HetrdWs {
     cx<R>* V; int64_t sV;      // reflectors, n x n, ld n (zero outside the reflector rows)
     cx<R>* W; int64_t sW;      // panel W, n x nb, ld n
     R* d; R* e; cx<R>* tau;    // stride n per problem
-    R* pnorm; int64_t s_pnorm; // partial squared norms, hetrd_pn(n)
+    // The per-column partials below come in two buffers selected by the
+    // parity of the column they describe: the kernel that consumes column
+    // i's partials writes column i+1's in the same launch.
+    R* pnorm; int64_t s_pnorm; // partial squared norms, 2 x hetrd_pn(n)
     cx<R>* ypart; int64_t s_ypart;   // NBmax x NBmax x 64
     cx<R>* ypartT; int64_t s_ypartT; // NBmax x CHmax x 64
-    cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;  // NBmax x nb
-    cx<R>* pyv;                // NBmax per problem
-    cx<R>* ybuf;               // n per problem
+    cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;  // 2 x NBmax x nb
+    R* qpart; int64_t s_qpart;       // NBmax x CHmax: per-chunk shares of Re(u^H A22 u)
 };
 
 inline int hetrd_nbmax(int64_t n) { return (int)((n - 1 + 63) / 64) > 0 ? (int)((n - 1 + 63) / 64) : 1; }
@@ -130,5 +132,14 @@ template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
                  int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk);
 int64_t unmtr_work_elems(int64_t n, int kb);   // complex elements per problem
+
+// ---------------------------------------------------------------------------
+// Band_DFT_Col Parts 5 and 6 (band.hip)
+hipError_t fermi_level(hipStream_t st, const double* w, int64_t ldw, int n, int nk, const double* wk, double nelec,
+                       double kT, double g, double* occ, int64_t ldo, double* out, int32_t* status);
+size_t density_work_bytes(int64_t n, int64_t nk, int64_t nocc);
+hipError_t density(hipStream_t st, const double2* C, int64_t ldc, int n, int nk, int nocc, const double* w,
+                   int64_t ldw, const double* occ, int64_t ldo, const double* wk, double g, double2* rho,
+                   double2* edm, int64_t ldr, void* work);
 
 }  // namespace kgev

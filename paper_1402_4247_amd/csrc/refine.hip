@@ -9,8 +9,10 @@
 //   E_ij = (S_ij + lambda_j R_ij) / (lambda_j - lambda_i)   (|lambda_i - lambda_j| > delta)
 //   E_ij = R_ij / 2                                          (otherwise, and i == j),
 //   Y <- Y (I + E).
-// The products are the library's MFMA products; these kernels form lambda,
-// the norms behind delta and I + E.  Every sum is taken in a fixed order.
+// The products are the library's MFMA products; G and S are Hermitian, so
+// only their lower triangles are formed (G_ij, S_ij for i < j are read as
+// conj(G_ji), conj(S_ji)).  These kernels form lambda, the norms behind delta
+// and I + E.  Every sum is taken in a fixed order.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,8 +20,9 @@ namespace kgev {
 
 namespace {
 
-// one workgroup per column j: lambda_j and the column's squared norms of
-// S - diag(lambda) and R
+// one workgroup per column j: lambda_j and the column's share of the squared
+// Frobenius norms of S - diag(lambda) and R = I - G, from the lower
+// triangles (each strictly-lower entry stands for itself and its mirror)
 __global__ __launch_bounds__(256) void k_refine_stats(int64_t n, const double2* G, const double2* S, int64_t sNN,
                                                       double* lam, double* pS, double* pR)
 {
@@ -29,11 +32,18 @@ __global__ __launch_bounds__(256) void k_refine_stats(int64_t n, const double2* 
     const double2* sc = S + b * sNN + j * n;
     const double lj = sc[j].x / g[j].x;
     double as = 0.0, ar = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
+    for (int64_t i = j + threadIdx.x; i < n; i += 256) {
         double2 sv = sc[i], gv = g[i];
-        if (i == j) { sv.x -= lj; gv.x -= 1.0; }
-        as = fma(sv.x, sv.x, fma(sv.y, sv.y, as));
-        ar = fma(gv.x, gv.x, fma(gv.y, gv.y, ar));
+        double wgt = 2.0;
+        if (i == j) {
+            sv.x -= lj;
+            sv.y = 0.0;
+            gv.x -= 1.0;
+            gv.y = 0.0;
+            wgt = 1.0;
+        }
+        as = fma(wgt, fma(sv.x, sv.x, sv.y * sv.y), as);
+        ar = fma(wgt, fma(gv.x, gv.x, gv.y * gv.y), ar);
     }
     as = wave_sum(as);
     ar = wave_sum(ar);
@@ -72,27 +82,70 @@ __global__ __launch_bounds__(256) void k_refine_delta(int64_t n, const double* l
     }
 }
 
-// F = I + E, column-major n x n per problem
+// F = I + E, column-major n x n per problem, one 32 x 32 tile per
+// workgroup.  G and S hold lower triangles: a tile above the diagonal reads
+// the mirrored lower tile through LDS (coalesced) and conjugates it.
+constexpr int RT = 32;
 __global__ __launch_bounds__(256) void k_refine_E(int64_t n, const double2* G, const double2* S, int64_t sNN,
                                                   const double* lam, const double* delta, double2* F)
 {
-    const int64_t b = blockIdx.z, j = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int64_t q = b * sNN + j * n + i;
-    const double2 g = G[q];
-    const double2 r = mk<double>((i == j ? 1.0 : 0.0) - g.x, -g.y);   // R = I - G
-    const double li = lam[b * n + i], lj = lam[b * n + j];
-    double2 e;
-    if (i != j && fabs(li - lj) > delta[b]) {
-        const double2 s = S[q];
-        const double den = 1.0 / (lj - li);
-        e = mk<double>((s.x + lj * r.x) * den, (s.y + lj * r.y) * den);
-    } else {
-        e = mk<double>(0.5 * r.x, 0.5 * r.y);
+    __shared__ double2 tg[RT][RT + 1], ts[RT][RT + 1];
+    const int64_t b = blockIdx.z;
+    const int64_t i0 = (int64_t)blockIdx.x * RT, j0 = (int64_t)blockIdx.y * RT;
+    const bool upper = i0 < j0;        // tile strictly above the diagonal blocks
+    const int tx = threadIdx.x & (RT - 1), ty = threadIdx.x / RT;   // 32 x 8
+    const double2* g = G + b * sNN;
+    const double2* sm = S + b * sNN;
+    if (upper) {
+        // stage the mirrored tile (rows j0.., columns i0..) as stored
+        for (int c = ty; c < RT; c += 8) {
+            const int64_t r = j0 + tx, col = i0 + c;
+            double2 gv = mk<double>(0, 0), sv = mk<double>(0, 0);
+            if (r < n && col < n) {
+                gv = g[r + col * n];
+                sv = sm[r + col * n];
+            }
+            tg[c][tx] = gv;
+            ts[c][tx] = sv;
+        }
+        __syncthreads();
     }
-    if (i == j) e.x += 1.0;
-    F[q] = e;
+    const double dl = delta[b];
+    for (int c = ty; c < RT; c += 8) {
+        const int64_t i = i0 + tx, j = j0 + c;
+        if (i >= n || j >= n) continue;
+        double2 gv, sv;
+        if (upper) {
+            // G_ij = conj(G_ji), G_ji staged at [i - i0][j - j0]
+            gv = tg[tx][c];
+            sv = ts[tx][c];
+            gv.y = -gv.y;
+            sv.y = -sv.y;
+        } else if (i >= j) {
+            gv = g[i + j * n];
+            sv = sm[i + j * n];
+        } else {
+            // inside a diagonal tile, above the diagonal
+            gv = g[j + i * n];
+            sv = sm[j + i * n];
+            gv.y = -gv.y;
+            sv.y = -sv.y;
+        }
+        const double2 r = mk<double>((i == j ? 1.0 : 0.0) - gv.x, -gv.y);   // R = I - G
+        const double li = lam[b * n + i], lj = lam[b * n + j];
+        double2 e;
+        if (i != j && fabs(li - lj) > dl) {
+            const double den = 1.0 / (lj - li);
+            e = mk<double>((sv.x + lj * r.x) * den, (sv.y + lj * r.y) * den);
+        } else {
+            e = mk<double>(0.5 * r.x, 0.5 * r.y);
+        }
+        if (i == j) {
+            e.x += 1.0;
+            e.y = 0.0;
+        }
+        F[b * sNN + i + j * n] = e;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_f2d(const float* src, double* dst, int64_t count)
@@ -131,17 +184,17 @@ hipError_t refine(hipStream_t st, const RefineWs& ws, int64_t nk, int iters, dou
     double2* Yn = ws.Ynext;
     for (int it = 0; it < iters; ++it) {
         hipError_t e;
-        e = cgemm<double>(st, 'C', 'N', n, n, n, one, Y, n, nn, Y, n, nn, zero, ws.G, n, nn, nk, false);
+        e = cgemm<double>(st, 'C', 'N', n, n, n, one, Y, n, nn, Y, n, nn, zero, ws.G, n, nn, nk, true);
         if (e != hipSuccess) return e;
         e = cgemm<double>(st, 'N', 'N', n, n, n, one, ws.Af, n, nn, Y, n, nn, zero, ws.P, n, nn, nk, false);
         if (e != hipSuccess) return e;
-        e = cgemm<double>(st, 'C', 'N', n, n, n, one, Y, n, nn, ws.P, n, nn, zero, ws.S, n, nn, nk, false);
+        e = cgemm<double>(st, 'C', 'N', n, n, n, one, Y, n, nn, ws.P, n, nn, zero, ws.S, n, nn, nk, true);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_refine_stats, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, ws.G, ws.S, nn,
                            lam_out, ws.pS, ws.pR);
         hipLaunchKernelGGL(k_refine_delta, dim3((unsigned)nk), dim3(256), 0, st, n, lam_out, ws.pS, ws.pR, ws.delta);
-        hipLaunchKernelGGL(k_refine_E, dim3((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nk), dim3(256), 0, st,
-                           n, ws.G, ws.S, nn, lam_out, ws.delta, ws.F);
+        hipLaunchKernelGGL(k_refine_E, dim3((unsigned)((n + RT - 1) / RT), (unsigned)((n + RT - 1) / RT), (unsigned)nk),
+                           dim3(256), 0, st, n, ws.G, ws.S, nn, lam_out, ws.delta, ws.F);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = cgemm<double>(st, 'N', 'N', n, n, n, one, Y, n, nn, ws.F, n, nn, zero, Yn, n, nn, nk, false);

@@ -115,17 +115,20 @@ __global__ __launch_bounds__(64) void k_larft(int kb, const cx<R>* G, int64_t sG
                                               int c0, cx<R>* T, int64_t strT)
 {
     __shared__ cx<R> sT[KBMAX][KBMAX + 1];   // sT[col][row]
-    __shared__ cx<R> sg[KBMAX];
+    __shared__ cx<R> gl[KBMAX][KBMAX + 1];   // gl[col][row] = G(row, col), read once
+    __shared__ cx<R> tl[KBMAX];
     const int64_t b = blockIdx.x;
     const int r = threadIdx.x;
     const cx<R>* g = G + b * sG;
+    for (int j = 0; j < kb; ++j)
+        if (r < kb) gl[j][r] = g[r + (int64_t)j * kb];
+    if (r < kb) tl[r] = tau[b * stau + c0 + r];
+    __syncthreads();
     for (int j = 0; j < kb; ++j) {
-        if (r < j) sg[r] = g[r + (int64_t)j * kb];
-        __syncthreads();
-        const cx<R> tj = tau[b * stau + c0 + j];
+        const cx<R> tj = tl[j];
         if (r < j) {
             cx<R> acc = czero<cx<R>>();
-            for (int q = r; q < j; ++q) acc = cfma(sT[q][r], sg[q], acc);
+            for (int q = r; q < j; ++q) acc = cfma(sT[q][r], gl[j][q], acc);
             sT[j][r] = cscale(cmul(tj, acc), (R)-1);
         } else if (r == j) {
             sT[j][r] = tj;

@@ -47,14 +47,16 @@ class Result(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
                 ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("s_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("s_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
-           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune"]
+           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
+           "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 
 
@@ -91,6 +93,13 @@ def _load():
     lib.kgev_unmtr_device.restype = I32
     lib.kgev_eigh_device.argtypes = [P, P, I64, I64, I64, P, P, P, ctypes.POINTER(Opts), P]
     lib.kgev_eigh_device.restype = I32
+    lib.kgev_fermi_device.argtypes = [P, P, I64, I64, I64, P, D, D, D, P, I64, P, P, P]
+    lib.kgev_fermi_device.restype = I32
+    lib.kgev_density_workspace_bytes.argtypes = [I64, I64, I64]
+    lib.kgev_density_workspace_bytes.restype = ctypes.c_size_t
+    lib.kgev_density_device.argtypes = [P, P, I64, I64, I64, I64, P, I64, P, I64, P, D, P, P, I64, P,
+                                        ctypes.c_size_t, P]
+    lib.kgev_density_device.restype = I32
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
@@ -126,10 +135,11 @@ def _check(fn, st):
 
 
 def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0,
-              use_graph=False) -> Opts:
+              use_graph=False, streams=0) -> Opts:
     o = Opts()
     lib.kgev_opts_default(ctypes.byref(o))
     o.use_graph = 1 if use_graph else 0
+    o.streams = streams
     o.precision = precision
     o.want_vectors = 1 if want_vectors else 0
     o.panel_nb = panel_nb
@@ -234,6 +244,28 @@ def zgemm_device(ctx, transa, transb, m, n, k, alpha, dA, lda, sA, dB, ldb, sB, 
     return lib.kgev_zgemm_device(ctx.handle, transa.encode(), transb.encode(), m, n, k, Z(al.real, al.imag),
                                  _ptr(dA), lda, sA, _ptr(dB), ldb, sB, Z(be.real, be.imag), _ptr(dC), ldc, sC,
                                  batch, 1 if lower else 0, _stream(stream))
+
+
+def fermi_device(ctx, dw, n, nk, d_wk, nelec, kT, g, d_occ, d_result, d_status, ldw=None, ldo=None,
+                 stream=None) -> int:
+    """kgev_fermi_device: Band_DFT_Col Part 5 (mu, band energy, occupations)."""
+    return lib.kgev_fermi_device(ctx.handle, _ptr(dw), n if ldw is None else ldw, n, nk, _ptr(d_wk), float(nelec),
+                                 float(kT), float(g), _ptr(d_occ), n if ldo is None else ldo, _ptr(d_result),
+                                 _ptr(d_status), _stream(stream))
+
+
+def density_workspace_bytes(n, nk, nocc) -> int:
+    return lib.kgev_density_workspace_bytes(n, nk, nocc)
+
+
+def density_device(ctx, dC, n, nk, nocc, dw, d_occ, d_wk, g, d_rho, d_edm=None, ldc=None, ldw=None, ldo=None,
+                   ldr=None, dwork=None, work_bytes=0, stream=None) -> int:
+    """kgev_density_device: Band_DFT_Col Part 6 (charge and energy density
+    matrices, lower triangles)."""
+    return lib.kgev_density_device(ctx.handle, _ptr(dC), n if ldc is None else ldc, n, nk, nocc, _ptr(dw),
+                                   n if ldw is None else ldw, _ptr(d_occ), n if ldo is None else ldo, _ptr(d_wk),
+                                   float(g), _ptr(d_rho), _ptr(d_edm), n if ldr is None else ldr, _ptr(dwork),
+                                   int(work_bytes), _stream(stream))
 
 
 def profile_begin(ctx, phase) -> None:

@@ -133,3 +133,17 @@ def test_density_truncated_columns_agree():
     r1, e1 = O.density(C, w, occ, [0.5, 0.5], 2.0)
     r2, e2 = O.density(C, w, occ, [0.5, 0.5], 2.0, nocc=nocc)
     assert np.abs(r1 - r2).max() < 1e-15 and np.abs(e1 - e2).max() < 1e-15
+
+
+def test_density_entries_match_full_matrices():
+    rng = np.random.default_rng(12)
+    n, nk = 11, 2
+    _, C = _s_orthonormal(n, nk, rng)
+    w = np.sort(rng.uniform(-1, 1, (nk, n)), axis=1)
+    occ = rng.uniform(0, 1, (nk, n))
+    wk = [0.3, 0.7]
+    rho, E = O.density(C, w, occ, wk, 2.0)
+    pairs = [(0, 0), (5, 2), (10, 9), (3, 3), (10, 0)]
+    r, e = O.density_entries(np.transpose(C, (0, 2, 1)), w, occ, wk, 2.0, pairs)
+    for q, (a, b) in enumerate(pairs):
+        assert r[q] == rho[a, b] and e[q] == E[a, b]
