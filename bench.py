@@ -131,6 +131,10 @@ def main():
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-nmax", type=int, default=6000)
+    ap.add_argument("--panel-nb", type=int, default=0,
+                    help="Householder panel width (0: the library default, or the tuned width with --autotune)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run kgev_autotune for this n before timing (the tuned panel width is then used)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of MIB MiB (3 launches) and exit: the "
                          "reference of known size for scaling the HBM byte counters")
@@ -165,8 +169,12 @@ def main():
     dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
     dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
     dst = torch.zeros(nk, dtype=torch.int32, device=dev)
-    opts = K.make_opts()
+    opts = K.make_opts(panel_nb=args.panel_nb)
     ctx = K.Context(0)
+    tuned_nb = None
+    if args.autotune:
+        tuned_nb = K.autotune(ctx, n)
+        log(f"[bench] autotuned panel width {tuned_nb}")
 
     def step():
         st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
@@ -290,7 +298,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
-                   "n": n, "nk": nk, "precision": "fp64", "seed": args.seed},
+                   "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
+                   "panel_nb": args.panel_nb or tuned_nb or 32},
         "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),

@@ -11,6 +11,25 @@ constexpr int WAVE = 64;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef int i4_t __attribute__((ext_vector_type(4)));
+typedef int i2_t __attribute__((ext_vector_type(2)));
+
+// Raw buffer loads (MUBUF): address = base + voffset (per lane, 32-bit) +
+// soffset (wave-uniform, 32-bit); an access at or beyond `bytes` returns 0.
+// The descriptor's third word is the raw-buffer format of the gfx9 family.
+__device__ i4_t raw_buffer_load_v4i32(i4_t rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4i32");
+__device__ i2_t raw_buffer_load_v2i32(i4_t rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2i32");
+
+__device__ inline i4_t buffer_rsrc(const void* base, uint32_t bytes)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(base);
+    i4_t r;
+    r.x = (int)(uint32_t)(a & 0xffffffffu);
+    r.y = (int)(uint32_t)(a >> 32);
+    r.z = (int)bytes;
+    r.w = 0x00020000;
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // complex numbers: double2 / float2 with x = re, y = im

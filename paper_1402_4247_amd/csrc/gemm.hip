@@ -36,7 +36,9 @@ struct CGemmArgs {
     int64_t ldc, sC;
     int lower;
     int tiles_m, tiles_n;
-    int64_t batch;
+    int64_t batch;             // total products = batch1 * batch2
+    int64_t batch2;            // inner batch: product L -> (L / batch2, L % batch2)
+    int64_t sA2[2], sB2[2], sC2;   // strides of the inner batch index
     int remap;
 };
 
@@ -155,6 +157,7 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
     int64_t bz;
     int tm, tn;
     tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, p.remap, bz, tm, tn);
+    const int64_t bo = bz / p.batch2, bi = bz - bo * p.batch2;
     const int64_t m = p.m, n = p.n, K = p.k;
     const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
     if (p.lower && i0 + BM <= j0) return;   // tile entirely above the diagonal
@@ -184,8 +187,8 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
     unsigned oka = 0, okb = 0;
     int cur = 0;
     if (total_k > 0) {
-        load_a<R, BM, TA>(p.A[0] + bz * p.sA[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
-        load_b<R, BN, TB>(p.B[0] + bz * p.sB[0], p.ldb[0], n, K, j0, 0, tid, rb, okb);
+        load_a<R, BM, TA>(p.A[0] + bo * p.sA[0] + bi * p.sA2[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
+        load_b<R, BN, TB>(p.B[0] + bo * p.sB[0] + bi * p.sB2[0], p.ldb[0], n, K, j0, 0, tid, rb, okb);
         store_a<R, BM, TA>(sAr[0], sAi[0], tid, ra, oka);
         store_b<R, BN, TB>(sBr[0], sBi[0], tid, rb, okb);
     }
@@ -194,8 +197,10 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
         const int nx = it + 1;
         const int sn = nx / nkt, kt = nx % nkt;
         if (nx < total_k) {
-            load_a<R, BM, TA>(p.A[sn] + bz * p.sA[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid, ra, oka);
-            load_b<R, BN, TB>(p.B[sn] + bz * p.sB[sn], p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid, rb, okb);
+            load_a<R, BM, TA>(p.A[sn] + bo * p.sA[sn] + bi * p.sA2[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid,
+                              ra, oka);
+            load_b<R, BN, TB>(p.B[sn] + bo * p.sB[sn] + bi * p.sB2[sn], p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid,
+                              rb, okb);
         }
 #pragma unroll
         for (int ks = 0; ks < GB_K; ks += 4) {
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
         if constexpr (NST == 2) cur ^= 1;
     }
 
-    cx<R>* C = p.C + bz * p.sC;
+    cx<R>* C = p.C + bo * p.sC + bi * p.sC2;
     const bool rb0 = (p.beta.x != 0 || p.beta.y != 0);
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -301,8 +306,10 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
 {
     if (a.m <= 0 || a.n <= 0 || batch <= 0) return hipSuccess;
     CGemmArgs<R> p = a;
-    p.batch = batch;
-    double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch;
+    if (p.batch2 < 1) p.batch2 = 1;
+    p.batch = batch * p.batch2;
+    double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch *
+                   (double)(a.batch2 < 1 ? 1 : a.batch2);
     if (a.lower) flops *= 0.5;
     // The 3M form is the default: on gfx950 it measured 1.22x the 4M form on
     // the path's products with unchanged residuals.  KGEV_GEMM_REMAP=0|1 and
@@ -348,6 +355,24 @@ hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t
 }
 
 template <typename R>
+hipError_t cgemm_batch2(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,
+                        const cx<R>* A, int64_t lda, int64_t sA, int64_t sA2, const cx<R>* B, int64_t ldb, int64_t sB,
+                        int64_t sB2, cx<R> beta, cx<R>* C, int64_t ldc, int64_t sC, int64_t sC2, int64_t batch,
+                        int64_t batch2)
+{
+    CGemmArgs<R> a{};
+    a.m = m; a.n = n; a.k = k; a.nseg = 1;
+    a.A[0] = a.A[1] = A; a.B[0] = a.B[1] = B;
+    a.lda[0] = a.lda[1] = lda; a.ldb[0] = a.ldb[1] = ldb;
+    a.sA[0] = a.sA[1] = sA; a.sB[0] = a.sB[1] = sB;
+    a.sA2[0] = a.sA2[1] = sA2; a.sB2[0] = a.sB2[1] = sB2;
+    a.ta[0] = a.ta[1] = (ta == 'C'); a.tb[0] = a.tb[1] = (tb == 'C');
+    a.alpha = alpha; a.beta = beta; a.C = C; a.ldc = ldc; a.sC = sC; a.sC2 = sC2; a.lower = 0;
+    a.batch2 = batch2;
+    return launch_cgemm<R>(a, batch, st);
+}
+
+template <typename R>
 hipError_t cher2k_lower(hipStream_t st, int64_t m, int64_t k, const cx<R>* V, int64_t ldv, int64_t sV,
                         const cx<R>* W, int64_t ldw, int64_t sW, cx<R>* C, int64_t ldc, int64_t sC,
                         int64_t batch)
@@ -370,6 +395,13 @@ template hipError_t cgemm<double>(hipStream_t, char, char, int64_t, int64_t, int
 template hipError_t cgemm<float>(hipStream_t, char, char, int64_t, int64_t, int64_t, float2,
                                  const float2*, int64_t, int64_t, const float2*, int64_t, int64_t,
                                  float2, float2*, int64_t, int64_t, int64_t, bool);
+template hipError_t cgemm_batch2<double>(hipStream_t, char, char, int64_t, int64_t, int64_t, double2,
+                                         const double2*, int64_t, int64_t, int64_t, const double2*, int64_t,
+                                         int64_t, int64_t, double2, double2*, int64_t, int64_t, int64_t, int64_t,
+                                         int64_t);
+template hipError_t cgemm_batch2<float>(hipStream_t, char, char, int64_t, int64_t, int64_t, float2, const float2*,
+                                        int64_t, int64_t, int64_t, const float2*, int64_t, int64_t, int64_t, float2,
+                                        float2*, int64_t, int64_t, int64_t, int64_t, int64_t);
 template hipError_t cher2k_lower<double>(hipStream_t, int64_t, int64_t, const double2*, int64_t, int64_t,
                                          const double2*, int64_t, int64_t, double2*, int64_t, int64_t,
                                          int64_t);

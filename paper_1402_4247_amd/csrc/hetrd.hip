@@ -131,7 +131,7 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // direct part z_R += A_RC u_C comes out complete per row, the transposed part
 // z_C += A_RC^H u_R per column after a transposing wave reduction, and the
 // four waves' column sums are added once.
-template <typename R, int MINW>
+template <typename R, int MINW, bool BUF, int PF>
 __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
 {
     __shared__ cx<R> svC[ZT];
@@ -163,20 +163,36 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
     // Loads are unconditional from a clamped (in-bounds) address and the value
     // is masked afterwards, so no branch guards them; each group of 8 columns
     // is requested one step ahead of its use.
-    // the column base is wave-uniform (scalar registers); the row is one
-    // 32-bit offset per lane shared by every load of the tile
+    // Matrices under 2 GiB are read with buffer loads: one 32-bit row offset
+    // per lane shared by every load of the tile, the column offset in a
+    // scalar register (fewer vector registers and no 64-bit address
+    // arithmetic); larger ones with plain global loads.
     const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
+    const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
     auto load_group = [&](int g, cx<R> (&a)[8]) {
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
             const int64_t gc = gcb + g * 8 + cc;
-            const cx<R>* col = A + (gc < n ? gc : (int64_t)n - 1) * lda;
-            a[cc] = col[rowc];
+            const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
+            if constexpr (BUF) {
+                const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
+                if constexpr (sizeof(R) == 8) {
+                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    a[cc] = __builtin_bit_cast(cx<R>, v);
+                } else {
+                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    a[cc] = __builtin_bit_cast(cx<R>, v);
+                }
+            } else {
+                a[cc] = A[gcc * lda + rowc];
+            }
         }
     };
-    cx<R> a[8], an[8];
+    // groups of 8 columns are requested PF groups ahead of their use
+    cx<R> a[8], an[8], an2[8];
     load_group(0, a);
+    if constexpr (PF == 2) load_group(1, an);
     if (tid < ZT) {
         const int64_t gc = gcb + tid;
         const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
@@ -193,7 +209,11 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
         cx<R> yd = czero<cx<R>>();
 #pragma unroll 1
         for (int g = 0; g < 8; ++g) {
-            if (g + 1 < 8) load_group(g + 1, an);
+            if constexpr (PF == 2) {
+                if (g + 2 < 8) load_group(g + 2, an2);
+            } else {
+                if (g + 1 < 8) load_group(g + 1, an);
+            }
             const int64_t gc0 = gcb + g * 8;
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc) {
@@ -210,7 +230,10 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
             const cx<R> r = transpose_sum8<R>(a, lane);
             if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
 #pragma unroll
-            for (int cc = 0; cc < 8; ++cc) a[cc] = an[cc];
+            for (int cc = 0; cc < 8; ++cc) {
+                a[cc] = an[cc];
+                if constexpr (PF == 2) an[cc] = an2[cc];
+            }
         }
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
         qd = uR.x * yd.x + uR.y * yd.y;
@@ -517,7 +540,17 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
     if (n < 1 || nk < 1) return hipSuccess;
     // KGEV_HEMV_OCC=3 selects the product kernel compiled for three
     // workgroups per CU (tuning experiments)
-    static const bool occ3 = [] {
+    static const bool buf_ok = [] {
+        const char* v = getenv("KGEV_HEMV_BUFFER");
+        return !(v && atoi(v) == 0);
+    }();
+    // buffer offsets are 32-bit: the matrix (ld x n) must stay under 2 GiB
+    const bool buf = buf_ok && (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
+    static const bool pf2 = [] {
+        const char* v = getenv("KGEV_HEMV_PREFETCH");
+        return v && atoi(v) == 2;
+    }();
+    const bool occ3 = buf && [] {
         const char* v = getenv("KGEV_HEMV_OCC");
         return v && atoi(v) == 3;
     }();
@@ -531,10 +564,15 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
             prof_before(PH_HEMV, st);
+            const dim3 gz((unsigned)nch, (unsigned)nk);
             if (occ3)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3>), dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 1>), gz, dim3(256), 0, st, ws, i);
+            else if (buf && pf2)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 2>), gz, dim3(256), 0, st, ws, i);
+            else if (buf)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
             else
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1>), dim3((unsigned)nch, (unsigned)nk), dim3(256), 0, st, ws, i);
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, false, 1>), gz, dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);

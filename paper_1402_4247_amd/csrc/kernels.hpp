@@ -23,6 +23,13 @@ hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t
                  cx<R> beta, cx<R>* C, int64_t ldc, int64_t sC, int64_t batch, bool lower);
 
 // C(lower) -= V W^H + W V^H   (m x m, inner dimension k)
+// C_L = alpha op(A_L) op(B_L) + beta C_L for L = (l1, l2), l1 < batch,
+// l2 < batch2, operands at base + l1 * s + l2 * s2
+template <typename R>
+hipError_t cgemm_batch2(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,
+                        const cx<R>* A, int64_t lda, int64_t sA, int64_t sA2, const cx<R>* B, int64_t ldb, int64_t sB,
+                        int64_t sB2, cx<R> beta, cx<R>* C, int64_t ldc, int64_t sC, int64_t sC2, int64_t batch,
+                        int64_t batch2);
 template <typename R>
 hipError_t cher2k_lower(hipStream_t st, int64_t m, int64_t k, const cx<R>* V, int64_t ldv, int64_t sV,
                         const cx<R>* W, int64_t ldw, int64_t sW, cx<R>* C, int64_t ldc, int64_t sC,
@@ -97,11 +104,6 @@ hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t
 // sets status 1 when s_0 <= s_tol * s_{n-1}
 hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
                           int64_t ss, double s_tol, int* status, int64_t nk);
-// T factor of a block of kb reflectors (columns c0..c0+kb-1 of V): T upper
-// triangular kb x kb, from G = V_b^H V_b
-template <typename R>
-hipError_t larft(hipStream_t st, int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau, int c0,
-                 cx<R>* T, int64_t sT, int64_t nk);
 hipError_t status_init(hipStream_t st, int* status, int64_t nk);
 // nk synthetic matrices (entries in [-1, 1), real diagonal) for timing runs
 template <typename R>

@@ -494,31 +494,43 @@ __global__ __launch_bounds__(256) void dc_gemm(DcWs ws, int t, int rb, int wb, i
             for (int r = 0; r < 4; ++r) acc[a][c][r] = 0.0;
 
     const int nkt = (K + DK - 1) / DK;
+    // tile loads from clamped (in-bounds) indices with no branch, so the next
+    // K step stays in flight during the MFMA work; the bounds mask is applied
+    // when the registers are stored to LDS
     double ra[4], rbv[4];
+    unsigned oka = 0, okb = 0;
     auto gload = [&](int k0) {
-        // A tile: rows i0..i0+63 (lanes), k = k0 + kq + 4q
+        // A tile: rows i0..i0+63 (lanes), k = k0 + kq + 4q, columns gathered through ndx
         const int r = tid & 63, kq = tid >> 6;
+        const int ic = i0 + r < ns ? i0 + r : 0;
+        oka = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + kq + 4 * q;
-            ra[q] = (i0 + r < ns && k < K) ? Qr[(s + i0 + r) + (s + ndx[k]) * n] : 0.0;
+            const int kc = k < K ? k : 0;
+            ra[q] = Qr[(s + ic) + (s + ndx[kc]) * n];
+            oka |= (unsigned)(i0 + r < ns && k < K) << q;
         }
         // B tile: k = k0 + (tid & 15), cols j0 + (tid >> 4) + 16 q
         const int kk = tid & 15, jq = tid >> 4;
+        const int k = k0 + kk;
+        const int kc = k < K ? k : 0;
+        okb = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int jj = j0 + jq + 16 * q;
-            const int k = k0 + kk;
-            rbv[q] = (jj < K && k < K) ? Vs[(s + k) + (s + jj) * n] : 0.0;
+            const int jc = jj < K ? jj : 0;
+            rbv[q] = Vs[(s + kc) + (s + jc) * n];
+            okb |= (unsigned)(jj < K && k < K) << q;
         }
     };
     auto sstore = [&](int buf) {
         const int r = tid & 63, kq = tid >> 6;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sA[buf][kq + 4 * q][r] = ra[q];
+        for (int q = 0; q < 4; ++q) sA[buf][kq + 4 * q][r] = ((oka >> q) & 1u) ? ra[q] : 0.0;
         const int kk = tid & 15, jq = tid >> 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sB[buf][kk][jq + 16 * q] = rbv[q];
+        for (int q = 0; q < 4; ++q) sB[buf][kk][jq + 16 * q] = ((okb >> q) & 1u) ? rbv[q] : 0.0;
     };
     int cur = 0;
     if (nkt > 0) { gload(0); sstore(0); }

@@ -107,39 +107,51 @@ __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, i
     for (int64_t i = threadIdx.x; i < n; i += 256) u[i] = cscale(u[i], f);
 }
 
-// T (kb x kb, ld kb, upper) for reflectors c0..c0+kb-1:
+// T (kk x kk, upper) for reflectors c0..c0+kk-1 (compact WY):
 // T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V_b^H V_b.
 constexpr int KBMAX = 64;
+// T factors of every reflector block at once, one workgroup per (block,
+// k-point): T_b (kk x kk, ld kb) from G_b = V_b^H V_b (ld kb).  The 256
+// threads take row r = tid / 4 of the recurrence and split its sum four
+// ways (fixed-order shuffle combine).
 template <typename R>
-__global__ __launch_bounds__(64) void k_larft(int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau,
-                                              int c0, cx<R>* T, int64_t strT)
+__global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>* G, int64_t sG,
+                                                   const cx<R>* tau, int64_t stau, cx<R>* T, int64_t strT)
 {
     __shared__ cx<R> sT[KBMAX][KBMAX + 1];   // sT[col][row]
-    __shared__ cx<R> gl[KBMAX][KBMAX + 1];   // gl[col][row] = G(row, col), read once
+    __shared__ cx<R> gl[KBMAX][KBMAX + 1];   // gl[col][row] = G(row, col)
     __shared__ cx<R> tl[KBMAX];
-    const int64_t b = blockIdx.x;
-    const int r = threadIdx.x;
-    const cx<R>* g = G + b * sG;
-    for (int j = 0; j < kb; ++j)
-        if (r < kb) gl[j][r] = g[r + (int64_t)j * kb];
-    if (r < kb) tl[r] = tau[b * stau + c0 + r];
+    const int blk = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int c0 = blk * kb;
+    const int kk = nref - c0 < kb ? nref - c0 : kb;
+    const int tid = threadIdx.x, r = tid >> 2, part = tid & 3;
+    const cx<R>* g = G + b * sG + (int64_t)blk * kb * kb;
+    for (int e = tid; e < kk * kk; e += 256) {
+        const int rr = e % kk, cc = e / kk;
+        gl[cc][rr] = g[rr + (int64_t)cc * kb];
+    }
+    if (tid < kk) tl[tid] = tau[b * stau + c0 + tid];
     __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        const cx<R> tj = tl[j];
-        if (r < j) {
-            cx<R> acc = czero<cx<R>>();
-            for (int q = r; q < j; ++q) acc = cfma(sT[q][r], gl[j][q], acc);
-            sT[j][r] = cscale(cmul(tj, acc), (R)-1);
-        } else if (r == j) {
-            sT[j][r] = tj;
-        } else if (r < kb) {
-            sT[j][r] = czero<cx<R>>();
+    for (int j = 0; j < kk; ++j) {
+        cx<R> acc = czero<cx<R>>();
+        if (r < j)
+            for (int q = r + part; q < j; q += 4) acc = cfma(sT[q][r], gl[j][q], acc);
+        acc.x += __shfl_xor(acc.x, 1, WAVE);
+        acc.y += __shfl_xor(acc.y, 1, WAVE);
+        acc.x += __shfl_xor(acc.x, 2, WAVE);
+        acc.y += __shfl_xor(acc.y, 2, WAVE);
+        if (part == 0 && r < kk) {
+            const cx<R> tj = tl[j];
+            sT[j][r] = csel(r < j, cscale(cmul(tj, acc), (R)-1), csel(r == j, tj, czero<cx<R>>()));
         }
         __syncthreads();
     }
-    cx<R>* Tb = T + b * strT;
-    for (int j = 0; j < kb; ++j)
-        if (r < kb) Tb[r + (int64_t)j * kb] = sT[j][r];
+    cx<R>* Tb = T + b * strT + (int64_t)blk * kb * kb;
+    for (int e = tid; e < kk * kk; e += 256) {
+        const int rr = e % kk, cc = e / kk;
+        Tb[rr + (int64_t)cc * kb] = sT[cc][rr];
+    }
 }
 
 }  // namespace
@@ -239,14 +251,6 @@ hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, in
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t larft(hipStream_t st, int kb, const cx<R>* G, int64_t sG, const cx<R>* tau, int64_t stau, int c0,
-                 cx<R>* T, int64_t sT, int64_t nk)
-{
-    if (kb > KBMAX || kb < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_larft<R>, dim3((unsigned)nk), dim3(64), 0, st, kb, G, sG, tau, stau, c0, T, sT);
-    return hipGetLastError();
-}
 
 template hipError_t copy_lower_check<double>(hipStream_t, int64_t, const double2*, int64_t, int64_t, double2*,
                                              int64_t, int64_t, int*, int64_t);
@@ -256,15 +260,18 @@ template hipError_t real_to_complex<double>(hipStream_t, int64_t, const double*,
                                             int64_t, int64_t);
 template hipError_t real_to_complex<float>(hipStream_t, int64_t, const double*, int64_t, float2*, int64_t,
                                            int64_t, int64_t);
-template hipError_t larft<double>(hipStream_t, int, const double2*, int64_t, const double2*, int64_t, int, double2*,
-                                  int64_t, int64_t);
-template hipError_t larft<float>(hipStream_t, int, const float2*, int64_t, const float2*, int64_t, int, float2*,
-                                 int64_t, int64_t);
 
 // ---------------------------------------------------------------------------
 // Back-transformation U <- Q U, Q = H_0 ... H_{n-2}, in blocks of kb
-// reflectors applied last block first as (I - V_b T_b V_b^H).
-int64_t unmtr_work_elems(int64_t n, int kb) { return 2 * (int64_t)kb * kb + 2 * (int64_t)kb * n; }
+// reflectors applied last block first as (I - V_b T_b V_b^H).  The Gram
+// matrices G_b = V_b^H V_b and T factors of all blocks are formed first, in
+// one launch each: V is zero above each reflector, so every full block's G_b
+// can be taken over rows 1..n-1, which gives all of them one stride.
+int64_t unmtr_work_elems(int64_t n, int kb)
+{
+    const int64_t nblk = (n - 1 + kb - 1) / kb;
+    return 2 * nblk * (int64_t)kb * kb + 2 * (int64_t)kb * n;
+}
 
 template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
@@ -272,26 +279,41 @@ hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx
 {
     const int64_t nref = n - 1;
     if (nref <= 0) return hipSuccess;
+    if (kb > KBMAX || kb < 1) return hipErrorInvalidValue;
     const int64_t sw = unmtr_work_elems(n, kb);
+    const int64_t nblk = (nref + kb - 1) / kb, nfull = nref / kb;
+    const int64_t kb2 = (int64_t)kb * kb;
     cx<R>* G = work;
-    cx<R>* T = work + (int64_t)kb * kb;
-    cx<R>* W1 = work + 2 * (int64_t)kb * kb;
+    cx<R>* T = work + nblk * kb2;
+    cx<R>* W1 = work + 2 * nblk * kb2;
     cx<R>* W2 = W1 + (int64_t)kb * n;
     const cx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
-    const int64_t nblk = (nref + kb - 1) / kb;
+    hipError_t e;
+    if (nfull > 0) {
+        e = cgemm_batch2<R>(st, 'C', 'N', kb, kb, n - 1, one, V + 1, n, sV, kb * n, V + 1, n, sV, kb * n, zero, G, kb,
+                            sw, kb2, nk, nfull);
+        if (e != hipSuccess) return e;
+    }
+    if (nfull < nblk) {
+        const int64_t c0 = nfull * kb;
+        const int kk = (int)(nref - c0);
+        const int64_t r0 = c0 + 1, m = n - r0;
+        const cx<R>* Vb = V + r0 + c0 * n;
+        e = cgemm<R>(st, 'C', 'N', kk, kk, m, one, Vb, n, sV, Vb, n, sV, zero, G + nfull * kb2, kb, sw, nk, false);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_larft_all<R>, dim3((unsigned)nblk, (unsigned)nk), dim3(256), 0, st, kb, (int)nref, G, sw,
+                       tau, stau, T, sw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     for (int64_t blk = nblk - 1; blk >= 0; --blk) {
         const int64_t c0 = blk * kb;
         const int kk = (int)((nref - c0) < kb ? (nref - c0) : kb);
         const int64_t r0 = c0 + 1, m = n - r0;
         const cx<R>* Vb = V + r0 + c0 * n;
-        hipError_t e;
-        e = cgemm<R>(st, 'C', 'N', kk, kk, m, one, Vb, n, sV, Vb, n, sV, zero, G, kk, sw, nk, false);
-        if (e != hipSuccess) return e;
-        e = larft<R>(st, kk, G, sw, tau, stau, (int)c0, T, sw, nk);
-        if (e != hipSuccess) return e;
         e = cgemm<R>(st, 'C', 'N', kk, n, m, one, Vb, n, sV, U + r0, ldu, sU, zero, W1, kk, sw, nk, false);
         if (e != hipSuccess) return e;
-        e = cgemm<R>(st, 'N', 'N', kk, n, kk, one, T, kk, sw, W1, kk, sw, zero, W2, kk, sw, nk, false);
+        e = cgemm<R>(st, 'N', 'N', kk, n, kk, one, T + blk * kb2, kb, sw, W1, kk, sw, zero, W2, kk, sw, nk, false);
         if (e != hipSuccess) return e;
         e = cgemm<R>(st, 'N', 'N', m, n, kk, mone, Vb, n, sV, W2, kk, sw, one, U + r0, ldu, sU, nk, false);
         if (e != hipSuccess) return e;
