@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=6000)
     ap.add_argument("--panel-nb", type=int, default=0,
                     help="Householder panel width (0: the library default, or the tuned width with --autotune)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the batched solve as one HIP graph on the first call and replay it")
     ap.add_argument("--autotune", action="store_true",
                     help="run kgev_autotune for this n before timing (the tuned panel width is then used)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -169,15 +171,21 @@ def main():
     dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
     dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
     dst = torch.zeros(nk, dtype=torch.int32, device=dev)
-    opts = K.make_opts(panel_nb=args.panel_nb)
+    opts = K.make_opts(panel_nb=args.panel_nb, use_graph=args.graph)
     ctx = K.Context(0)
+    stream = torch.cuda.Stream() if args.graph else None
     tuned_nb = None
     if args.autotune:
         tuned_nb = K.autotune(ctx, n)
         log(f"[bench] autotuned panel width {tuned_nb}")
 
     def step():
-        st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
+        if stream is not None:
+            with torch.cuda.stream(stream):
+                st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts,
+                                      stream=stream.cuda_stream)
+        else:
+            st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
         if st != 0:
             raise RuntimeError(f"kgev_solve_k_device returned {st}")
 
@@ -200,6 +208,21 @@ def main():
     value = nk * args.steps / elapsed
     status = dst.cpu().numpy()
     log(f"[bench] {ms_per_step:.1f} ms/step, {value:.2f} solves/s, status {set(status.tolist())}")
+    prof_elapsed, prof_note = elapsed, "the timed steps"
+    if args.graph:
+        # graph replays carry no per-launch events: the kernel is timed on one
+        # eager step with the same sizes and buffers
+        eager = K.make_opts(panel_nb=args.panel_nb)
+        K.profile_begin(ctx, phase)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=eager)
+        torch.cuda.synchronize()
+        prof_elapsed = time.perf_counter() - a
+        prof = K.profile_end(ctx)
+        if st != 0:
+            raise RuntimeError(f"eager profiling step returned {st}")
+        prof_note = "one eager step after the timed graph replays"
 
     avg_ms = prof["ms"] / max(prof["launches"], 1)
     if phase == K.PHASE_HEMV:
@@ -208,16 +231,16 @@ def main():
         roof = {"bound": "hbm", "kernel": "hetrd_zhemv", "achieved": achieved, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(n, nk),
                 "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
-                "alg_bytes_per_launch": per_launch,
-                "share_of_step": prof["ms"] / (1e3 * elapsed)}
+                "alg_bytes_per_launch": per_launch, "measured_on": prof_note,
+                "share_of_step": prof["ms"] / (1e3 * prof_elapsed)}
     else:
         per_launch = prof["flops"] / max(prof["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "cgemm_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
-                "alg_flops_per_launch": per_launch,
-                "share_of_step": prof["ms"] / (1e3 * elapsed)}
+                "alg_flops_per_launch": per_launch, "measured_on": prof_note,
+                "share_of_step": prof["ms"] / (1e3 * prof_elapsed)}
 
     # latency of single-k-point calls
     lat = []
@@ -299,7 +322,7 @@ def main():
         "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
-                   "panel_nb": args.panel_nb or tuned_nb or 32},
+                   "panel_nb": args.panel_nb or tuned_nb or 32, "graph": bool(args.graph)},
         "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),

@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
     cx<R> a[8], an[8], an2[8];
     load_group(0, a);
     if constexpr (PF == 2) load_group(1, an);
+    (void)an2;
     if (tid < ZT) {
         const int64_t gc = gcb + tid;
         const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
@@ -211,8 +212,10 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
         for (int g = 0; g < 8; ++g) {
             if constexpr (PF == 2) {
                 if (g + 2 < 8) load_group(g + 2, an2);
-            } else {
+            } else if constexpr (PF == 1) {
                 if (g + 1 < 8) load_group(g + 1, an);
+            } else {
+                if (g > 0) load_group(g, a);
             }
             const int64_t gc0 = gcb + g * 8;
 #pragma unroll
@@ -229,10 +232,12 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
             }
             const cx<R> r = transpose_sum8<R>(a, lane);
             if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
+            if constexpr (PF > 0) {
 #pragma unroll
-            for (int cc = 0; cc < 8; ++cc) {
-                a[cc] = an[cc];
-                if constexpr (PF == 2) an[cc] = an2[cc];
+                for (int cc = 0; cc < 8; ++cc) {
+                    a[cc] = an[cc];
+                    if constexpr (PF == 2) an[cc] = an2[cc];
+                }
             }
         }
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
@@ -538,21 +543,17 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
 {
     const int n = ws.n, nb = ws.nb;
     if (n < 1 || nk < 1) return hipSuccess;
-    // KGEV_HEMV_OCC=3 selects the product kernel compiled for three
-    // workgroups per CU (tuning experiments)
     static const bool buf_ok = [] {
         const char* v = getenv("KGEV_HEMV_BUFFER");
         return !(v && atoi(v) == 0);
     }();
     // buffer offsets are 32-bit: the matrix (ld x n) must stay under 2 GiB
     const bool buf = buf_ok && (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
-    static const bool pf2 = [] {
-        const char* v = getenv("KGEV_HEMV_PREFETCH");
-        return v && atoi(v) == 2;
-    }();
-    const bool occ3 = buf && [] {
-        const char* v = getenv("KGEV_HEMV_OCC");
-        return v && atoi(v) == 3;
+    // KGEV_HEMV_VARIANT = 10 * (min waves per SIMD) + (groups of 8 columns
+    // prefetched): 11 (default), 12, 30, 31, 40 (tuning experiments)
+    static const int variant = [] {
+        const char* v = getenv("KGEV_HEMV_VARIANT");
+        return v ? atoi(v) : 11;
     }();
     for (int p = 0; p <= n - 1; p += nb) {
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
@@ -565,14 +566,18 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
             prof_before(PH_HEMV, st);
             const dim3 gz((unsigned)nch, (unsigned)nk);
-            if (occ3)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 1>), gz, dim3(256), 0, st, ws, i);
-            else if (buf && pf2)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 2>), gz, dim3(256), 0, st, ws, i);
-            else if (buf)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
-            else
+            if (!buf)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 1, false, 1>), gz, dim3(256), 0, st, ws, i);
+            else if (variant == 30)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 0>), gz, dim3(256), 0, st, ws, i);
+            else if (variant == 40)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 4, true, 0>), gz, dim3(256), 0, st, ws, i);
+            else if (variant == 31)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 1>), gz, dim3(256), 0, st, ws, i);
+            else if (variant == 12)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 2>), gz, dim3(256), 0, st, ws, i);
+            else
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);

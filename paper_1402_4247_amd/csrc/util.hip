@@ -262,16 +262,48 @@ template hipError_t real_to_complex<float>(hipStream_t, int64_t, const double*, 
                                            int64_t, int64_t);
 
 // ---------------------------------------------------------------------------
-// Back-transformation U <- Q U, Q = H_0 ... H_{n-2}, in blocks of kb
-// reflectors applied last block first as (I - V_b T_b V_b^H).  The Gram
-// matrices G_b = V_b^H V_b and T factors of all blocks are formed first, in
-// one launch each: V is zero above each reflector, so every full block's G_b
-// can be taken over rows 1..n-1, which gives all of them one stride.
+// Back-transformation U <- Q U, Q = H_0 ... H_{n-2}, in blocks of 2 kb
+// reflectors applied last block first as (I - V_B T_B V_B^H).
+//   * The Gram matrices G_b = V_b^H V_b of the kb-blocks and their T factors
+//     are formed first, one launch each: V is zero above each reflector, so
+//     every full block's G_b can be taken over rows 1..n-1, which gives all
+//     of them one stride.
+//   * Pairs of kb-blocks are joined into 2kb-blocks,
+//     T_B = [[T_1, -T_1 (V_1^H V_2) T_2], [0, T_2]] (three batched products),
+//     so the two products that apply a block have 2kb rows / a 2kb inner
+//     dimension.
 int64_t unmtr_work_elems(int64_t n, int kb)
 {
-    const int64_t nblk = (n - 1 + kb - 1) / kb;
-    return 2 * nblk * (int64_t)kb * kb + 2 * (int64_t)kb * n;
+    const int64_t nblk = (n - 1 + kb - 1) / kb, npair = (nblk + 1) / 2;
+    const int64_t kb2 = (int64_t)kb * kb;
+    return nblk * kb2                 // G of the kb-blocks
+           + nblk * kb2               // T of the kb-blocks
+           + npair * 4 * kb2          // T of the 2kb-blocks
+           + 2 * npair * kb2          // V_1^H V_2 and (V_1^H V_2) T_2 per pair
+           + 2 * 2 * (int64_t)kb * n; // W1, W2 (2kb x n)
 }
+
+namespace {
+// T_B of every pair: diagonal blocks copied from the kb-block factors, the
+// lower-left block zeroed (the upper-right block is written by products)
+template <typename R>
+__global__ __launch_bounds__(256) void k_pair_t(int kb, int nblk, const cx<R>* T, int64_t sT, cx<R>* TB, int64_t sTB)
+{
+    const int q = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int b1 = 2 * q, b2 = 2 * q + 1;
+    const int64_t kb2 = (int64_t)kb * kb, ld = 2 * kb;
+    cx<R>* t = TB + b * sTB + (int64_t)q * 4 * kb2;
+    const cx<R>* t1 = T + b * sT + (int64_t)b1 * kb2;
+    const cx<R>* t2 = T + b * sT + (int64_t)b2 * kb2;
+    for (int e = threadIdx.x; e < kb * kb; e += 256) {
+        const int r = e % kb, c = e / kb;
+        t[r + (int64_t)c * ld] = t1[r + (int64_t)c * kb];
+        t[(kb + r) + (int64_t)c * ld] = czero<cx<R>>();
+        if (b2 < nblk) t[(kb + r) + (int64_t)(kb + c) * ld] = t2[r + (int64_t)c * kb];
+    }
+}
+}  // namespace
 
 template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
@@ -281,14 +313,18 @@ hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx
     if (nref <= 0) return hipSuccess;
     if (kb > KBMAX || kb < 1) return hipErrorInvalidValue;
     const int64_t sw = unmtr_work_elems(n, kb);
-    const int64_t nblk = (nref + kb - 1) / kb, nfull = nref / kb;
-    const int64_t kb2 = (int64_t)kb * kb;
+    const int64_t nblk = (nref + kb - 1) / kb, nfull = nref / kb, npair = (nblk + 1) / 2;
+    const int64_t kb2 = (int64_t)kb * kb, ld2 = 2 * kb;
     cx<R>* G = work;
-    cx<R>* T = work + nblk * kb2;
-    cx<R>* W1 = work + 2 * nblk * kb2;
-    cx<R>* W2 = W1 + (int64_t)kb * n;
+    cx<R>* T = G + nblk * kb2;
+    cx<R>* TB = T + nblk * kb2;
+    cx<R>* G12 = TB + npair * 4 * kb2;
+    cx<R>* X12 = G12 + npair * kb2;
+    cx<R>* W1 = X12 + npair * kb2;
+    cx<R>* W2 = W1 + 2 * (int64_t)kb * n;
     const cx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
     hipError_t e;
+    // Gram matrices and T factors of the kb-blocks
     if (nfull > 0) {
         e = cgemm_batch2<R>(st, 'C', 'N', kb, kb, n - 1, one, V + 1, n, sV, kb * n, V + 1, n, sV, kb * n, zero, G, kb,
                             sw, kb2, nk, nfull);
@@ -306,14 +342,46 @@ hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx
                        tau, stau, T, sw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    for (int64_t blk = nblk - 1; blk >= 0; --blk) {
-        const int64_t c0 = blk * kb;
-        const int kk = (int)((nref - c0) < kb ? (nref - c0) : kb);
+    // T of the 2kb-blocks: diagonal blocks, then T12 = -T_1 (V_1^H V_2) T_2
+    hipLaunchKernelGGL(k_pair_t<R>, dim3((unsigned)npair, (unsigned)nk), dim3(256), 0, st, kb, (int)nblk, T, sw, TB,
+                       sw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nfp = nfull / 2;               // pairs of two full kb-blocks
+    if (nfp > 0) {
+        e = cgemm_batch2<R>(st, 'C', 'N', kb, kb, n - 1, one, V + 1, n, sV, 2 * kb * n, V + 1 + kb * n, n, sV,
+                            2 * kb * n, zero, G12, kb, sw, kb2, nk, nfp);
+        if (e != hipSuccess) return e;
+        e = cgemm_batch2<R>(st, 'N', 'N', kb, kb, kb, one, G12, kb, sw, kb2, T + kb2, kb, sw, 2 * kb2, zero, X12, kb,
+                            sw, kb2, nk, nfp);
+        if (e != hipSuccess) return e;
+        e = cgemm_batch2<R>(st, 'N', 'N', kb, kb, kb, mone, T, kb, sw, 2 * kb2, X12, kb, sw, kb2, zero, TB + kb * ld2,
+                            ld2, sw, 4 * kb2, nk, nfp);
+        if (e != hipSuccess) return e;
+    }
+    if (nfp < npair && 2 * nfp + 1 < nblk) {
+        // last pair with a partial second block
+        const int64_t q = nfp, c1 = 2 * q * kb, c2 = c1 + kb;
+        const int kk2 = (int)(nref - c2);
+        e = cgemm<R>(st, 'C', 'N', kb, kk2, n - 1, one, V + 1 + c1 * n, n, sV, V + 1 + c2 * n, n, sV, zero,
+                     G12 + q * kb2, kb, sw, nk, false);
+        if (e != hipSuccess) return e;
+        e = cgemm<R>(st, 'N', 'N', kb, kk2, kk2, one, G12 + q * kb2, kb, sw, T + (2 * q + 1) * kb2, kb, sw, zero,
+                     X12 + q * kb2, kb, sw, nk, false);
+        if (e != hipSuccess) return e;
+        e = cgemm<R>(st, 'N', 'N', kb, kk2, kb, mone, T + 2 * q * kb2, kb, sw, X12 + q * kb2, kb, sw, zero,
+                     TB + q * 4 * kb2 + kb * ld2, ld2, sw, nk, false);
+        if (e != hipSuccess) return e;
+    }
+    // apply the 2kb-blocks, last first
+    for (int64_t q = npair - 1; q >= 0; --q) {
+        const int64_t c0 = 2 * q * kb;
+        const int kk = (int)((nref - c0) < 2 * kb ? (nref - c0) : 2 * kb);
         const int64_t r0 = c0 + 1, m = n - r0;
         const cx<R>* Vb = V + r0 + c0 * n;
         e = cgemm<R>(st, 'C', 'N', kk, n, m, one, Vb, n, sV, U + r0, ldu, sU, zero, W1, kk, sw, nk, false);
         if (e != hipSuccess) return e;
-        e = cgemm<R>(st, 'N', 'N', kk, n, kk, one, T + blk * kb2, kb, sw, W1, kk, sw, zero, W2, kk, sw, nk, false);
+        e = cgemm<R>(st, 'N', 'N', kk, n, kk, one, TB + q * 4 * kb2, ld2, sw, W1, kk, sw, zero, W2, kk, sw, nk, false);
         if (e != hipSuccess) return e;
         e = cgemm<R>(st, 'N', 'N', m, n, kk, mone, Vb, n, sV, W2, kk, sw, one, U + r0, ldu, sU, nk, false);
         if (e != hipSuccess) return e;
