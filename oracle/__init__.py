@@ -60,6 +60,7 @@ def _L():
                                     P, I]
         lib.or_fermi.argtypes = [I, I, P, I, P, D, D, D, P, P, I]
         lib.or_density.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, P, P]
+        lib.or_cholesky_inv.argtypes = [I, P, I, D, P, P]
         lib.or_density_entries.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, I, P, P, P]
         lib.or_max_threads.restype = I
         lib.or_set_threads.argtypes = [I]
@@ -271,3 +272,15 @@ def density_entries(Ccol, w, occ, wk, g, pairs, nocc=None):
     _L().or_density_entries(nk, n, nocc, _p(Ccol), n, n * n, _p(w), n, _p(occ), n, _p(wk), float(g), len(ab),
                             _p(ab), _p(r), _p(e))
     return r, e
+
+
+def cholesky_inv(S, s_tol: float = 1e-12):
+    """Part 2 variant (not the paper's method): S = L L^H (textbook Cholesky,
+    lower triangle read) and L^{-1} by forward substitution.  Returns
+    (status, L, Linv)."""
+    S = _colmajor(S)
+    n = S.shape[0]
+    L = np.zeros((n, n), dtype=np.complex128, order="F")
+    Li = np.zeros((n, n), dtype=np.complex128, order="F")
+    st = _L().or_cholesky_inv(n, _p(S), n, float(s_tol), _p(L), _p(Li))
+    return st, L, Li

@@ -650,3 +650,49 @@ void or_density_entries(int nk, int n, int nocc, const zc* C, int ldc, long sc, 
         edm[q] = g * se;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Part 2 variant (not the paper's method): S = L L^H by the textbook
+ * column-oriented Cholesky factorisation (lower, real positive diagonal),
+ * and the lower-triangular inverse L^{-1} by forward substitution on the
+ * identity.  X = L^{-H} satisfies X^H S X = I, so Parts 3 and 4 are then the
+ * same as with X = U diag(s)^{-1/2}.  S is read from its lower triangle.
+ * Returns OR_ENOTPD when a pivot d_j <= s_tol * max_i S_ii (or is not
+ * positive); L and Linv are full n x n, column-major, ld n, zero above the
+ * diagonal.
+ * ---------------------------------------------------------------------- */
+int or_cholesky_inv(int n, const zc* S, int lds, double s_tol, zc* L, zc* Linv)
+{
+    if (n < 1) return OR_EARG;
+    double smax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double d = creal(S[IX(i, i, lds)]);
+        if (d > smax) smax = d;
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) L[IX(i, j, n)] = (i >= j) ? S[IX(i, j, lds)] : 0.0;
+    for (int j = 0; j < n; ++j) {
+        double d = creal(L[IX(j, j, n)]);
+        for (int k = 0; k < j; ++k) {
+            const zc l = L[IX(j, k, n)];
+            d -= creal(l * conj(l));
+        }
+        if (!(d > s_tol * smax)) return OR_ENOTPD;
+        const double ljj = sqrt(d);
+        L[IX(j, j, n)] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            zc s = L[IX(i, j, n)];
+            for (int k = 0; k < j; ++k) s -= L[IX(i, k, n)] * conj(L[IX(j, k, n)]);
+            L[IX(i, j, n)] = s / ljj;
+        }
+    }
+    /* L Linv = I, column c: forward substitution */
+    for (int c = 0; c < n; ++c)
+        for (int i = 0; i < n; ++i) {
+            if (i < c) { Linv[IX(i, c, n)] = 0.0; continue; }
+            zc s = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s -= L[IX(i, k, n)] * Linv[IX(k, c, n)];
+            Linv[IX(i, c, n)] = s / L[IX(i, i, n)];
+        }
+    return OR_OK;
+}

@@ -147,3 +147,4 @@ def test_density_entries_match_full_matrices():
     r, e = O.density_entries(np.transpose(C, (0, 2, 1)), w, occ, wk, 2.0, pairs)
     for q, (a, b) in enumerate(pairs):
         assert r[q] == rho[a, b] and e[q] == E[a, b]
+
