@@ -3,15 +3,22 @@ eigensolve (Band_DFT_Col Parts 2-4) on one MI355X.
 
 One step = one call of kgev_solve_k_device on a batch of nk k-points of the
 magnetite-like LCAO workload (n = 2000, 16 k-points of the 4x4x4 grid,
-complex128, all eigenpairs), inputs resident in HBM.  Prints ONE JSON line.
+complex128, all eigenpairs), inputs resident in HBM, kernels launched one by
+one.  Prints ONE JSON line.
 
 Extra fields:
-  roofline      dominant kernel measured with HIP events (recorded by the
+  roofline      dominant kernel measured with HIP events recorded by the
                 library around each of its launches, on the stream it is
-                enqueued on) over the timed steps;
+                enqueued on, over the timed steps;
+  graph_replay  the same batch with the whole solve captured once as a HIP
+                graph and replayed (the kernels are the same; host launch
+                work disappears);
   cpu_baseline  the plain FP64 oracle on a bounded sample of the same work
                 (one of the k-points), timed on the host cores;
-  latency_ms    p50/p99 of single-k-point calls (nk = 1);
+  latency_ms    p50/p99 of single-k-point calls (nk = 1, kernel by kernel);
+  fp32_refine, cholesky_s
+                the mixed-precision form and the Cholesky form of Part 2 on
+                the same batch (kernel by kernel), with their residuals;
   check         residuals of one k-point and its eigenvalue error against the
                 oracle's.
 """
@@ -127,14 +134,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed steps of the FP32+refine form (0 skips it)")
+    ap.add_argument("--cholesky-steps", type=int, default=2,
+                    help="steps of the Cholesky form of Part 2 on the same batch (0 skips it)")
     ap.add_argument("--serve", type=int, default=0,
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-nmax", type=int, default=6000)
     ap.add_argument("--panel-nb", type=int, default=0,
                     help="Householder panel width (0: the library default, or the tuned width with --autotune)")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture the batched solve as one HIP graph on the first call and replay it")
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="steps of graph replay (the solve captured once as a HIP graph) reported beside the "
+                         "kernel-by-kernel headline; 0 skips it")
     ap.add_argument("--autotune", action="store_true",
                     help="run kgev_autotune for this n before timing (the tuned panel width is then used)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -171,21 +181,15 @@ def main():
     dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
     dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
     dst = torch.zeros(nk, dtype=torch.int32, device=dev)
-    opts = K.make_opts(panel_nb=args.panel_nb, use_graph=args.graph)
+    opts = K.make_opts(panel_nb=args.panel_nb)
     ctx = K.Context(0)
-    stream = torch.cuda.Stream() if args.graph else None
     tuned_nb = None
     if args.autotune:
         tuned_nb = K.autotune(ctx, n)
         log(f"[bench] autotuned panel width {tuned_nb}")
 
     def step():
-        if stream is not None:
-            with torch.cuda.stream(stream):
-                st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts,
-                                      stream=stream.cuda_stream)
-        else:
-            st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
+        st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
         if st != 0:
             raise RuntimeError(f"kgev_solve_k_device returned {st}")
 
@@ -209,20 +213,6 @@ def main():
     status = dst.cpu().numpy()
     log(f"[bench] {ms_per_step:.1f} ms/step, {value:.2f} solves/s, status {set(status.tolist())}")
     prof_elapsed, prof_note = elapsed, "the timed steps"
-    if args.graph:
-        # graph replays carry no per-launch events: the kernel is timed on one
-        # eager step with the same sizes and buffers
-        eager = K.make_opts(panel_nb=args.panel_nb)
-        K.profile_begin(ctx, phase)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=eager)
-        torch.cuda.synchronize()
-        prof_elapsed = time.perf_counter() - a
-        prof = K.profile_end(ctx)
-        if st != 0:
-            raise RuntimeError(f"eager profiling step returned {st}")
-        prof_note = "one eager step after the timed graph replays"
 
     avg_ms = prof["ms"] / max(prof["launches"], 1)
     if phase == K.PHASE_HEMV:
@@ -298,6 +288,67 @@ def main():
                  "eig_diff_vs_fp64_rel": float(np.abs(wmk - w0).max() / np.abs(w0).max())}
         log(f"[bench] FP32+refine {mixed['value']:.2f} solves/s")
 
+    # Part 2 in Cholesky form (X = L^-H) on the same batch, same accuracy gate
+    chol = None
+    if args.cholesky_steps > 0:
+        oc = K.make_opts(s_method=K.S_CHOLESKY)
+        wc = torch.zeros_like(dw)
+        Cc = torch.zeros_like(dC)
+        stc = torch.zeros_like(dst)
+
+        def cstep():
+            st = K.solve_k_device(ctx, dH, dS, n, n, nk, wc, Cc, n, d_status=stc, opts=oc)
+            if st != 0:
+                raise RuntimeError(f"Cholesky-form solve returned {st}")
+
+        log(f"[bench] Cholesky form: warmup 1, timing {args.cholesky_steps} steps")
+        cstep()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.cholesky_steps):
+            cstep()
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - a
+        wck = wc[0].cpu().numpy()
+        Cck = Cc[0].cpu().numpy().T
+        chol = {"value": nk * args.cholesky_steps / tc, "unit": "solves/s",
+                "ms_per_step": 1e3 * tc / args.cholesky_steps, "steps": args.cholesky_steps,
+                "status_all_ok": bool(np.all(stc.cpu().numpy() == 0)),
+                "r_res": float(np.linalg.norm(H0 @ Cck - S0 @ Cck * wck) / np.linalg.norm(H0)),
+                "r_orth": float(np.abs(Cck.conj().T @ S0 @ Cck - np.eye(n)).max()),
+                "eig_diff_vs_fp64_rel": float(np.abs(wck - w0).max() / np.abs(w0).max())}
+        log(f"[bench] Cholesky form {chol['value']:.2f} solves/s")
+
+    # the same batch in graph mode: captured once (untimed), then replayed
+    graph = None
+    if args.graph_steps > 0:
+        og = K.make_opts(panel_nb=args.panel_nb, use_graph=True)
+        gs = torch.cuda.Stream()
+        wg = torch.zeros_like(dw)
+        Cg = torch.zeros_like(dC)
+        stg = torch.zeros_like(dst)
+
+        def gstep():
+            with torch.cuda.stream(gs):
+                st = K.solve_k_device(ctx, dH, dS, n, n, nk, wg, Cg, n, d_status=stg, opts=og,
+                                      stream=gs.cuda_stream)
+            if st != 0:
+                raise RuntimeError(f"graph-mode solve returned {st}")
+
+        log(f"[bench] graph replay: capture, timing {args.graph_steps} replays")
+        gstep()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.graph_steps):
+            gstep()
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - a
+        graph = {"value": nk * args.graph_steps / tg, "unit": "solves/s",
+                 "ms_per_step": 1e3 * tg / args.graph_steps, "steps": args.graph_steps,
+                 "bitwise_equal_to_headline": bool(torch.equal(wg, dw) and torch.equal(Cg, dC)),
+                 "status_all_ok": bool(np.all(stg.cpu().numpy() == 0))}
+        log(f"[bench] graph replay {graph['value']:.2f} solves/s")
+
     serving = serve_stream(args, K, G, torch, dev) if args.serve > 0 else None
 
     cpu = None
@@ -322,8 +373,9 @@ def main():
         "config": {"workload": f"magnetite-like LCAO pencil H(k)C = S(k)C Lambda, n={n}, {nk} k-points of the "
                                "4x4x4 Monkhorst-Pack grid, complex128, all eigenpairs",
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
-                   "panel_nb": args.panel_nb or tuned_nb or 32, "graph": bool(args.graph)},
-        "roofline": roof, "cpu_baseline": cpu, "fp32_refine": mixed, "serving": serving,
+                   "panel_nb": args.panel_nb or tuned_nb or 32},
+        "roofline": roof, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "cholesky_s": chol,
+        "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,

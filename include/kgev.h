@@ -81,8 +81,20 @@ typedef struct {
                              not be the null stream); 0 (default): launch kernel by kernel */
     int32_t streams;      /* k-point groups solved concurrently, each on its own stream forked from
                              (and joined back into) the caller's stream: 0 = default, 1..8 */
-    int32_t reserved[6];  /* must be zero */
+    int32_t s_method;     /* Part 2: KGEV_S_EIG (default, the paper's diagonalisation of S,
+                             X = U s^-1/2, KGEV_ENOTPD when s_min <= s_tol s_max),
+                             KGEV_S_CHOLESKY (S = L L^H, X = L^-H: the same eigenpairs with a cheaper
+                             S side; a pivot <= s_tol * max_i S_ii gives KGEV_ENOTPD), or
+                             KGEV_S_PRUNE (the paper's diagonalisation; the n - n' directions with
+                             s_j <= s_tol s_max are dropped instead of failing: w[0:n'] are the
+                             reduced pencil's eigenvalues ascending, w[n':n] = +inf and columns
+                             n'..n-1 of C are zero) */
+    int32_t reserved[5];  /* must be zero */
 } kgev_opts;
+
+#define KGEV_S_EIG      0
+#define KGEV_S_CHOLESKY 1
+#define KGEV_S_PRUNE    2
 
 /* Fill *opts with the defaults listed above. */
 void kgev_opts_default(kgev_opts* opts);
@@ -282,7 +294,10 @@ void kgev_server_destroy(kgev_server* srv);
  * kgev_profile_end waits for the recorded events, returns the number of
  * launches, their summed duration in milliseconds and the summed algorithmic
  * bytes and flops, and stops recording.  Timing adds two event records per
- * launch of the chosen phase and nothing else.
+ * launch of the chosen phase and nothing else.  Launches captured into a
+ * graph (opts.use_graph) are not timed or counted, since the runtime does not
+ * time events recorded by graph nodes; both calls drop the context's cached
+ * graphs.
  */
 /*
  * Band_DFT_Col Part 5 (arXiv:1402.4247, the routine's outline in the

@@ -61,6 +61,7 @@ def _L():
         lib.or_fermi.argtypes = [I, I, P, I, P, D, D, D, P, P, I]
         lib.or_density.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, P, P]
         lib.or_cholesky_inv.argtypes = [I, P, I, D, P, P]
+        lib.or_solve_k_prune.argtypes = [I, P, I, P, I, D, P, P, I, P]
         lib.or_density_entries.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, I, P, P, P]
         lib.or_max_threads.restype = I
         lib.or_set_threads.argtypes = [I]
@@ -284,3 +285,18 @@ def cholesky_inv(S, s_tol: float = 1e-12):
     Li = np.zeros((n, n), dtype=np.complex128, order="F")
     st = _L().or_cholesky_inv(n, _p(S), n, float(s_tol), _p(L), _p(Li))
     return st, L, Li
+
+
+def solve_k_prune(H, S, s_tol: float = 1e-12, vectors: bool = True):
+    """Part 2 variant (not the paper's method): canonical orthogonalisation
+    with pruning of the directions with s_j <= s_tol s_max, then Parts 3-4 on
+    the reduced pencil.  Returns (status, nkeep, w, C) with w[nkeep:] = +inf
+    and the corresponding columns of C zero."""
+    H = _colmajor(H)
+    S = _colmajor(S)
+    n = H.shape[0]
+    w = np.zeros(n)
+    C = np.zeros((n, n), dtype=np.complex128, order="F") if vectors else None
+    nk = ctypes.c_int(0)
+    st = _L().or_solve_k_prune(n, _p(H), n, _p(S), n, float(s_tol), _p(w), _p(C), n, ctypes.byref(nk))
+    return st, nk.value, w, C

@@ -696,3 +696,55 @@ int or_cholesky_inv(int n, const zc* S, int lds, double s_tol, zc* L, zc* Linv)
         }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Part 2 variant (not the paper's method): canonical orthogonalisation with
+ * pruning.  S = U diag(s) U^H as in Part 2; the directions with
+ * s_j <= s_tol * s_max are dropped, X' = U(:, keep) diag(s_keep)^(-1/2)
+ * (n x n' with n' kept columns, taken in ascending order of s); then Parts 3
+ * and 4 on the reduced n' x n' matrix A' = X'^H H X': A' = Y' diag(w') Y'^H,
+ * C' = X' Y'.  Outputs: *nkeep = n', w[0:n'] ascending and w[n':n] = +inf,
+ * C (n x n, ld ldc) with columns 0..n'-1 = C' and the rest zero.
+ * ---------------------------------------------------------------------- */
+int or_solve_k_prune(int n, const zc* H, int ldh, const zc* S, int lds, double s_tol, double* w, zc* C, int ldc,
+                     int* nkeep)
+{
+    if (n < 1) return OR_EARG;
+    if (!lower_finite(n, H, ldh) || !lower_finite(n, S, lds)) return OR_ENONFINITE;
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    zc* U = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    zc* Hf = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    zc* G = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    zc* A = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    zc* Y = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    double* wr = (double*)malloc(sizeof(double) * (size_t)n);
+    int st = OR_ENOMEM;
+    if (!s || !U || !Hf || !G || !A || !Y || !wr) goto out;
+    st = or_eigen_hh(n, S, lds, s, U, NULL, NULL);
+    if (st != OR_OK) goto out;
+    int j0 = 0;
+    while (j0 < n && !(s[j0] > s_tol * s[n - 1])) ++j0;      /* s ascending: dropped ones first */
+    const int m = n - j0;
+    *nkeep = m;
+    for (int j = 0; j < m; ++j) {
+        const double f = 1.0 / sqrt(s[j0 + j]);
+        for (int i = 0; i < n; ++i) U[IX(i, j, n)] = U[IX(i, j0 + j, n)] * f;   /* X' in the first m columns */
+    }
+    herm_full(n, H, ldh, Hf);
+    if (m > 0) {
+        or_zgemm('N', 'N', n, m, n, 1.0, Hf, n, U, n, 0.0, G, n);
+        or_zgemm('C', 'N', m, m, n, 1.0, U, n, G, n, 0.0, A, m);
+        st = or_eigen_hh(m, A, m, wr, Y, NULL, NULL);
+        if (st != OR_OK) goto out;
+        or_zgemm('N', 'N', n, m, m, 1.0, U, n, Y, m, 0.0, G, n);
+    }
+    for (int j = 0; j < n; ++j) {
+        w[j] = j < m ? wr[j] : INFINITY;
+        if (C)
+            for (int i = 0; i < n; ++i) C[IX(i, j, ldc)] = j < m ? G[IX(i, j, n)] : 0.0;
+    }
+    st = OR_OK;
+out:
+    free(s); free(U); free(Hf); free(G); free(A); free(Y); free(wr);
+    return st;
+}

@@ -32,7 +32,7 @@ bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double
 // Everything that identifies a captured solve: sizes, options, buffers, stream.
 struct GraphKey {
     int64_t n, ld, nk, ldc;
-    int32_t precision, want_vectors, panel_nb, refine_iters, streams;
+    int32_t precision, want_vectors, panel_nb, refine_iters, streams, s_method;
     double s_tol;
     const void *H, *S, *w, *C, *work, *status, *stream;
     bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
@@ -75,7 +75,7 @@ struct SolvePlan {
     int nb, kb;
     int NBmax, CHmax, PN;
     // complex128 arrays
-    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, qpart, uwork;
+    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, qpart, uwork, cwork, ppart, ndrop;
     // real / int arrays
     size_t d, e, sS, wA, pnorm, Zr, Qs, Vsec;
     size_t dc_es, dc_onrm, dc_D0, dc_D1, dc_sd, dc_sz, dc_ndd, dc_ndz, dc_dfd, dc_rotc, dc_rots, dc_rho, dc_tauv,
@@ -119,6 +119,9 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.pvv = L.add(z * 2 * (size_t)p.NBmax * nbA * nk);
     p.qpart = L.add(r * (size_t)p.NBmax * p.CHmax * nk);
     p.uwork = L.add(z * (size_t)unmtr_work_elems(n, p.kb) * nk);
+    p.cwork = L.add(z * (size_t)chol_work_elems(n) * nk);
+    p.ppart = L.add(r * n * nk);
+    p.ndrop = L.add(i4 * nk);
     p.d = L.add(r * n * nk);
     p.e = L.add(r * n * nk);
     p.sS = L.add(r * n * nk);
@@ -254,7 +257,8 @@ bool opts_valid(const kgev_opts& o)
     if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
     if (o.use_graph != 0 && o.use_graph != 1) return false;
     if (o.streams < 1 || o.streams > 8) return false;
-    for (int q = 0; q < 6; ++q)
+    if (o.s_method != KGEV_S_EIG && o.s_method != KGEV_S_CHOLESKY && o.s_method != KGEV_S_PRUNE) return false;
+    for (int q = 0; q < 5; ++q)
         if (o.reserved[q] != 0) return false;
     return true;
 }
@@ -384,15 +388,24 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     // inputs: non-finite check on both, S copied into the working matrix
     KCHECK(copy_lower_check<double>(st, n, H, ld, ld * n, nullptr, 0, 0, status, nk));
     KCHECK(copy_lower_check<double>(st, n, S, ld, ld * n, Aw, n, nn, status, nk));
-    // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2)
-    kgev_status r = eigen_hh(p, w, st, sS, X, status);
-    if (r != KGEV_OK) return r;
-    KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk));
+    kgev_status r;
+    if (o.s_method == KGEV_S_CHOLESKY) {
+        // Part 2 in Cholesky form: S = L L^H, X = L^(-H) (L in Vs, L^(-1) in G)
+        KCHECK(cholesky_x(st, n, Aw, n, nn, Vs, G, X, at<double2>(w, p.cwork), sS, o.s_tol, status, nk));
+    } else {
+        // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2) (pruned: the
+        // columns with s_j <= s_tol s_max are zero)
+        r = eigen_hh(p, w, st, sS, X, status);
+        if (r != KGEV_OK) return r;
+        KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk, o.s_method == KGEV_S_PRUNE));
+    }
     // Part 3: A = X^H (H X), lower half
     KCHECK(hermitian_full(st, n, H, ld, ld * n, Vs, n, nn, nk));
     const double2 one = mk<double>(1, 0), zero = mk<double>(0, 0);
     KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, Vs, n, nn, X, n, nn, zero, G, n, nn, nk, false));
     KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, Aw, n, nn, nk, true));
+    if (o.s_method == KGEV_S_PRUNE)
+        KCHECK(prune_shift(st, n, Aw, nn, at<double>(w, p.ppart), sS, n, o.s_tol, at<int>(w, p.ndrop), nk));
     // Part 4: A = Y diag(lambda) Y^H, C = X Y
     if (o.precision == KGEV_PREC_FP32_REFINE) {
         r = eigen_hh_mixed(p, w, st, dw, G, status, o.refine_iters);
@@ -404,6 +417,8 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
         KCHECK(normalize_cols(st, n, G, n, nn, nullptr, 0, 0.0, nullptr, nk));
         KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, dC, ldc, ldc * n, nk, false));
     }
+    if (o.s_method == KGEV_S_PRUNE)
+        KCHECK(prune_finish(st, n, dw, o.want_vectors ? dC : nullptr, ldc, at<int>(w, p.ndrop), nk));
     if (d_status) KCHECK(status_finish(st, status, d_status, nk));
     return KGEV_OK;
 }
@@ -467,6 +482,15 @@ kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, vo
     }
     for (int q = 1; q < g.G; ++q) KCHECK(hipStreamWaitEvent(st, ctx->ev[q], 0));
     return KGEV_OK;
+}
+
+// Destroy every cached graph of the context (after the device is idle).
+void drop_graphs(kgev_ctx* ctx)
+{
+    if (ctx->graphs.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.second);
+    ctx->graphs.clear();
 }
 
 }  // namespace
@@ -586,7 +610,7 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     memset(&key, 0, sizeof(key));
     key.n = n; key.ld = ld; key.nk = nk; key.ldc = o.want_vectors ? ldc : 0;
     key.precision = o.precision; key.want_vectors = o.want_vectors; key.panel_nb = o.panel_nb;
-    key.refine_iters = o.refine_iters; key.streams = o.streams; key.s_tol = o.s_tol;
+    key.refine_iters = o.refine_iters; key.streams = o.streams; key.s_method = o.s_method; key.s_tol = o.s_tol;
     key.H = dH; key.S = dS; key.w = dw; key.C = o.want_vectors ? dC : nullptr; key.work = w; key.status = d_status;
     key.stream = stream;
     for (size_t q = 0; q < ctx->graphs.size(); ++q)
@@ -858,6 +882,7 @@ kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase)
     if (!ctx) return -1;
     if (phase != KGEV_PHASE_HEMV && phase != KGEV_PHASE_GEMM) return -2;
     DevGuard g(ctx->device);
+    drop_graphs(ctx);
     if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
     ctx->prof = prof_start(phase, 16384);
     return KGEV_OK;
@@ -871,6 +896,7 @@ kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms,
     DevGuard g(ctx->device);
     const bool ok = prof_stop(ctx->prof, launches, total_ms, alg_bytes, alg_flops);
     ctx->prof = nullptr;
+    drop_graphs(ctx);
     return ok ? KGEV_OK : KGEV_EDEVICE;
 }
 

@@ -550,10 +550,12 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
     // buffer offsets are 32-bit: the matrix (ld x n) must stay under 2 GiB
     const bool buf = buf_ok && (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
     // KGEV_HEMV_VARIANT = 10 * (min waves per SIMD) + (groups of 8 columns
-    // prefetched): 11 (default), 12, 30, 31, 40 (tuning experiments)
+    // prefetched): 30 (default: three workgroups per CU, each group loaded
+    // and consumed in turn; measured fastest on gfx950), 11, 12, 31, 40
+    // (tuning experiments)
     static const int variant = [] {
         const char* v = getenv("KGEV_HEMV_VARIANT");
-        return v ? atoi(v) : 11;
+        return v ? atoi(v) : 30;
     }();
     for (int p = 0; p <= n - 1; p += nb) {
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
@@ -568,8 +570,8 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const dim3 gz((unsigned)nch, (unsigned)nk);
             if (!buf)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 1, false, 1>), gz, dim3(256), 0, st, ws, i);
-            else if (variant == 30)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 0>), gz, dim3(256), 0, st, ws, i);
+            else if (variant == 11)
+                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
             else if (variant == 40)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 4, true, 0>), gz, dim3(256), 0, st, ws, i);
             else if (variant == 31)
@@ -577,7 +579,7 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             else if (variant == 12)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 2>), gz, dim3(256), 0, st, ws, i);
             else
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 0>), gz, dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);

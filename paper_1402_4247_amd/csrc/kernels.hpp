@@ -102,8 +102,15 @@ hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t
                            int64_t sd, int64_t nk);
 // columns to unit 2-norm, optionally divided by sqrt(s_j); with s given, also
 // sets status 1 when s_0 <= s_tol * s_{n-1}
+// (prune: a column with s_j <= s_tol s_{n-1} is zeroed instead, no status)
 hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
-                          int64_t ss, double s_tol, int* status, int64_t nk);
+                          int64_t ss, double s_tol, int* status, int64_t nk, int prune = 0);
+// pruned canonical orthogonalisation (util.hip): shift the dropped directions
+// of A above its spectrum; afterwards set their eigenvalues to +inf and
+// eigenvector columns to zero.  part: n doubles per k; ndrop: nk ints.
+hipError_t prune_shift(hipStream_t st, int64_t n, double2* A, int64_t sA, double* part, const double* s, int64_t sst,
+                       double s_tol, int* ndrop, int64_t nk);
+hipError_t prune_finish(hipStream_t st, int64_t n, double* w, double2* C, int64_t ldc, const int* ndrop, int64_t nk);
 hipError_t status_init(hipStream_t st, int* status, int64_t nk);
 // nk synthetic matrices (entries in [-1, 1), real diagonal) for timing runs
 template <typename R>
@@ -143,5 +150,13 @@ size_t density_work_bytes(int64_t n, int64_t nk, int64_t nocc);
 hipError_t density(hipStream_t st, const double2* C, int64_t ldc, int n, int nk, int nocc, const double* w,
                    int64_t ldw, const double* occ, int64_t ldo, const double* wk, double g, double2* rho,
                    double2* edm, int64_t ldr, void* work);
+
+// ---------------------------------------------------------------------------
+// Part 2 in Cholesky form (chol.hip): X = L^{-H} with S = L L^H.  A (the lower
+// copy of S) is overwritten; L, Linv, X are n x n (ld n, stride n*n); work
+// holds chol_work_elems(n) complex values per k; smax nk doubles.
+int64_t chol_work_elems(int64_t n);
+hipError_t cholesky_x(hipStream_t st, int64_t n, double2* A, int64_t lda, int64_t sA, double2* L, double2* Linv,
+                      double2* X, double2* work, double* smax, double s_tol, int* status, int64_t nk);
 
 }  // namespace kgev

@@ -26,10 +26,18 @@ static hipEvent_t next_event(Profiler* p)
     return p->pool[p->used++];
 }
 
+// Launches captured into a graph are not timed: the runtime does not time
+// events recorded by graph nodes.
+static bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 void prof_before(int phase, hipStream_t st)
 {
     Profiler* p = g_prof;
-    if (!p || p->phase != phase) return;
+    if (!p || p->phase != phase || capturing(st)) return;
     hipEvent_t e = next_event(p);
     if (e) (void)hipEventRecord(e, st);
 }
@@ -37,7 +45,7 @@ void prof_before(int phase, hipStream_t st)
 void prof_after(int phase, hipStream_t st, double bytes, double flops)
 {
     Profiler* p = g_prof;
-    if (!p || p->phase != phase) return;
+    if (!p || p->phase != phase || capturing(st)) return;
     hipEvent_t e = next_event(p);
     if (e) (void)hipEventRecord(e, st);
     p->launches += 1;

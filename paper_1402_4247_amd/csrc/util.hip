@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_real_to_complex(int64_t n, const double
 
 // one workgroup per column
 __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
-                                                       int64_t sst, double s_tol, int* status)
+                                                       int64_t sst, double s_tol, int* status, int prune)
 {
     __shared__ double sh[4];
     const int64_t b = blockIdx.y;
@@ -98,9 +98,12 @@ __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, i
     double f = 1.0 / sqrt(ss);
     if (s) {
         const double sj = s[b * sst + j];
+        const double smax = s[b * sst + n - 1];
         f = f / sqrt(sj);
-        if (j == 0 && threadIdx.x == 0 && status) {
-            const double smax = s[b * sst + n - 1];
+        if (prune) {
+            // a pruned direction: its column of X is zero
+            if (!(sj > s_tol * smax)) f = 0.0;
+        } else if (j == 0 && threadIdx.x == 0 && status) {
             if (!(sj > s_tol * smax)) atomicOr(status + b, ST_NOTPD);
         }
     }
@@ -244,10 +247,84 @@ hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t
 }
 
 hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s, int64_t ss,
-                          double s_tol, int* status, int64_t nk)
+                          double s_tol, int* status, int64_t nk, int prune)
 {
     hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, U, ldu, su, s, ss,
-                       s_tol, status);
+                       s_tol, status, prune);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pruned canonical orthogonalisation.  The s_j <= s_tol s_max directions are
+// the first ndrop columns of X (s ascending) and are zero there, so rows and
+// columns 0..ndrop-1 of A = X^H H X are zero; their diagonal is set to
+// big = 2 ||A||_F + 1, above the spectrum of the kept block, which sorts
+// their eigenvalues last and leaves them decoupled.  At the end those
+// eigenvalues become +inf and their eigenvector columns zero.
+namespace {
+__global__ __launch_bounds__(256) void k_prune_colnorm(int64_t n, const double2* A, int64_t sA, double* part)
+{
+    __shared__ double sh[4];
+    const int64_t b = blockIdx.y, j = blockIdx.x;
+    const double2* a = A + b * sA + j * n;
+    double acc = 0.0;
+    for (int64_t i = j + threadIdx.x; i < n; i += 256) {
+        const double2 v = a[i];
+        acc = fma(i > j ? 2.0 : 1.0, fma(v.x, v.x, v.y * v.y), acc);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[b * n + j] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_prune_shift(int64_t n, double2* A, int64_t sA, const double* part,
+                                                     const double* s, int64_t sst, double s_tol, int* ndrop)
+{
+    __shared__ double sh[4];
+    __shared__ int sc[4];
+    const int64_t b = blockIdx.x;
+    const double smax = s[b * sst + n - 1];
+    double acc = 0.0;
+    int cnt = 0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        acc += part[b * n + j];
+        cnt += !(s[b * sst + j] > s_tol * smax);
+    }
+    acc = wave_sum(acc);
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, WAVE);
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = acc;
+        sc[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    const double big = 2.0 * sqrt((sh[0] + sh[1]) + (sh[2] + sh[3])) + 1.0;
+    const int nd = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+    for (int64_t j = threadIdx.x; j < nd; j += 256) A[b * sA + j + j * n] = mk<double>(big, 0.0);
+    if (threadIdx.x == 0) ndrop[b] = nd;
+}
+
+__global__ __launch_bounds__(256) void k_prune_finish(int64_t n, double* w, double2* C, int64_t ldc, const int* ndrop)
+{
+    const int64_t b = blockIdx.y, j = blockIdx.x;
+    if (j < n - ndrop[b]) return;
+    if (threadIdx.x == 0) w[b * n + j] = INFINITY;
+    if (C)
+        for (int64_t i = threadIdx.x; i < n; i += 256) C[b * ldc * n + j * ldc + i] = mk<double>(0.0, 0.0);
+}
+}  // namespace
+
+hipError_t prune_shift(hipStream_t st, int64_t n, double2* A, int64_t sA, double* part, const double* s, int64_t sst,
+                       double s_tol, int* ndrop, int64_t nk)
+{
+    hipLaunchKernelGGL(k_prune_colnorm, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, A, sA, part);
+    hipLaunchKernelGGL(k_prune_shift, dim3((unsigned)nk), dim3(256), 0, st, n, A, sA, part, s, sst, s_tol, ndrop);
+    return hipGetLastError();
+}
+
+hipError_t prune_finish(hipStream_t st, int64_t n, double* w, double2* C, int64_t ldc, const int* ndrop, int64_t nk)
+{
+    hipLaunchKernelGGL(k_prune_finish, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, w, C, ldc, ndrop);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
                 ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("s_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("streams", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("s_method", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
@@ -58,6 +58,7 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
            "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
+S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
 
 
 def _load():
@@ -135,11 +136,12 @@ def _check(fn, st):
 
 
 def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0,
-              use_graph=False, streams=0) -> Opts:
+              use_graph=False, streams=0, s_method=0) -> Opts:
     o = Opts()
     lib.kgev_opts_default(ctypes.byref(o))
     o.use_graph = 1 if use_graph else 0
     o.streams = streams
+    o.s_method = s_method
     o.precision = precision
     o.want_vectors = 1 if want_vectors else 0
     o.panel_nb = panel_nb
