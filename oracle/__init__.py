@@ -61,6 +61,7 @@ def _L():
         lib.or_fermi.argtypes = [I, I, P, I, P, D, D, D, P, P, I]
         lib.or_density.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, P, P]
         lib.or_cholesky_inv.argtypes = [I, P, I, D, P, P]
+        lib.or_bloch.argtypes = [I, P, I, P, P, P, P, P, P, I, P, P]
         lib.or_solve_k_prune.argtypes = [I, P, I, P, I, D, P, P, I, P]
         lib.or_density_entries.argtypes = [I, I, I, P, I, ctypes.c_long, P, I, P, I, P, D, I, P, P, P]
         lib.or_max_threads.restype = I
@@ -300,3 +301,27 @@ def solve_k_prune(H, S, s_tol: float = 1e-12, vectors: bool = True):
     nk = ctypes.c_int(0)
     st = _L().or_solve_k_prune(n, _p(H), n, _p(S), n, float(s_tol), _p(w), _p(C), n, ctypes.byref(nk))
     return st, nk.value, w, C
+
+
+def bloch(off, blocks, R, kf):
+    """Band_DFT_Col Part 1: M(k) = sum over blocks (I, J, r, M_IJ) of
+    exp(2 pi i k.R[r]) M_IJ placed at rows off[I].., columns off[J]..
+    (fractional coordinates).  Returns (nk, n, n) mathematical matrices."""
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int32))
+    natom = len(off) - 1
+    n = int(off[-1])
+    bi = np.ascontiguousarray([b[0] for b in blocks], dtype=np.int32)
+    bj = np.ascontiguousarray([b[1] for b in blocks], dtype=np.int32)
+    rid = np.ascontiguousarray([b[2] for b in blocks], dtype=np.int32)
+    sizes = [np.asarray(b[3]).size for b in blocks]
+    doff = np.ascontiguousarray(np.concatenate([[0], np.cumsum(sizes)[:-1]]) if blocks else np.zeros(0),
+                                dtype=np.int64)
+    data = np.ascontiguousarray(np.concatenate([np.asfortranarray(np.asarray(b[3], dtype=np.complex128)).ravel(order="F")
+                                                for b in blocks]) if blocks else np.zeros(1, dtype=np.complex128))
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(-1, 3))
+    kf = np.ascontiguousarray(np.asarray(kf, dtype=np.float64).reshape(-1, 3))
+    nk = len(kf)
+    out = np.zeros((nk, n, n), dtype=np.complex128)      # per k column-major
+    _L().or_bloch(natom, _p(off), len(blocks), _p(bi), _p(bj), _p(rid), _p(doff), _p(data), _p(R), nk, _p(kf),
+                  _p(out))
+    return np.swapaxes(out, 1, 2).copy()

@@ -748,3 +748,33 @@ out:
     free(s); free(U); free(Hf); free(G); free(A); free(Y); free(wr);
     return st;
 }
+
+/* ------------------------------------------------------------------------
+ * Band_DFT_Col Part 1 (k-point dependence of H and S).  The paper names the
+ * step only; the reading is the Bloch sum over real-space blocks,
+ *   M(k)_{IJ} = sum over the blocks (I, J, R) of exp(2 pi i k.R) M_{IJ}(R),
+ * with k and R in fractional (reciprocal / direct lattice) coordinates.
+ * Atoms I have orbitals off[I] .. off[I+1]-1.  Block q (q < nblocks) is the
+ * pair (bi[q], bj[q]) at lattice vector R[rid[q]] (3 doubles), with data at
+ * data + doff[q] (n_I x n_J, column-major).  Out: nk matrices n x n (ld n),
+ * zero where no block contributes; blocks are added in index order.
+ * ---------------------------------------------------------------------- */
+void or_bloch(int natom, const int* off, int nblocks, const int* bi, const int* bj, const int* rid,
+              const long* doff, const zc* data, const double* R, int nk, const double* kf, zc* out)
+{
+    const int n = off[natom];
+    for (size_t q = 0; q < (size_t)nk * n * n; ++q) out[q] = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        zc* Ok = out + (size_t)k * n * n;
+        for (int q = 0; q < nblocks; ++q) {
+            const double* r = R + 3 * (size_t)rid[q];
+            const double ph = 2.0 * M_PI * (kf[3 * k] * r[0] + kf[3 * k + 1] * r[1] + kf[3 * k + 2] * r[2]);
+            const zc e = cos(ph) + I * sin(ph);
+            const int I0 = off[bi[q]], ni = off[bi[q] + 1] - I0;
+            const int J0 = off[bj[q]], nj = off[bj[q] + 1] - J0;
+            const zc* M = data + doff[q];
+            for (int c = 0; c < nj; ++c)
+                for (int a = 0; a < ni; ++a) Ok[IX(I0 + a, J0 + c, n)] += e * M[IX(a, c, ni)];
+        }
+    }
+}

@@ -152,6 +152,40 @@ class LcaoSystem:
         else:
             self.c = 0.5                      # a single orbital: W = 0
 
+    def real_space_blocks(self):
+        """The pseudo-crystal in real space, for a Bloch sum (Band_DFT_Col
+        Part 1): orbital offsets per atom, the lattice vectors in units of a,
+        and for every atom pair I >= J its block of H and of S at the pair's
+        minimum-image lattice vector R_IJ.  The Bloch sum of these blocks
+        reproduces the lower triangles of hs(k) for every k (the diagonal
+        blocks are given in full and are Hermitian)."""
+        natom = len(self.counts)
+        off = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int32)
+        Rint = np.rint(self.R_atom / CELL_A).astype(np.int64)
+        keys = {}
+        Rlist = []
+        hb, sb = [], []
+        for I in range(natom):
+            for J in range(I + 1):
+                key = tuple(Rint[I, J])
+                if key not in keys:
+                    keys[key] = len(Rlist)
+                    Rlist.append(key)
+                r = keys[key]
+                rows = slice(off[I], off[I + 1])
+                cols = slice(off[J], off[J + 1])
+                r2 = self.r2[rows, cols]
+                Hb = -np.exp(-r2 / 3.0) * self.v[rows, cols]
+                if I == J:
+                    Hb = Hb.copy()
+                    np.fill_diagonal(Hb, self.diagH[rows])
+                    Sb = np.eye(off[I + 1] - off[I], dtype=np.complex128)
+                else:
+                    Sb = self.c * np.exp(-r2 / 4.0) * self.u[rows, cols]
+                hb.append((I, J, r, Hb))
+                sb.append((I, J, r, Sb))
+        return off, np.array(Rlist, dtype=np.float64), hb, sb
+
     def hs(self, kfrac):
         """(H(k), S(k)) for k = kfrac * 2 pi / a."""
         n = self.n
