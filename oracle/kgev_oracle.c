@@ -308,12 +308,18 @@ int or_tridiag_ql(int n, double* d, const double* e_in, double* Z, int ldz)
             for (int i = 0; i < n; ++i) Z[IX(i, j, ldz)] = (i == j) ? 1.0 : 0.0;
 
     int status = OR_OK;
+    /* Deflation is tested against the running norm tst1 = max(|d_l| + |e_l|)
+     * over the rows reached so far, as in the published QL algorithm (tql2):
+     * a coupling below eps * tst1 is within the rounding already committed,
+     * and clusters of eigenvalues near zero deflate as readily as others. */
+    double tst1 = 0.0;
     for (int l = 0; l < n && status == OR_OK; ++l) {
         int sweeps = 0;
+        tst1 = fmax(tst1, fabs(d[l]) + fabs(e[l]));
         for (;;) {
             /* Smallest m >= l whose coupling to m+1 is negligible. */
             int m = l;
-            while (m < n - 1 && fabs(e[m]) > eps * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
+            while (m < n - 1 && fabs(e[m]) > eps * tst1) ++m;
             if (m == l) break;
             if (++sweeps > 30) { status = OR_ENOCONV; break; }
             /* Shift: eigenvalue of the leading 2x2 block nearer d_l. */
