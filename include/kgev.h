@@ -348,6 +348,32 @@ kgev_status kgev_density_device(kgev_ctx* ctx, const kgev_z* dC, int64_t ldc, in
                                 double g, kgev_z* d_rho, kgev_z* d_edm, int64_t ldr, void* dwork, size_t work_bytes,
                                 void* stream);
 
+/*
+ * Band_DFT_Col Part 1 (the routine's outline: giving S and H their k-point
+ * dependence), on the device, as the Bloch sum of real-space blocks:
+ *   out_k = sum over blocks q of exp(2 pi i kf_k . R_{rid[q]}) M_q
+ * with M_q placed at rows off[bi[q]].., columns off[bj[q]].. (k and R in
+ * fractional coordinates: reciprocal and direct lattice units).
+ *   off     : host, natom+1 orbital offsets per atom, off[0] = 0, n = off[natom]
+ *   bi, bj, rid, doff : host, nblocks entries, sorted by (bi, bj); block q's
+ *             data is d_data + doff[q], (n_bi x n_bj) column-major
+ *   d_data  : device, data_elems kgev_z
+ *   R       : host, nR x 3 doubles;  kf : host, nk x 3 doubles
+ *   d_out   : device, nk matrices n x n (ld n); entries no block covers are
+ *             zero.  The solver reads lower triangles, so blocks with bi >= bj
+ *             (diagonal blocks Hermitian) suffice for kgev_solve_k_device.
+ * The metadata is validated on the host (indices, offsets against
+ * data_elems, order) and copied to the device on `stream` before the call
+ * returns; the sum itself is asynchronous.  Returns -1 ctx, -2 natom/off,
+ * -3 off not a valid layout (or n > 65535), -4 nblocks or order, -5 bi/bj,
+ * -7 rid, -8 doff, -10 data_elems, -11 nR/R, -13 nk/kf, -15 d_out,
+ * KGEV_ENOMEM / KGEV_EDEVICE, else KGEV_OK.
+ */
+kgev_status kgev_bloch_device(kgev_ctx* ctx, int32_t natom, const int32_t* off, int64_t nblocks, const int32_t* bi,
+                              const int32_t* bj, const int32_t* rid, const int64_t* doff, const kgev_z* d_data,
+                              int64_t data_elems, int64_t nR, const double* R, int64_t nk, const double* kf,
+                              kgev_z* d_out, void* stream);
+
 #define KGEV_PHASE_HEMV 1
 #define KGEV_PHASE_GEMM 2
 kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase);

@@ -877,6 +877,77 @@ kgev_status kgev_density_device(kgev_ctx* ctx, const kgev_z* dC, int64_t ldc, in
     return KGEV_OK;
 }
 
+kgev_status kgev_bloch_device(kgev_ctx* ctx, int32_t natom, const int32_t* off, int64_t nblocks, const int32_t* bi,
+                              const int32_t* bj, const int32_t* rid, const int64_t* doff, const kgev_z* d_data,
+                              int64_t data_elems, int64_t nR, const double* R, int64_t nk, const double* kf,
+                              kgev_z* d_out, void* stream)
+{
+    if (!ctx) return -1;
+    if (natom < 1 || !off) return -2;
+    if (off[0] != 0) return -3;
+    for (int32_t a = 0; a < natom; ++a)
+        if (off[a + 1] < off[a]) return -3;
+    const int64_t n = off[natom];
+    if (n < 1 || n > 65535) return -3;
+    if (nblocks < 0) return -4;
+    if (nblocks > 0 && (!bi || !bj || !rid || !doff || !d_data)) return -5;
+    if (data_elems < 0) return -10;
+    if (nR < 0 || (nR > 0 && !R)) return -11;
+    if (nk < 1 || !kf) return -13;
+    if (!d_out) return -15;
+    // validate every block and group consecutive blocks of one atom pair
+    std::vector<int32_t> gptr;
+    for (int64_t q = 0; q < nblocks; ++q) {
+        if (bi[q] < 0 || bi[q] >= natom || bj[q] < 0 || bj[q] >= natom) return -5;
+        if (rid[q] < 0 || rid[q] >= nR) return -7;
+        const int64_t sz = (int64_t)(off[bi[q] + 1] - off[bi[q]]) * (off[bj[q] + 1] - off[bj[q]]);
+        if (doff[q] < 0 || doff[q] + sz > data_elems) return -8;
+        if (q > 0) {
+            const bool same = bi[q] == bi[q - 1] && bj[q] == bj[q - 1];
+            const bool after = bi[q] > bi[q - 1] || (bi[q] == bi[q - 1] && bj[q] > bj[q - 1]);
+            if (!same && !after) return -4;      // blocks must be sorted by (I, J)
+            if (!same) gptr.push_back((int32_t)q);
+        } else {
+            gptr.push_back(0);
+        }
+    }
+    gptr.push_back((int32_t)nblocks);
+    const int64_t ngroups = nblocks > 0 ? (int64_t)gptr.size() - 1 : 0;
+    DevGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // metadata: one stream-ordered allocation, freed after the kernels
+    Layout L;
+    const size_t o_off = L.add(sizeof(int32_t) * (natom + 1)), o_gp = L.add(sizeof(int32_t) * gptr.size()),
+                 o_bi = L.add(sizeof(int32_t) * nblocks), o_bj = L.add(sizeof(int32_t) * nblocks),
+                 o_rid = L.add(sizeof(int32_t) * nblocks), o_doff = L.add(sizeof(int64_t) * nblocks),
+                 o_R = L.add(sizeof(double) * 3 * nR), o_k = L.add(sizeof(double) * 3 * nk),
+                 o_ph = L.add(sizeof(double2) * nk * nR);
+    std::vector<char> host(L.total);
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+        if (bytes) memcpy(host.data() + o, src, bytes);
+    };
+    put(o_off, off, sizeof(int32_t) * (natom + 1));
+    put(o_gp, gptr.data(), sizeof(int32_t) * gptr.size());
+    put(o_bi, bi, sizeof(int32_t) * nblocks);
+    put(o_bj, bj, sizeof(int32_t) * nblocks);
+    put(o_rid, rid, sizeof(int32_t) * nblocks);
+    put(o_doff, doff, sizeof(int64_t) * nblocks);
+    put(o_R, R, sizeof(double) * 3 * nR);
+    put(o_k, kf, sizeof(double) * 3 * nk);
+    char* dm = nullptr;
+    if (hipMallocAsync((void**)&dm, L.total, st) != hipSuccess) return KGEV_ENOMEM;
+    KCHECK(hipMemcpyAsync(dm, host.data(), L.total, hipMemcpyHostToDevice, st));
+    KCHECK(hipStreamSynchronize(st));          // the host staging may go out of scope
+    const hipError_t e = bloch_sum(st, (int)n, (const int*)(dm + o_off), ngroups, (const int*)(dm + o_gp),
+                                   (const int*)(dm + o_bi), (const int*)(dm + o_bj), (const int*)(dm + o_rid),
+                                   (const int64_t*)(dm + o_doff), (const double2*)d_data, nR,
+                                   (const double*)(dm + o_R), nk, (const double*)(dm + o_k), (double2*)(dm + o_ph),
+                                   (double2*)d_out);
+    (void)hipFreeAsync(dm, st);
+    if (e != hipSuccess) return KGEV_EDEVICE;
+    return KGEV_OK;
+}
+
 kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase)
 {
     if (!ctx) return -1;

@@ -159,4 +159,12 @@ int64_t chol_work_elems(int64_t n);
 hipError_t cholesky_x(hipStream_t st, int64_t n, double2* A, int64_t lda, int64_t sA, double2* L, double2* Linv,
                       double2* X, double2* work, double* smax, double s_tol, int* status, int64_t nk);
 
+// ---------------------------------------------------------------------------
+// Band_DFT_Col Part 1 (bloch.hip): Bloch sum of real-space blocks grouped by
+// atom pair (group g = blocks gptr[g] .. gptr[g+1]-1); all index arrays on
+// the device and already validated; ph: nk x nR complex scratch.
+hipError_t bloch_sum(hipStream_t st, int n, const int* off, int64_t ngroups, const int* gptr, const int* bi,
+                     const int* bj, const int* rid, const int64_t* doff, const double2* data, int64_t nR,
+                     const double* R, int64_t nk, const double* kf, double2* ph, double2* out);
+
 }  // namespace kgev

@@ -56,7 +56,7 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
-           "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device"]
+           "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
 
@@ -101,6 +101,8 @@ def _load():
     lib.kgev_density_device.argtypes = [P, P, I64, I64, I64, I64, P, I64, P, I64, P, D, P, P, I64, P,
                                         ctypes.c_size_t, P]
     lib.kgev_density_device.restype = I32
+    lib.kgev_bloch_device.argtypes = [P, I32, P, I64, P, P, P, P, P, I64, I64, P, I64, P, P, P]
+    lib.kgev_bloch_device.restype = I32
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
@@ -268,6 +270,24 @@ def density_device(ctx, dC, n, nk, nocc, dw, d_occ, d_wk, g, d_rho, d_edm=None, 
                                    n if ldw is None else ldw, _ptr(d_occ), n if ldo is None else ldo, _ptr(d_wk),
                                    float(g), _ptr(d_rho), _ptr(d_edm), n if ldr is None else ldr, _ptr(dwork),
                                    int(work_bytes), _stream(stream))
+
+
+def bloch_device(ctx, off, blocks, d_data, R, kf, d_out, stream=None) -> int:
+    """kgev_bloch_device: Band_DFT_Col Part 1.  ``blocks`` is a list of
+    (I, J, r, doff) sorted by (I, J) with the block data at d_data + doff;
+    off, R (nR x 3) and kf (nk x 3) are host arrays."""
+    import numpy as np
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    bi = np.ascontiguousarray([b[0] for b in blocks], dtype=np.int32)
+    bj = np.ascontiguousarray([b[1] for b in blocks], dtype=np.int32)
+    rid = np.ascontiguousarray([b[2] for b in blocks], dtype=np.int32)
+    doff = np.ascontiguousarray([b[3] for b in blocks], dtype=np.int64)
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
+    kf = np.ascontiguousarray(kf, dtype=np.float64).reshape(-1, 3)
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+    return lib.kgev_bloch_device(ctx.handle, len(off) - 1, hp(off), len(blocks), hp(bi), hp(bj), hp(rid), hp(doff),
+                                 _ptr(d_data), d_data.numel(), len(R), hp(R), len(kf), hp(kf), _ptr(d_out),
+                                 _stream(stream))
 
 
 def profile_begin(ctx, phase) -> None:
