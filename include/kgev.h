@@ -167,6 +167,30 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
                                 const kgev_opts* opts, void* stream);
 
 /*
+ * The per-k solve with the S-orthonormaliser X of Part 2 exported or reused.
+ * Band_DFT_Col solves every k-point twice per step (eigenvalues, then
+ * eigenvectors) and, spin-collinear, once per spin with the same S(k); Part 2
+ * depends on S(k) only, so its X can be formed once and reused.
+ *   dX     : device, nk matrices n x n (ld n, k-stride n*n)
+ *   x_mode : KGEV_X_EXPORT - Part 2 from dS as in kgev_solve_k_device, and its
+ *            X written to dX;  KGEV_X_REUSE - Part 2 skipped, X read from dX
+ *            (as exported by an earlier call with the same S(k)); dS is not
+ *            read (may be NULL) and no S-definiteness status is reported.
+ * The other arguments, results and statuses are as for kgev_solve_k_device
+ * (kernels are launched one by one; opts.use_graph and opts.streams are
+ * ignored; KGEV_X_REUSE with KGEV_S_PRUNE is KGEV_EUNSUPPORTED).  The
+ * workspace is kgev_workspace_bytes(n, nk, opts) with opts.streams = 1.
+ * Returns -1 ctx, -2 dH, -3 dS (export), -4 n, -5 ld, -6 nk, -7 dw, -8 dC/ldc,
+ * -10 dX, -11 x_mode, -13 work too small, -15 opts invalid.
+ */
+#define KGEV_X_EXPORT 0
+#define KGEV_X_REUSE  1
+kgev_status kgev_solve_k_x_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
+                                  int64_t nk, double* dw, kgev_z* dC, int64_t ldc, kgev_z* dX, int32_t x_mode,
+                                  void* dwork, size_t work_bytes, int32_t* d_status, const kgev_opts* opts,
+                                  void* stream);
+
+/*
  * Stage entry points.  Each runs one step of the path on nk problems and
  * exists so that every step can be checked on its own; all are device-pointer
  * and asynchronous on `stream`, with the argument conventions above.

@@ -374,8 +374,11 @@ kgev_status eigen_hh_mixed(const SolvePlan& p, void* w, hipStream_t st, double* 
     return KGEV_OK;
 }
 
+// Xin: Part 2 skipped and this X (n x n per k, ld n) used; Xout: the X of
+// Part 2 also written there.
 kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStream_t st, const double2* H,
-                         const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status)
+                         const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status,
+                         const double2* Xin = nullptr, double2* Xout = nullptr)
 {
     const int64_t n = p.n, nk = p.nk, nn = n * n;
     int* status = at<int>(w, p.status);
@@ -387,18 +390,23 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     KCHECK(status_init(st, status, nk));
     // inputs: non-finite check on both, S copied into the working matrix
     KCHECK(copy_lower_check<double>(st, n, H, ld, ld * n, nullptr, 0, 0, status, nk));
-    KCHECK(copy_lower_check<double>(st, n, S, ld, ld * n, Aw, n, nn, status, nk));
     kgev_status r;
-    if (o.s_method == KGEV_S_CHOLESKY) {
-        // Part 2 in Cholesky form: S = L L^H, X = L^(-H) (L in Vs, L^(-1) in G)
-        KCHECK(cholesky_x(st, n, Aw, n, nn, Vs, G, X, at<double2>(w, p.cwork), sS, o.s_tol, status, nk));
+    if (Xin) {
+        X = const_cast<double2*>(Xin);        // Part 2 done by an earlier call
     } else {
-        // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2) (pruned: the
-        // columns with s_j <= s_tol s_max are zero)
-        r = eigen_hh(p, w, st, sS, X, status);
-        if (r != KGEV_OK) return r;
-        KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk, o.s_method == KGEV_S_PRUNE));
+        KCHECK(copy_lower_check<double>(st, n, S, ld, ld * n, Aw, n, nn, status, nk));
+        if (o.s_method == KGEV_S_CHOLESKY) {
+            // Part 2 in Cholesky form: S = L L^H, X = L^(-H) (L in Vs, L^(-1) in G)
+            KCHECK(cholesky_x(st, n, Aw, n, nn, Vs, G, X, at<double2>(w, p.cwork), sS, o.s_tol, status, nk));
+        } else {
+            // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2) (pruned: the
+            // columns with s_j <= s_tol s_max are zero)
+            r = eigen_hh(p, w, st, sS, X, status);
+            if (r != KGEV_OK) return r;
+            KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk, o.s_method == KGEV_S_PRUNE));
+        }
     }
+    if (Xout) KCHECK(hipMemcpyAsync(Xout, X, sizeof(double2) * (size_t)nn * nk, hipMemcpyDeviceToDevice, st));
     // Part 3: A = X^H (H X), lower half
     KCHECK(hermitian_full(st, n, H, ld, ld * n, Vs, n, nn, nk));
     const double2 one = mk<double>(1, 0), zero = mk<double>(0, 0);
@@ -642,6 +650,44 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     ctx->graphs.push_back({key, exec});
     KCHECK(hipGraphLaunch(exec, st));
     return KGEV_OK;
+}
+
+kgev_status kgev_solve_k_x_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
+                                  int64_t nk, double* dw, kgev_z* dC, int64_t ldc, kgev_z* dX, int32_t x_mode,
+                                  void* dwork, size_t work_bytes, int32_t* d_status, const kgev_opts* opts,
+                                  void* stream)
+{
+    if (!ctx) return -1;
+    if (!dH) return -2;
+    if (x_mode != KGEV_X_EXPORT && x_mode != KGEV_X_REUSE) return -11;
+    if (!dS && x_mode == KGEV_X_EXPORT) return -3;
+    if (n < 1) return -4;
+    if (ld < n) return -5;
+    if (nk < 1) return -6;
+    if (!dw) return -7;
+    if (!dX) return -10;
+    kgev_opts o = resolve_opts(opts);
+    if ((!opts || opts->panel_nb == 0)) {
+        auto it = ctx->tuned_nb.find({n, o.precision});
+        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
+    }
+    if (!opts_valid(o)) return -15;
+    if (o.want_vectors && (!dC || ldc < n)) return -8;
+    if (x_mode == KGEV_X_REUSE && o.s_method == KGEV_S_PRUNE) return KGEV_EUNSUPPORTED;
+    DevGuard g(ctx->device);
+    SolvePlan p = make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+    void* w = dwork;
+    if (w) {
+        if (work_bytes < p.total) return -13;
+    } else {
+        kgev_status r = ensure_work(ctx, p.total);
+        if (r != KGEV_OK) return r;
+        w = ctx->work;
+    }
+    return solve_device(p, o, w, (hipStream_t)stream, (const double2*)dH, (const double2*)dS, ld, dw,
+                        o.want_vectors ? (double2*)dC : nullptr, ldc, d_status,
+                        x_mode == KGEV_X_REUSE ? (const double2*)dX : nullptr,
+                        x_mode == KGEV_X_EXPORT ? (double2*)dX : nullptr);
 }
 
 kgev_status kgev_solve_k(kgev_ctx* ctx, const kgev_z* H, const kgev_z* S, int64_t n, int64_t nk, double* w,

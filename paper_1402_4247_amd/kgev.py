@@ -56,7 +56,8 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
-           "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device"]
+           "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device",
+           "kgev_solve_k_x_device"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
 
@@ -103,6 +104,9 @@ def _load():
     lib.kgev_density_device.restype = I32
     lib.kgev_bloch_device.argtypes = [P, I32, P, I64, P, P, P, P, P, I64, I64, P, I64, P, P, P]
     lib.kgev_bloch_device.restype = I32
+    lib.kgev_solve_k_x_device.argtypes = [P, P, P, I64, I64, I64, P, P, I64, P, I32, P, ctypes.c_size_t, P,
+                                          ctypes.POINTER(Opts), P]
+    lib.kgev_solve_k_x_device.restype = I32
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
@@ -210,6 +214,18 @@ def solve_k_device(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, dwork=None, wor
     return lib.kgev_solve_k_device(ctx.handle, _ptr(dH), _ptr(dS), n, ld, nk, _ptr(dw), _ptr(dC), ldc,
                                    _ptr(dwork), work_bytes, _ptr(d_status),
                                    None if opts is None else ctypes.byref(opts), _stream(stream))
+
+
+X_EXPORT, X_REUSE = 0, 1
+
+
+def solve_k_x_device(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, dX, x_mode, dwork=None, work_bytes=0,
+                     d_status=None, opts: Opts | None = None, stream=None) -> int:
+    """kgev_solve_k_x_device: the per-k solve exporting (X_EXPORT) or reusing
+    (X_REUSE) Part 2's S-orthonormaliser X."""
+    return lib.kgev_solve_k_x_device(ctx.handle, _ptr(dH), _ptr(dS), n, ld, nk, _ptr(dw), _ptr(dC), ldc, _ptr(dX),
+                                     int(x_mode), _ptr(dwork), work_bytes, _ptr(d_status),
+                                     None if opts is None else ctypes.byref(opts), _stream(stream))
 
 
 def solve_k(ctx: Context, H, S, n, nk, w, C, opts: Opts | None = None):
