@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--nk", type=int, default=16)
     ap.add_argument("--seed", type=int, default=2002)
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
+    ap.add_argument("--time-stride", type=int, default=16,
+                    help="time every N-th launch of the roofline kernel with HIP events")
     ap.add_argument("--latency-reps", type=int, default=20, help="0 skips the latency measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=2,
@@ -198,7 +200,7 @@ def main():
         step()
     torch.cuda.synchronize()
     phase = K.PHASE_HEMV if args.roofline_phase == "hemv" else K.PHASE_GEMM
-    K.profile_begin(ctx, phase)
+    K.profile_begin(ctx, phase, args.time_stride)
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -212,25 +214,29 @@ def main():
     value = nk * args.steps / elapsed
     status = dst.cpu().numpy()
     log(f"[bench] {ms_per_step:.1f} ms/step, {value:.2f} solves/s, status {set(status.tolist())}")
-    prof_elapsed, prof_note = elapsed, "the timed steps"
+    prof_elapsed = elapsed
+    prof_note = (f"every {args.time_stride}-th launch of the timed steps" if args.time_stride > 1
+                 else "every launch of the timed steps")
 
     avg_ms = prof["ms"] / max(prof["launches"], 1)
+    # the phase's share of the step, from the sampled mean duration
+    share = avg_ms * prof["phase_launches"] / (1e3 * prof_elapsed)
     if phase == K.PHASE_HEMV:
         per_launch = prof["bytes"] / max(prof["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "hetrd_zhemv", "achieved": achieved, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(n, nk),
-                "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
-                "alg_bytes_per_launch": per_launch, "measured_on": prof_note,
-                "share_of_step": prof["ms"] / (1e3 * prof_elapsed)}
+                "launches": prof["phase_launches"], "timed_launches": prof["launches"],
+                "avg_launch_us": 1e3 * avg_ms, "alg_bytes_per_launch": per_launch, "measured_on": prof_note,
+                "share_of_step": share}
     else:
         per_launch = prof["flops"] / max(prof["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "cgemm_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
-                "alg_flops_per_launch": per_launch, "measured_on": prof_note,
-                "share_of_step": prof["ms"] / (1e3 * prof_elapsed)}
+                "launches": prof["phase_launches"], "timed_launches": prof["launches"],
+                "avg_launch_us": 1e3 * avg_ms, "alg_flops_per_launch": per_launch, "measured_on": prof_note,
+                "share_of_step": share}
 
     # latency of single-k-point calls
     lat = []

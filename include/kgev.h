@@ -307,21 +307,27 @@ void kgev_server_destroy(kgev_server* srv);
 
 /*
  * Kernel timing for measurement.  Between kgev_profile_begin and
- * kgev_profile_end, every launch of the chosen phase made through this
- * context is bracketed by two HIP events on the stream it is enqueued on, and
- * the phase's algorithmic work per launch is tallied:
+ * kgev_profile_end, every stride-th launch (stride >= 1; the first launch is
+ * always timed) of the chosen phase made through this context is bracketed
+ * by two HIP events on the stream it is enqueued on, and the phase's
+ * algorithmic work of the timed launches is tallied:
  *   KGEV_PHASE_HEMV : the Hermitian product A22 v of the tridiagonalisation
  *                     (Procedure 4); work = bytes of the lower triangle of the
  *                     trailing matrix, 16 m (m + 1) / 2 per k-point;
  *   KGEV_PHASE_GEMM : every complex matrix product on MFMA; work = real flops,
  *                     8 m n k per product (half for lower-only outputs).
  * kgev_profile_end waits for the recorded events, returns the number of
- * launches, their summed duration in milliseconds and the summed algorithmic
- * bytes and flops, and stops recording.  Timing adds two event records per
- * launch of the chosen phase and nothing else.  Launches captured into a
- * graph (opts.use_graph) are not timed or counted, since the runtime does not
- * time events recorded by graph nodes; both calls drop the context's cached
- * graphs.
+ * timed launches, the number of all launches of the phase, the summed
+ * duration of the timed launches in milliseconds and their summed
+ * algorithmic bytes and flops, and stops recording.  Timing adds two event
+ * records per timed launch and nothing else; an event record costs the
+ * stream a few microseconds, so a stride above 1 keeps the measured run
+ * close to an untimed one.  Launches captured into a graph (opts.use_graph)
+ * are not timed or counted, since the runtime does not time events recorded
+ * by graph nodes; both calls drop the context's cached graphs.
+ * Errors: -1 ctx, -2 phase, -3 stride < 1; kgev_profile_end without a
+ * matching begin returns KGEV_EUNSUPPORTED, a failed event query
+ * KGEV_EDEVICE.
  */
 /*
  * Band_DFT_Col Part 5 (arXiv:1402.4247, the routine's outline in the
@@ -400,9 +406,9 @@ kgev_status kgev_bloch_device(kgev_ctx* ctx, int32_t natom, const int32_t* off, 
 
 #define KGEV_PHASE_HEMV 1
 #define KGEV_PHASE_GEMM 2
-kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase);
-kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes,
-                             double* alg_flops);
+kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase, int32_t stride);
+kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, int64_t* phase_launches, double* total_ms,
+                             double* alg_bytes, double* alg_flops);
 
 #ifdef __cplusplus
 }

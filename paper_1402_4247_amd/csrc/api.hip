@@ -25,8 +25,8 @@ using namespace kgev;
 
 namespace kgev {
 struct Profiler;
-Profiler* prof_start(int phase, size_t reserve);
-bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double* flops);
+Profiler* prof_start(int phase, int stride, size_t reserve);
+bool prof_stop(Profiler* p, int64_t* launches, int64_t* seen, double* ms, double* bytes, double* flops);
 }  // namespace kgev
 
 // Everything that identifies a captured solve: sizes, options, buffers, stream.
@@ -556,7 +556,7 @@ void kgev_destroy(kgev_ctx* ctx)
     if (!ctx) return;
     DevGuard g(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
+    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr, nullptr);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.second);
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->stage) (void)hipFree(ctx->stage);
@@ -994,24 +994,25 @@ kgev_status kgev_bloch_device(kgev_ctx* ctx, int32_t natom, const int32_t* off, 
     return KGEV_OK;
 }
 
-kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase)
+kgev_status kgev_profile_begin(kgev_ctx* ctx, int32_t phase, int32_t stride)
 {
     if (!ctx) return -1;
     if (phase != KGEV_PHASE_HEMV && phase != KGEV_PHASE_GEMM) return -2;
+    if (stride < 1) return -3;
     DevGuard g(ctx->device);
     drop_graphs(ctx);
-    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr);
-    ctx->prof = prof_start(phase, 16384);
+    if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr, nullptr);
+    ctx->prof = prof_start(phase, stride, 16384);
     return KGEV_OK;
 }
 
-kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes,
-                             double* alg_flops)
+kgev_status kgev_profile_end(kgev_ctx* ctx, int64_t* launches, int64_t* phase_launches, double* total_ms,
+                             double* alg_bytes, double* alg_flops)
 {
     if (!ctx) return -1;
     if (!ctx->prof) return KGEV_EUNSUPPORTED;
     DevGuard g(ctx->device);
-    const bool ok = prof_stop(ctx->prof, launches, total_ms, alg_bytes, alg_flops);
+    const bool ok = prof_stop(ctx->prof, launches, phase_launches, total_ms, alg_bytes, alg_flops);
     ctx->prof = nullptr;
     drop_graphs(ctx);
     return ok ? KGEV_OK : KGEV_EDEVICE;

@@ -557,6 +557,7 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
         const char* v = getenv("KGEV_HEMV_VARIANT");
         return v ? atoi(v) : 30;
     }();
+
     for (int p = 0; p <= n - 1; p += nb) {
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
         hipLaunchKernelGGL(hetrd_colstart<R>, g1, dim3(RB), 0, st, ws, p);

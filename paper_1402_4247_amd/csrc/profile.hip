@@ -6,11 +6,17 @@
 
 namespace kgev {
 
+// Every stride-th launch of the phase is bracketed by two events (an event
+// record costs the stream a few microseconds, so timing every launch of a
+// phase with thousands of short launches would slow what is measured).
 struct Profiler {
     int phase = PH_NONE;
+    int stride = 1;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    int64_t launches = 0;
+    int64_t seen = 0;          // launches of the phase
+    bool open = false;         // the current launch is timed
+    int64_t launches = 0;      // timed launches
     double bytes = 0, flops = 0;
 };
 
@@ -38,25 +44,40 @@ void prof_before(int phase, hipStream_t st)
 {
     Profiler* p = g_prof;
     if (!p || p->phase != phase || capturing(st)) return;
+    p->open = (p->seen % p->stride) == 0;
+    if (!p->open) return;
     hipEvent_t e = next_event(p);
-    if (e) (void)hipEventRecord(e, st);
+    if (!e) {
+        p->open = false;
+        return;
+    }
+    (void)hipEventRecord(e, st);
 }
 
 void prof_after(int phase, hipStream_t st, double bytes, double flops)
 {
     Profiler* p = g_prof;
     if (!p || p->phase != phase || capturing(st)) return;
+    p->seen += 1;
+    if (!p->open) return;
+    p->open = false;
     hipEvent_t e = next_event(p);
-    if (e) (void)hipEventRecord(e, st);
+    if (!e) {
+        // no closing event: drop the opening one
+        p->used -= 1;
+        return;
+    }
+    (void)hipEventRecord(e, st);
     p->launches += 1;
     p->bytes += bytes;
     p->flops += flops;
 }
 
-Profiler* prof_start(int phase, size_t reserve)
+Profiler* prof_start(int phase, int stride, size_t reserve)
 {
     Profiler* p = new Profiler;
     p->phase = phase;
+    p->stride = stride < 1 ? 1 : stride;
     p->pool.reserve(reserve);
     for (size_t q = 0; q < reserve; ++q) {
         hipEvent_t e = nullptr;
@@ -67,7 +88,7 @@ Profiler* prof_start(int phase, size_t reserve)
     return p;
 }
 
-bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double* flops)
+bool prof_stop(Profiler* p, int64_t* launches, int64_t* seen, double* ms, double* bytes, double* flops)
 {
     if (g_prof == p) g_prof = nullptr;
     double total = 0;
@@ -79,6 +100,7 @@ bool prof_stop(Profiler* p, int64_t* launches, double* ms, double* bytes, double
         total += t;
     }
     if (launches) *launches = p->launches;
+    if (seen) *seen = p->seen;
     if (ms) *ms = total;
     if (bytes) *bytes = p->bytes;
     if (flops) *flops = p->flops;

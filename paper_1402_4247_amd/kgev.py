@@ -110,10 +110,10 @@ def _load():
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
-    lib.kgev_profile_begin.argtypes = [P, I32]
+    lib.kgev_profile_begin.argtypes = [P, I32, I32]
     lib.kgev_profile_begin.restype = I32
-    lib.kgev_profile_end.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D),
-                                     ctypes.POINTER(D)]
+    lib.kgev_profile_end.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(D),
+                                     ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.kgev_profile_end.restype = I32
     lib.kgev_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
     lib.kgev_server_create.restype = I32
@@ -306,17 +306,19 @@ def bloch_device(ctx, off, blocks, d_data, R, kf, d_out, stream=None) -> int:
                                  _stream(stream))
 
 
-def profile_begin(ctx, phase) -> None:
-    _check("kgev_profile_begin", lib.kgev_profile_begin(ctx.handle, int(phase)))
+def profile_begin(ctx, phase, stride: int = 1) -> None:
+    _check("kgev_profile_begin", lib.kgev_profile_begin(ctx.handle, int(phase), int(stride)))
 
 
 def profile_end(ctx):
-    """Returns dict(launches, ms, bytes, flops) for the profiled phase."""
-    n = ctypes.c_int64()
+    """Returns dict(launches, phase_launches, ms, bytes, flops): the timed
+    launches, all launches of the phase, and the duration and algorithmic
+    work of the timed ones."""
+    n, na = ctypes.c_int64(), ctypes.c_int64()
     ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _check("kgev_profile_end", lib.kgev_profile_end(ctx.handle, ctypes.byref(n), ctypes.byref(ms),
-                                                    ctypes.byref(by), ctypes.byref(fl)))
-    return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+    _check("kgev_profile_end", lib.kgev_profile_end(ctx.handle, ctypes.byref(n), ctypes.byref(na),
+                                                    ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)))
+    return dict(launches=n.value, phase_launches=na.value, ms=ms.value, bytes=by.value, flops=fl.value)
 
 
 class Server:
