@@ -1,0 +1,143 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (one batched call per system, default options unless the
+form says otherwise):
+
+* the magnetite-like LCAO system at n = 2000 with 16 k-points (the benchmark
+  batch) and at n = 3000 with one k-point;
+* the batched form: n = 1024, all 64 k-points of the 4x4x4 grid in one
+  captured-graph call with the autotuned panel width;
+* the mixed-precision form: n = 4096, the 8 k-points of the 2x2x2 grid,
+  complex64 reduction + FP64 refinement beside the FP64 path.
+
+Every k-point is checked by properties that hold at any size, computed with
+plain PyTorch products on the device (independent of the library's
+kernels): r_res = ||H C - S C diag(w)||_F / ||H||_F <= 1e-12 and
+max |C^H S C - I| <= 1e-12, eigenvalues ascending.  Sampled k-points are
+compared with the oracle's eigenvalues (1e-10 relative), where the oracle
+finishes in seconds (n <= 2000)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_helpers import DEV, K, check
+from paper_1402_4247_amd import inputs as G
+
+pytestmark = pytest.mark.gpu
+
+TOL_RES, TOL_ORTH, TOL_EIG = 1e-12, 1e-12, 1e-10
+
+
+def to_dev(Ms):
+    return torch.from_numpy(G.colmajor(Ms)).to(DEV)
+
+
+def math_view(buf):
+    """(nk, n, n) column-major device buffer -> the matrices it holds."""
+    return buf.transpose(-1, -2).contiguous()
+
+
+def residuals(dH, dS, dw, dC):
+    """Per-k r_res and max |C^H S C - I| with torch products on the device."""
+    H, S, C = math_view(dH), math_view(dS), math_view(dC)
+    SC = torch.matmul(S, C)
+    R = torch.matmul(H, C) - SC * dw.to(torch.complex128)[:, None, :]
+    r_res = torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(H)
+    CSC = torch.matmul(C.conj().transpose(-1, -2).contiguous(), SC)
+    eye = torch.eye(C.shape[-1], dtype=torch.complex128, device=DEV)
+    r_orth = (CSC - eye).abs().amax(dim=(-2, -1))
+    return r_res.cpu().numpy(), r_orth.cpu().numpy()
+
+
+def solve(ctx, dH, dS, n, nk, opts):
+    dw = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+    dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV)
+    st = torch.full((nk,), -9, dtype=torch.int32, device=DEV)
+    check(K().solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=st, opts=opts), "solve")
+    torch.cuda.synchronize()
+    return dw, dC, st.cpu().numpy()
+
+
+def check_all(dH, dS, dw, dC, st, what):
+    assert np.all(st == 0), f"{what}: statuses {st}"
+    w = dw.cpu().numpy()
+    assert np.all(np.diff(w, axis=1) >= 0), f"{what}: eigenvalues not ascending"
+    r_res, r_orth = residuals(dH, dS, dw, dC)
+    print(f"{what}: max r_res {r_res.max():.2e}, max r_orth {r_orth.max():.2e}", flush=True)
+    assert r_res.max() <= TOL_RES and r_orth.max() <= TOL_ORTH
+    return w
+
+
+def oracle_eigs(Hs, Ss, w, ks, what):
+    for k in ks:
+        s0, w0, _ = O.solve_k(Hs[k], Ss[k], vectors=False)
+        assert s0 == 0
+        err = np.abs(w[k] - w0).max() / np.abs(w0).max()
+        print(f"{what}: k={k} eigenvalues vs oracle {err:.2e}", flush=True)
+        assert err <= TOL_EIG
+
+
+@pytest.mark.timeout(600)
+def test_lcao_n2000_16k_benchmark_batch():
+    kg = K()
+    n, nk = 2000, 16
+    Hs, Ss = G.config2(n, nk, 2002)
+    dH, dS = to_dev(Hs), to_dev(Ss)
+    with kg.Context(0) as ctx:
+        dw, dC, st = solve(ctx, dH, dS, n, nk, kg.make_opts())
+    w = check_all(dH, dS, dw, dC, st, "n=2000 x16")
+    oracle_eigs(Hs, Ss, w, [0, nk - 1], "n=2000 x16")
+
+
+@pytest.mark.timeout(600)
+def test_lcao_n3000_one_k():
+    kg = K()
+    n, nk = 3000, 1
+    Hs, Ss = G.config2(n, nk, 2002)
+    dH, dS = to_dev(Hs), to_dev(Ss)
+    with kg.Context(0) as ctx:
+        dw, dC, st = solve(ctx, dH, dS, n, nk, kg.make_opts())
+    check_all(dH, dS, dw, dC, st, "n=3000 x1")
+
+
+@pytest.mark.timeout(600)
+def test_batched_n1024_64k_graph_autotuned():
+    kg = K()
+    n, nk = 1024, 64
+    Hs, Ss = G.config3(n, nk, 3003)
+    dH, dS = to_dev(Hs), to_dev(Ss)
+    stream = torch.cuda.Stream()
+    with kg.Context(0) as ctx:
+        nb = kg.autotune(ctx, n)
+        assert nb in (16, 24, 32, 48, 64)
+        opts = kg.make_opts(use_graph=True, panel_nb=nb)
+        for rep in range(2):          # capture, then a replay
+            dw = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+            dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV)
+            st = torch.full((nk,), -9, dtype=torch.int32, device=DEV)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                check(kg.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=st, opts=opts,
+                                        stream=stream.cuda_stream), "graph solve")
+            stream.synchronize()
+            w = check_all(dH, dS, dw, dC, st.cpu().numpy(), f"n=1024 x64 nb={nb} pass {rep}")
+    oracle_eigs(Hs, Ss, w, [0, 21, nk - 1], "n=1024 x64")
+
+
+@pytest.mark.timeout(900)
+def test_mixed_n4096_8k_against_fp64_path():
+    kg = K()
+    n, nk = 4096, 8
+    Hs, Ss = G.config4(n, nk, 4004)
+    dH, dS = to_dev(Hs), to_dev(Ss)
+    del Hs, Ss
+    with kg.Context(0) as ctx:
+        w64, C64, st64 = solve(ctx, dH, dS, n, nk, kg.make_opts())
+        w64h = check_all(dH, dS, w64, C64, st64, "n=4096 x8 fp64")
+        del C64
+        torch.cuda.empty_cache()
+        wm, Cm, stm = solve(ctx, dH, dS, n, nk, kg.make_opts(precision=kg.PREC_FP32_REFINE))
+        wmh = check_all(dH, dS, wm, Cm, stm, "n=4096 x8 fp32+refine")
+    diff = np.abs(wmh - w64h).max() / np.abs(w64h).max()
+    print(f"n=4096 x8: mixed vs fp64 eigenvalues {diff:.2e}", flush=True)
+    assert diff <= TOL_EIG
