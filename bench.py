@@ -8,8 +8,8 @@ one.  Prints ONE JSON line.
 
 Extra fields:
   roofline      dominant kernel measured with HIP events recorded by the
-                library around each of its launches, on the stream it is
-                enqueued on, over the timed steps;
+                library around every --time-stride-th of its launches, on the
+                stream it is enqueued on, over the timed steps;
   graph_replay  the same batch with the whole solve captured once as a HIP
                 graph and replayed (the kernels are the same; host launch
                 work disappears);
@@ -19,6 +19,10 @@ Extra fields:
   fp32_refine, cholesky_s
                 the mixed-precision form and the Cholesky form of Part 2 on
                 the same batch (kernel by kernel), with their residuals;
+  host_path     the host-pointer entry point (kgev_solve_k) on the same batch
+                from pageable host memory: solves/s including the PCIe
+                copies, and the plain host-to-device and device-to-host copy
+                times of the inputs and outputs (not the headline);
   check         residuals of one k-point and its eigenvalue error against the
                 oracle's.
 """
@@ -124,15 +128,17 @@ def serve_stream(args, K, G, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--nk", type=int, default=16)
     ap.add_argument("--seed", type=int, default=2002)
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
     ap.add_argument("--time-stride", type=int, default=16,
                     help="time every N-th launch of the roofline kernel with HIP events")
-    ap.add_argument("--latency-reps", type=int, default=20, help="0 skips the latency measurement")
+    ap.add_argument("--latency-reps", type=int, default=50, help="0 skips the latency measurement")
+    ap.add_argument("--host-steps", type=int, default=1,
+                    help="timed calls of the host-pointer entry point (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed steps of the FP32+refine form (0 skips it)")
@@ -355,6 +361,36 @@ def main():
                  "status_all_ok": bool(np.all(stg.cpu().numpy() == 0))}
         log(f"[bench] graph replay {graph['value']:.2f} solves/s")
 
+    # the host-pointer entry point: PCIe copies included
+    host = None
+    if args.host_steps > 0:
+        Hc = np.ascontiguousarray(G.colmajor(Hs))
+        Sc = np.ascontiguousarray(G.colmajor(Ss))
+        wh = np.zeros((nk, n))
+        Ch = np.zeros((nk, n, n), dtype=np.complex128)
+        log(f"[bench] host-pointer path: warmup 1, timing {args.host_steps} calls")
+        K.solve_k(ctx, Hc, Sc, n, nk, wh, Ch)
+        a = time.perf_counter()
+        for _ in range(args.host_steps):
+            sth, _bad = K.solve_k(ctx, Hc, Sc, n, nk, wh, Ch)
+            if sth != 0:
+                raise RuntimeError(f"kgev_solve_k returned {sth}")
+        th = (time.perf_counter() - a) / args.host_steps
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        tH = torch.from_numpy(Hc).to(dev)
+        tS = torch.from_numpy(Sc).to(dev)
+        torch.cuda.synchronize()
+        h2d = time.perf_counter() - a
+        a = time.perf_counter()
+        _ = dC.cpu()
+        d2h = time.perf_counter() - a
+        del tH, tS, _
+        host = {"value": nk / th, "unit": "solves/s", "ms_per_call": 1e3 * th, "calls": args.host_steps,
+                "h2d_ms_H_S": 1e3 * h2d, "d2h_ms_C": 1e3 * d2h,
+                "bitwise_equal_to_headline": bool(np.array_equal(wh, dw.cpu().numpy()))}
+        log(f"[bench] host-pointer path {host['value']:.2f} solves/s")
+
     serving = serve_stream(args, K, G, torch, dev) if args.serve > 0 else None
 
     cpu = None
@@ -381,7 +417,7 @@ def main():
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
                    "panel_nb": args.panel_nb or tuned_nb or 32},
         "roofline": roof, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "cholesky_s": chol,
-        "serving": serving,
+        "host_path": host, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,

@@ -129,13 +129,17 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // One chunk of z = A22 u.  A chunk is up to four 64x64 tiles (R0..R0+3, C) of
 // one block column of the lower triangle; wave w owns tile R0 + w whole: the
 // direct part z_R += A_RC u_C comes out complete per row, the transposed part
-// z_C += A_RC^H u_R per column after a transposing wave reduction, and the
-// four waves' column sums are added once.
+// z_C += A_RC^H u_R per column after a wave reduction (a transposing shuffle
+// reduction, or, by default, column sums through LDS that leave the registers
+// free for the next group's loads), and the four waves' column sums are added
+// once.
 template <typename R, int MINW, bool BUF, int PF>
 __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
 {
     __shared__ cx<R> svC[ZT];
     __shared__ cx<R> sT[ZCH][ZT];
+    // per-wave staging of one group's products (PF == 3)
+    __shared__ cx<R> sP[PF == 3 ? ZCH : 1][8][ZT + 1];
     const int64_t b = blockIdx.y;
     const int n = ws.n;
     const int o = i + 1;
@@ -161,8 +165,7 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
     const int64_t gr = (int64_t)o + (int64_t)(have_tile ? Rb : C) * ZT + lane;
     const bool row_ok = gr < n;
     // Loads are unconditional from a clamped (in-bounds) address and the value
-    // is masked afterwards, so no branch guards them; each group of 8 columns
-    // is requested one step ahead of its use.
+    // is masked afterwards, so no branch guards them.
     // Matrices under 2 GiB are read with buffer loads: one 32-bit row offset
     // per lane shared by every load of the tile, the column offset in a
     // scalar register (fewer vector registers and no 64-bit address
@@ -189,11 +192,11 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
             }
         }
     };
-    // groups of 8 columns are requested PF groups ahead of their use
-    cx<R> a[8], an[8], an2[8];
+    // PF = 0: each group of 8 columns is requested once the previous one is
+    // reduced; 1: one group ahead (separate registers); 3: requested into
+    // the same registers once the previous group's products are in LDS
+    cx<R> a[8], an[8];
     load_group(0, a);
-    if constexpr (PF == 2) load_group(1, an);
-    (void)an2;
     if (tid < ZT) {
         const int64_t gc = gcb + tid;
         const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
@@ -210,11 +213,9 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
         cx<R> yd = czero<cx<R>>();
 #pragma unroll 1
         for (int g = 0; g < 8; ++g) {
-            if constexpr (PF == 2) {
-                if (g + 2 < 8) load_group(g + 2, an2);
-            } else if constexpr (PF == 1) {
+            if constexpr (PF == 1) {
                 if (g + 1 < 8) load_group(g + 1, an);
-            } else {
+            } else if constexpr (PF == 0) {
                 if (g > 0) load_group(g, a);
             }
             const int64_t gc0 = gcb + g * 8;
@@ -230,14 +231,31 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
                 // the diagonal entry is counted once (direct part only)
                 a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
             }
-            const cx<R> r = transpose_sum8<R>(a, lane);
-            if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
-            if constexpr (PF > 0) {
+            if constexpr (PF == 3) {
+                // the products go to this wave's LDS block, the next group is
+                // requested, and the column sums are taken from LDS while it
+                // is in flight: lane l adds rows 8 (l / 8) .. +7 of column
+                // l mod 8, then the eight lanes of a column combine
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc) {
-                    a[cc] = an[cc];
-                    if constexpr (PF == 2) an[cc] = an2[cc];
-                }
+                for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
+                if (g + 1 < 8) load_group(g + 1, a);
+                __builtin_amdgcn_wave_barrier();
+                const int c = lane & 7, r0 = (lane >> 3) * 8;
+                cx<R> cs = czero<cx<R>>();
+#pragma unroll
+                for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
+                cs = xor_add<8, R>(cs);
+                cs = xor_add<16, R>(cs);
+                cs = xor_add<32, R>(cs);
+                if (lane < 8) sT[w][g * 8 + lane] = cs;
+                __builtin_amdgcn_wave_barrier();
+            } else {
+                const cx<R> r = transpose_sum8<R>(a, lane);
+                if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
+            }
+            if constexpr (PF == 1) {
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc) a[cc] = an[cc];
             }
         }
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
@@ -549,15 +567,14 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
     }();
     // buffer offsets are 32-bit: the matrix (ld x n) must stay under 2 GiB
     const bool buf = buf_ok && (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
-    // KGEV_HEMV_VARIANT = 10 * (min waves per SIMD) + (groups of 8 columns
-    // prefetched): 30 (default: three workgroups per CU, each group loaded
-    // and consumed in turn; measured fastest on gfx950), 11, 12, 31, 40
-    // (tuning experiments)
+    // KGEV_HEMV_VARIANT: 33 (default: three workgroups per CU, each group of
+    // 8 columns consumed while the next is requested, column sums through
+    // LDS; measured fastest on gfx950) or 30 (shuffle reductions, each group
+    // loaded after the previous one is reduced; 1% slower)
     static const int variant = [] {
         const char* v = getenv("KGEV_HEMV_VARIANT");
-        return v ? atoi(v) : 30;
+        return v ? atoi(v) : 33;
     }();
-
     for (int p = 0; p <= n - 1; p += nb) {
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
         hipLaunchKernelGGL(hetrd_colstart<R>, g1, dim3(RB), 0, st, ws, p);
@@ -571,16 +588,10 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const dim3 gz((unsigned)nch, (unsigned)nk);
             if (!buf)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 1, false, 1>), gz, dim3(256), 0, st, ws, i);
-            else if (variant == 11)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 1>), gz, dim3(256), 0, st, ws, i);
-            else if (variant == 40)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 4, true, 0>), gz, dim3(256), 0, st, ws, i);
-            else if (variant == 31)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 1>), gz, dim3(256), 0, st, ws, i);
-            else if (variant == 12)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, true, 2>), gz, dim3(256), 0, st, ws, i);
-            else
+            else if (variant == 30)
                 hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 0>), gz, dim3(256), 0, st, ws, i);
+            else
+                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 3>), gz, dim3(256), 0, st, ws, i);
             prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);
