@@ -162,7 +162,8 @@ def main():
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the per-k solve needs no "
-                                   "communication and shards by k-point (see DESIGN.md)",
+                                   "communication, and a multi-GPU run would give each GPU its own "
+                                   "share of the k-points",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -17,7 +17,7 @@
  *     tridiagonal eigensolver, rearrangement (back-transformation) of the
  *     eigenvectors, normalisation.
  *
- * Readings of passages the paper leaves open (all restated in the design doc):
+ * Readings of passages the paper leaves open:
  *   - "rearrange S" is canonical orthogonalisation X = U diag(s)^(-1/2) where
  *     S = U diag(s) U^dagger; "S^dagger H S" is X^dagger H X.
  *   - Procedure 2 "subtract s" is taken with the stable sign: the reflector
