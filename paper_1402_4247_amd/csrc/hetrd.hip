@@ -552,6 +552,139 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The last columns, once the trailing matrix has at most TAIL_M rows: one
+// workgroup per problem holds its lower triangle in LDS (packed by rows,
+// element (r, s), r >= s, at r (r + 1) / 2 + s) and reduces it column by
+// column, unblocked: Procedure 2's reflector from the column's norm,
+// y = tau A22 v (Procedure 4), w = y - (tau / 2)(y^H v) v (Procedure 5) and
+// A22 -= v w^H + w v^H (Procedure 6), with the same reflector convention as
+// the blocked columns.  Sums are taken in a fixed order (bitwise
+// reproducible).  It replaces two launches per column, whose fixed cost
+// dominates at this size, by one launch for all of them.
+constexpr int TAIL_M = 128;
+constexpr int TAIL_T = 1024;
+
+template <typename R>
+__device__ inline R block_sum_tail(R v, R* red, int tid)
+{
+    v = wave_sum(v);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    R t = 0;
+#pragma unroll
+    for (int q = 0; q < TAIL_T / 64; ++q) t += red[q];
+    return t;
+}
+
+template <typename R>
+__global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
+{
+    __shared__ cx<R> P[TAIL_M * (TAIL_M + 1) / 2];
+    __shared__ cx<R> sv[TAIL_M], sy[TAIL_M], sw[TAIL_M];
+    __shared__ R red[TAIL_T / 64];
+    __shared__ cx<R> sred[TAIL_T / 64];
+    __shared__ cx<R> sref[2];       // tau, scale
+    const int64_t b = blockIdx.x;
+    const int n = ws.n, M = n - i0, tid = threadIdx.x, lane = tid & 63;
+    const cx<R>* A = ws.A + b * ws.sA;
+    cx<R>* V = ws.V + b * ws.sV;
+    const cx<R> zero = czero<cx<R>>();
+    for (int e = tid; e < M * M; e += TAIL_T) {
+        const int r = e % M, c = e / M;
+        if (r >= c) P[r * (r + 1) / 2 + c] = A[(int64_t)(i0 + r) + (int64_t)(i0 + c) * ws.lda];
+    }
+    __syncthreads();
+    for (int c = 0; c + 1 < M; ++c) {
+        const int i = i0 + c, mm = M - c - 1;     // trailing order below column c
+        // Procedure 2: squared norm of rows c+2.. of column c
+        R part = 0;
+        if (tid >= 1 && tid < mm) {
+            const cx<R> x = P[(c + 1 + tid) * (c + 2 + tid) / 2 + c];
+            part = x.x * x.x + x.y * x.y;
+        }
+        const R sig2 = block_sum_tail(part, red, tid);
+        if (tid == 0) {
+            const cx<R> alpha = P[(c + 1) * (c + 2) / 2 + c];
+            cx<R> tau, scale;
+            R beta;
+            if (sig2 == (R)0 && alpha.y == (R)0) {
+                tau = zero;
+                scale = zero;
+                beta = alpha.x;
+            } else {
+                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+                beta = (alpha.x >= (R)0) ? -nrm : nrm;
+                tau = mk<R>((beta - alpha.x) / beta, -alpha.y / beta);
+                const R dr = alpha.x - beta, di = alpha.y;
+                const R den = dr * dr + di * di;
+                scale = mk<R>(dr / den, -di / den);
+            }
+            sref[0] = tau;
+            sref[1] = scale;
+            ws.d[b * n + i] = P[c * (c + 1) / 2 + c].x;
+            ws.e[b * n + i] = beta;
+            ws.tau[b * n + i] = tau;
+        }
+        __syncthreads();
+        const cx<R> tau = sref[0], scale = sref[1];
+        // Procedure 3: v = (1, scale x_1, ...), stored for the back-transformation
+        if (tid < mm) {
+            const cx<R> v = tid == 0 ? mk<R>(1, 0) : cmul(scale, P[(c + 1 + tid) * (c + 2 + tid) / 2 + c]);
+            sv[tid] = v;
+            V[(int64_t)(i + 1 + tid) + (int64_t)i * ws.n] = v;
+        }
+        __syncthreads();
+        // Procedure 4: y = tau A22 v, eight threads per row, each a strided
+        // share of the row, combined in a fixed order
+        {
+            const int r = tid >> 3, q = tid & 7;
+            cx<R> acc = zero;
+            if (r < mm) {
+                const int gr = c + 1 + r;
+                for (int s2 = q; s2 < mm; s2 += 8) {
+                    const int gs = c + 1 + s2;
+                    const cx<R> a = s2 <= r ? P[gr * (gr + 1) / 2 + gs] : cconj(P[gs * (gs + 1) / 2 + gr]);
+                    acc = cfma(a, sv[s2], acc);
+                }
+            }
+            acc.x += __shfl_xor(acc.x, 1, WAVE);
+            acc.y += __shfl_xor(acc.y, 1, WAVE);
+            acc.x += __shfl_xor(acc.x, 2, WAVE);
+            acc.y += __shfl_xor(acc.y, 2, WAVE);
+            acc.x += __shfl_xor(acc.x, 4, WAVE);
+            acc.y += __shfl_xor(acc.y, 4, WAVE);
+            if (q == 0 && r < mm) sy[r] = cmul(tau, acc);
+        }
+        __syncthreads();
+        // Procedure 5: w = y - (tau / 2) (y^H v) v
+        cx<R> yv = zero;
+        if (tid < mm) yv = cmulc(sy[tid], sv[tid]);
+        yv.x = wave_sum(yv.x);
+        yv.y = wave_sum(yv.y);
+        if (lane == 0) sred[tid >> 6] = yv;
+        __syncthreads();
+        cx<R> dot = zero;
+#pragma unroll
+        for (int q = 0; q < TAIL_T / 64; ++q) dot = cadd(dot, sred[q]);
+        const cx<R> k = cscale(cmul(tau, dot), (R)0.5);
+        if (tid < mm) sw[tid] = csub(sy[tid], cmul(k, sv[tid]));
+        __syncthreads();
+        // Procedure 6: A22 -= v w^H + w v^H (lower triangle)
+        for (int e = tid; e < mm * mm; e += TAIL_T) {
+            const int r = e / mm, s2 = e % mm;
+            if (s2 <= r) {
+                const int gr = c + 1 + r, gs = c + 1 + s2;
+                cx<R>& a = P[gr * (gr + 1) / 2 + gs];
+                a = csub(a, cadd(cmulc(sw[s2], sv[r]), cmulc(sv[s2], sw[r])));
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) ws.d[b * n + n - 1] = P[(M - 1) * M / 2 + (M - 1)].x;
+}
+
 }  // namespace
 
 int hetrd_pn(int64_t n) { return (int)((n + RB - 1) / RB); }
@@ -575,7 +708,18 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
         const char* v = getenv("KGEV_HEMV_VARIANT");
         return v ? atoi(v) : 33;
     }();
+    // trailing matrices of at most this order go to the LDS-resident tail
+    // kernel (KGEV_HETRD_TAIL=0 keeps every column on the blocked path)
+    static const int tail_m = [] {
+        const char* v = getenv("KGEV_HETRD_TAIL");
+        const int t = v ? atoi(v) : TAIL_M;
+        return t < 0 ? 0 : (t > TAIL_M ? TAIL_M : t);
+    }();
     for (int p = 0; p <= n - 1; p += nb) {
+        if (n - p <= tail_m && p < n - 1) {
+            hipLaunchKernelGGL(hetrd_tail<R>, dim3((unsigned)nk), dim3(TAIL_T), 0, st, ws, p);
+            break;
+        }
         dim3 g1((unsigned)((n - p + RB - 1) / RB), (unsigned)nk);
         hipLaunchKernelGGL(hetrd_colstart<R>, g1, dim3(RB), 0, st, ws, p);
         const int iend = min(p + nb, n - 1);
