@@ -7,9 +7,11 @@ complex128, all eigenpairs), inputs resident in HBM, kernels launched one by
 one.  Prints ONE JSON line.
 
 Extra fields:
-  roofline      dominant kernel measured with HIP events recorded by the
-                library around every --time-stride-th of its launches, on the
-                stream it is enqueued on, over the timed steps;
+  roofline      dominant kernel timed by HIP events carried in the dispatch
+                of every --time-stride-th of its launches (the library's
+                extended launch; the events are stamped when the kernel starts
+                and ends, on the stream it is enqueued on), over the timed
+                steps;
   graph_replay  the same batch with the whole solve captured once as a HIP
                 graph and replayed (the kernels are the same; host launch
                 work disappears);
@@ -134,7 +136,7 @@ def main():
     ap.add_argument("--nk", type=int, default=16)
     ap.add_argument("--seed", type=int, default=2002)
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
-    ap.add_argument("--time-stride", type=int, default=16,
+    ap.add_argument("--time-stride", type=int, default=17,
                     help="time every N-th launch of the roofline kernel with HIP events")
     ap.add_argument("--latency-reps", type=int, default=50, help="0 skips the latency measurement")
     ap.add_argument("--host-steps", type=int, default=1,

@@ -308,9 +308,10 @@ void kgev_server_destroy(kgev_server* srv);
 /*
  * Kernel timing for measurement.  Between kgev_profile_begin and
  * kgev_profile_end, every stride-th launch (stride >= 1; the first launch is
- * always timed) of the chosen phase made through this context is bracketed
- * by two HIP events on the stream it is enqueued on, and the phase's
- * algorithmic work of the timed launches is tallied:
+ * always timed) of the chosen phase made through this context carries two
+ * HIP events in its own dispatch (hipExtLaunchKernel: the runtime stamps
+ * them when the kernel starts and when it ends, on the stream it is enqueued
+ * on), and the phase's algorithmic work of the timed launches is tallied:
  *   KGEV_PHASE_HEMV : the Hermitian product A22 v of the tridiagonalisation
  *                     (Procedure 4); work = bytes of the lower triangle of the
  *                     trailing matrix, 16 m (m + 1) / 2 per k-point;
@@ -319,10 +320,8 @@ void kgev_server_destroy(kgev_server* srv);
  * kgev_profile_end waits for the recorded events, returns the number of
  * timed launches, the number of all launches of the phase, the summed
  * duration of the timed launches in milliseconds and their summed
- * algorithmic bytes and flops, and stops recording.  Timing adds two event
- * records per timed launch and nothing else; an event record costs the
- * stream a few microseconds, so a stride above 1 keeps the measured run
- * close to an untimed one.  Launches captured into a graph (opts.use_graph)
+ * algorithmic bytes and flops, and stops recording.  Timing adds no packet
+ * to the stream; a stride above 1 keeps the host-side event work small.  Launches captured into a graph (opts.use_graph)
  * are not timed or counted, since the runtime does not time events recorded
  * by graph nodes; both calls drop the context's cached graphs.
  * Errors: -1 ctx, -2 phase, -3 stride < 1; kgev_profile_end without a

@@ -279,25 +279,25 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
 }
 
 template <typename R, int BM, int BN, bool G3, int TA, int TB, int NST>
-hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st)
+hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st, const ProfLaunch& pl)
 {
     p.tiles_m = (int)((p.m + BM - 1) / BM);
     p.tiles_n = (int)((p.n + BN - 1) / BN);
     const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
-    hipLaunchKernelGGL((cgemm_kernel<R, BM, BN, G3, TA, TB, NST>), dim3((unsigned)total), dim3(G_THREADS), 0, st, p);
+    launch_timed(pl, cgemm_kernel<R, BM, BN, G3, TA, TB, NST>, dim3((unsigned)total), dim3(G_THREADS), st, p);
     return hipGetLastError();
 }
 
 // the operand forms are compile-time so that the tile loads are straight-line
 template <typename R, bool G3, int NST>
-hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st)
+hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st, const ProfLaunch& pl)
 {
     const int f = p.ta[0] * 2 + p.tb[0];
     switch (f) {
-    case 0: return launch_tiles<R, 64, 64, G3, 0, 0, NST>(p, st);
-    case 1: return launch_tiles<R, 64, 64, G3, 0, 1, NST>(p, st);
-    case 2: return launch_tiles<R, 64, 64, G3, 1, 0, NST>(p, st);
-    default: return launch_tiles<R, 64, 64, G3, 1, 1, NST>(p, st);
+    case 0: return launch_tiles<R, 64, 64, G3, 0, 0, NST>(p, st, pl);
+    case 1: return launch_tiles<R, 64, 64, G3, 0, 1, NST>(p, st, pl);
+    case 2: return launch_tiles<R, 64, 64, G3, 1, 0, NST>(p, st, pl);
+    default: return launch_tiles<R, 64, 64, G3, 1, 1, NST>(p, st, pl);
     }
 }
 
@@ -327,13 +327,13 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
         return v ? atoi(v) : 2;
     }();
     p.remap = remap;
-    prof_before(PH_GEMM, st);
+    const ProfLaunch pl = prof_launch_begin(PH_GEMM, st);
     hipError_t e;
     if (stages == 1)
-        e = g3 ? launch_forms<R, true, 1>(p, st) : launch_forms<R, false, 1>(p, st);
+        e = g3 ? launch_forms<R, true, 1>(p, st, pl) : launch_forms<R, false, 1>(p, st, pl);
     else
-        e = g3 ? launch_forms<R, true, 2>(p, st) : launch_forms<R, false, 2>(p, st);
-    prof_after(PH_GEMM, st, 0.0, flops);
+        e = g3 ? launch_forms<R, true, 2>(p, st, pl) : launch_forms<R, false, 2>(p, st, pl);
+    prof_launch_end(PH_GEMM, st, pl, 0.0, flops);
     return e;
 }
 

@@ -728,15 +728,16 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int NB = (m + ZT - 1) / ZT;
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
-            prof_before(PH_HEMV, st);
+            const ProfLaunch pl = prof_launch_begin(PH_HEMV, st);
             const dim3 gz((unsigned)nch, (unsigned)nk);
             if (!buf)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 1, false, 1>), gz, dim3(256), 0, st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 1, false, 1>, gz, dim3(256), st, ws, i);
             else if (variant == 30)
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 0>), gz, dim3(256), 0, st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 0>, gz, dim3(256), st, ws, i);
             else
-                hipLaunchKernelGGL((hetrd_zhemv<R, 3, true, 3>), gz, dim3(256), 0, st, ws, i);
-            prof_after(PH_HEMV, st, (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 3>, gz, dim3(256), st, ws, i);
+            prof_launch_end(PH_HEMV, st, pl,
+                            (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
             hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);
         }

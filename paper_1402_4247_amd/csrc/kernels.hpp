@@ -1,6 +1,7 @@
 // Internal launcher declarations and workspace descriptors of the HIP library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -9,11 +10,26 @@
 namespace kgev {
 
 // ---------------------------------------------------------------------------
-// launch timing (profile.cpp): while a phase is being profiled on this host
-// thread, its launch sites bracket each launch with two events.
+// launch timing (profile.hip): while a phase is being profiled on this host
+// thread, every stride-th launch of it carries a start and a stop event in
+// its own dispatch (the runtime stamps them when the kernel starts and ends).
 enum Phase { PH_NONE = 0, PH_HEMV = 1, PH_GEMM = 2 };
-void prof_before(int phase, hipStream_t st);
-void prof_after(int phase, hipStream_t st, double bytes, double flops);
+struct ProfLaunch {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+// the events for this launch of the phase, or none if it is not timed
+ProfLaunch prof_launch_begin(int phase, hipStream_t st);
+// counts the launch; tallies its algorithmic work if it was timed
+void prof_launch_end(int phase, hipStream_t st, const ProfLaunch& pl, double bytes, double flops);
+
+template <typename F, typename... Args>
+inline void launch_timed(const ProfLaunch& pl, F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    if (pl.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, pl.start, pl.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
 
 // ---------------------------------------------------------------------------
 // matrix products (gemm.hip)

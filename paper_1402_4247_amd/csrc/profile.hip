@@ -6,16 +6,15 @@
 
 namespace kgev {
 
-// Every stride-th launch of the phase is bracketed by two events (an event
-// record costs the stream a few microseconds, so timing every launch of a
-// phase with thousands of short launches would slow what is measured).
+// Every stride-th launch of the phase is timed by events carried in its own
+// dispatch (timing every launch of a phase with thousands of short launches
+// would slow what is measured).
 struct Profiler {
     int phase = PH_NONE;
     int stride = 1;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     int64_t seen = 0;          // launches of the phase
-    bool open = false;         // the current launch is timed
     int64_t launches = 0;      // timed launches
     double bytes = 0, flops = 0;
 };
@@ -40,34 +39,28 @@ static bool capturing(hipStream_t st)
     return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
-void prof_before(int phase, hipStream_t st)
+ProfLaunch prof_launch_begin(int phase, hipStream_t st)
 {
+    ProfLaunch pl;
     Profiler* p = g_prof;
-    if (!p || p->phase != phase || capturing(st)) return;
-    p->open = (p->seen % p->stride) == 0;
-    if (!p->open) return;
-    hipEvent_t e = next_event(p);
-    if (!e) {
-        p->open = false;
-        return;
+    if (!p || p->phase != phase || capturing(st)) return pl;
+    if (p->seen % p->stride != 0) return pl;
+    const size_t mark = p->used;
+    pl.start = next_event(p);
+    pl.stop = pl.start ? next_event(p) : nullptr;
+    if (!pl.stop) {
+        p->used = mark;
+        pl.start = nullptr;
     }
-    (void)hipEventRecord(e, st);
+    return pl;
 }
 
-void prof_after(int phase, hipStream_t st, double bytes, double flops)
+void prof_launch_end(int phase, hipStream_t st, const ProfLaunch& pl, double bytes, double flops)
 {
     Profiler* p = g_prof;
     if (!p || p->phase != phase || capturing(st)) return;
     p->seen += 1;
-    if (!p->open) return;
-    p->open = false;
-    hipEvent_t e = next_event(p);
-    if (!e) {
-        // no closing event: drop the opening one
-        p->used -= 1;
-        return;
-    }
-    (void)hipEventRecord(e, st);
+    if (!pl.start) return;
     p->launches += 1;
     p->bytes += bytes;
     p->flops += flops;
