@@ -21,6 +21,8 @@ Extra fields:
   fp32_refine, cholesky_s
                 the mixed-precision form and the Cholesky form of Part 2 on
                 the same batch (kernel by kernel), with their residuals;
+  x_reuse       the batch with Part 2's X(k) exported by an earlier call and
+                reused (an SCF iteration after the first: S(k) unchanged);
   host_path     the host-pointer entry point (kgev_solve_k) on the same batch
                 from pageable host memory: solves/s including the PCIe
                 copies, and the plain host-to-device and device-to-host copy
@@ -139,6 +141,8 @@ def main():
     ap.add_argument("--time-stride", type=int, default=17,
                     help="time every N-th launch of the roofline kernel with HIP events")
     ap.add_argument("--latency-reps", type=int, default=50, help="0 skips the latency measurement")
+    ap.add_argument("--reuse-steps", type=int, default=2,
+                    help="timed calls reusing Part 2's X from an earlier call (0 skips them)")
     ap.add_argument("--host-steps", type=int, default=1,
                     help="timed calls of the host-pointer entry point (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -364,6 +368,32 @@ def main():
                  "status_all_ok": bool(np.all(stg.cpu().numpy() == 0))}
         log(f"[bench] graph replay {graph['value']:.2f} solves/s")
 
+    # an SCF iteration after the first: S(k) unchanged, so Part 2's X(k) from
+    # an earlier call is reused and only Parts 3-4 run (same H here)
+    xreuse = None
+    if args.reuse_steps > 0:
+        dX = torch.empty((nk, n, n), dtype=torch.complex128, device=dev)
+        wx = torch.zeros_like(dw)
+        Cx = torch.zeros_like(dC)
+        stx = torch.zeros_like(dst)
+        st = K.solve_k_x_device(ctx, dH, dS, n, n, nk, wx, Cx, n, dX, K.X_EXPORT, d_status=stx, opts=opts)
+        if st != 0:
+            raise RuntimeError(f"X export returned {st}")
+        log(f"[bench] X reuse: timing {args.reuse_steps} calls")
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.reuse_steps):
+            st = K.solve_k_x_device(ctx, dH, dS, n, n, nk, wx, Cx, n, dX, K.X_REUSE, d_status=stx, opts=opts)
+            if st != 0:
+                raise RuntimeError(f"X reuse returned {st}")
+        torch.cuda.synchronize()
+        tx = time.perf_counter() - a
+        xreuse = {"value": nk * args.reuse_steps / tx, "unit": "solves/s", "ms_per_step": 1e3 * tx / args.reuse_steps,
+                  "steps": args.reuse_steps, "status_all_ok": bool(np.all(stx.cpu().numpy() == 0)),
+                  "bitwise_equal_to_headline": bool(torch.equal(wx, dw) and torch.equal(Cx, dC))}
+        del dX, Cx
+        log(f"[bench] X reuse {xreuse['value']:.2f} solves/s")
+
     # the host-pointer entry point: PCIe copies included
     host = None
     if args.host_steps > 0:
@@ -420,7 +450,7 @@ def main():
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
                    "panel_nb": args.panel_nb or tuned_nb or 32},
         "roofline": roof, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "cholesky_s": chol,
-        "host_path": host, "serving": serving,
+        "host_path": host, "x_reuse": xreuse, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "check": check,

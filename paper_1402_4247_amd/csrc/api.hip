@@ -414,16 +414,29 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, Aw, n, nn, nk, true));
     if (o.s_method == KGEV_S_PRUNE)
         KCHECK(prune_shift(st, n, Aw, nn, at<double>(w, p.ppart), sS, n, o.s_tol, at<int>(w, p.ndrop), nk));
-    // Part 4: A = Y diag(lambda) Y^H, C = X Y
+    // Part 4: A = Y diag(lambda) Y^H with Y = Q_A Z (Householder reflectors
+    // Q_A, real tridiagonal eigenvectors Z), C = X Y
     if (o.precision == KGEV_PREC_FP32_REFINE) {
         r = eigen_hh_mixed(p, w, st, dw, G, status, o.refine_iters);
+        if (r != KGEV_OK) return r;
+        if (o.want_vectors) {
+            KCHECK(normalize_cols(st, n, G, n, nn, nullptr, 0, 0.0, nullptr, nk));
+            KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, dC, ldc, ldc * n, nk, false));
+        }
     } else {
-        r = eigen_hh(p, w, st, dw, o.want_vectors ? G : nullptr, status);
-    }
-    if (r != KGEV_OK) return r;
-    if (o.want_vectors) {
-        KCHECK(normalize_cols(st, n, G, n, nn, nullptr, 0, 0.0, nullptr, nk));
-        KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, dC, ldc, ldc * n, nk, false));
+        // eigenvalues and Z; with vectors, C = (X Q_A) Z: the reflectors are
+        // applied to a copy of X from the right, and the last product takes
+        // the real Z as it is (two real products instead of three)
+        r = eigen_hh(p, w, st, dw, nullptr, status);
+        if (r != KGEV_OK) return r;
+        if (o.want_vectors) {
+            double* Zr = at<double>(w, p.Zr);
+            KCHECK(normalize_cols_real(st, n, Zr, n, nn, nk));
+            KCHECK(hipMemcpyAsync(G, X, sizeof(double2) * (size_t)nn * nk, hipMemcpyDeviceToDevice, st));
+            KCHECK(unmtr<double>(st, n, Vs, nn, at<double2>(w, p.tau), n, G, n, nn, at<double2>(w, p.uwork), p.kb,
+                                 nk, true));
+            KCHECK(cgemm_rb<double>(st, n, n, n, G, n, nn, Zr, n, nn, dC, ldc, ldc * n, nk));
+        }
     }
     if (o.s_method == KGEV_S_PRUNE)
         KCHECK(prune_finish(st, n, dw, o.want_vectors ? dC : nullptr, ldc, at<int>(w, p.ndrop), nk));

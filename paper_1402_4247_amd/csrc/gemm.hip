@@ -111,12 +111,15 @@ __device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int64_t 
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int c = TB ? e % BN : e / GB_K;
-        const int kk = TB ? e / BN : e % GB_K;
+        const int c = TB == 1 ? e % BN : e / GB_K;
+        const int kk = TB == 1 ? e / BN : e % GB_K;
         const int64_t gj = j0 + c, gk = k0 + kk;
         const bool ok = gj < n && gk < K;
         const int64_t gjc = gj < n ? gj : n - 1, gkc = gk < K ? gk : K - 1;
-        rb[q] = TB ? B[gjc + gkc * ldb] : B[gkc + gjc * ldb];
+        if constexpr (TB == 2)
+            rb[q] = mk<R>(reinterpret_cast<const R*>(B)[gkc + gjc * ldb], (R)0);
+        else
+            rb[q] = TB ? B[gjc + gkc * ldb] : B[gkc + gjc * ldb];
         okmask |= (unsigned)ok << q;
     }
 }
@@ -129,11 +132,11 @@ __device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const 
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int c = TB ? e % BN : e / GB_K;
-        const int kk = TB ? e / BN : e % GB_K;
+        const int c = TB == 1 ? e % BN : e / GB_K;
+        const int kk = TB == 1 ? e / BN : e % GB_K;
         const bool ok = (okmask >> q) & 1u;
         sr[kk][c] = ok ? rb[q].x : (R)0;
-        si[kk][c] = ok ? (TB ? -rb[q].y : rb[q].y) : (R)0;
+        if constexpr (TB != 2) si[kk][c] = ok ? (TB ? -rb[q].y : rb[q].y) : (R)0;
     }
 }
 
@@ -181,6 +184,14 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
                 if constexpr (G3) accT[a][b][r] = 0;
             }
 
+    // operand B of term s (strides in real elements when B is real)
+    auto bbase = [&](int sg) -> const cx<R>* {
+        if constexpr (TB == 2)
+            return reinterpret_cast<const cx<R>*>(reinterpret_cast<const R*>(p.B[sg]) + bo * p.sB[sg] +
+                                                  bi * p.sB2[sg]);
+        else
+            return p.B[sg] + bo * p.sB[sg] + bi * p.sB2[sg];
+    };
     const int nkt = (int)((K + GB_K - 1) / GB_K);
     const int total_k = nkt * p.nseg;
     cx<R> ra[BM * GB_K / G_THREADS], rb[BN * GB_K / G_THREADS];
@@ -188,7 +199,7 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
     int cur = 0;
     if (total_k > 0) {
         load_a<R, BM, TA>(p.A[0] + bo * p.sA[0] + bi * p.sA2[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
-        load_b<R, BN, TB>(p.B[0] + bo * p.sB[0] + bi * p.sB2[0], p.ldb[0], n, K, j0, 0, tid, rb, okb);
+        load_b<R, BN, TB>(bbase(0), p.ldb[0], n, K, j0, 0, tid, rb, okb);
         store_a<R, BM, TA>(sAr[0], sAi[0], tid, ra, oka);
         store_b<R, BN, TB>(sBr[0], sBi[0], tid, rb, okb);
     }
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
         if (nx < total_k) {
             load_a<R, BM, TA>(p.A[sn] + bo * p.sA[sn] + bi * p.sA2[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid,
                               ra, oka);
-            load_b<R, BN, TB>(p.B[sn] + bo * p.sB[sn] + bi * p.sB2[sn], p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid,
+            load_b<R, BN, TB>(bbase(sn), p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid,
                               rb, okb);
         }
 #pragma unroll
@@ -213,9 +224,18 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
                 br[t] = sBr[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
-                bi[t] = sBi[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
+                bi[t] = TB == 2 ? (R)0 : sBi[cur][ks + lk][wn * (BN / 2) + t * 16 + li];
             }
-            if constexpr (G3) {
+            if constexpr (TB == 2) {
+                // real B: two real products
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) {
+                        accR[a][b] = M::mma(ar[a], br[b], accR[a][b]);
+                        accI[a][b] = M::mma(ai[a], br[b], accI[a][b]);
+                    }
+            } else if constexpr (G3) {
                 R bs[TN];
 #pragma unroll
                 for (int t = 0; t < TN; ++t) bs[t] = br[t] + bi[t];
@@ -292,6 +312,7 @@ hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st, const ProfLaunch& pl)
 template <typename R, bool G3, int NST>
 hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st, const ProfLaunch& pl)
 {
+    if (p.tb[0] == 2) return launch_tiles<R, 64, 64, false, 0, 2, NST>(p, st, pl);
     const int f = p.ta[0] * 2 + p.tb[0];
     switch (f) {
     case 0: return launch_tiles<R, 64, 64, G3, 0, 0, NST>(p, st, pl);
@@ -311,6 +332,7 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
     double flops = 8.0 * (double)a.m * (double)a.n * (double)a.k * (double)a.nseg * (double)batch *
                    (double)(a.batch2 < 1 ? 1 : a.batch2);
     if (a.lower) flops *= 0.5;
+    if (a.tb[0] == 2) flops *= 0.5;   // complex times real: 4 real flops per term
     // The 3M form is the default: on gfx950 it measured 1.22x the 4M form on
     // the path's products with unchanged residuals.  KGEV_GEMM_REMAP=0|1 and
     // KGEV_GEMM_3M=0|1 override the defaults (tuning experiments).
@@ -373,6 +395,21 @@ hipError_t cgemm_batch2(hipStream_t st, char ta, char tb, int64_t m, int64_t n, 
 }
 
 template <typename R>
+hipError_t cgemm_rb(hipStream_t st, int64_t m, int64_t n, int64_t k, const cx<R>* A, int64_t lda, int64_t sA,
+                    const R* B, int64_t ldb, int64_t sB, cx<R>* C, int64_t ldc, int64_t sC, int64_t batch)
+{
+    // C = A B with B real (ldb, sB in real elements)
+    CGemmArgs<R> a{};
+    a.m = m; a.n = n; a.k = k; a.nseg = 1;
+    a.A[0] = a.A[1] = A; a.lda[0] = a.lda[1] = lda; a.sA[0] = a.sA[1] = sA; a.ta[0] = a.ta[1] = 0;
+    a.B[0] = a.B[1] = reinterpret_cast<const cx<R>*>(B);
+    a.ldb[0] = a.ldb[1] = ldb; a.sB[0] = a.sB[1] = sB; a.tb[0] = a.tb[1] = 2;
+    a.alpha = mk<R>(1, 0); a.beta = mk<R>(0, 0);
+    a.C = C; a.ldc = ldc; a.sC = sC; a.lower = 0;
+    return launch_cgemm<R>(a, batch, st);
+}
+
+template <typename R>
 hipError_t cher2k_lower(hipStream_t st, int64_t m, int64_t k, const cx<R>* V, int64_t ldv, int64_t sV,
                         const cx<R>* W, int64_t ldw, int64_t sW, cx<R>* C, int64_t ldc, int64_t sC,
                         int64_t batch)
@@ -402,6 +439,8 @@ template hipError_t cgemm_batch2<double>(hipStream_t, char, char, int64_t, int64
 template hipError_t cgemm_batch2<float>(hipStream_t, char, char, int64_t, int64_t, int64_t, float2, const float2*,
                                         int64_t, int64_t, int64_t, const float2*, int64_t, int64_t, int64_t, float2,
                                         float2*, int64_t, int64_t, int64_t, int64_t, int64_t);
+template hipError_t cgemm_rb<double>(hipStream_t, int64_t, int64_t, int64_t, const double2*, int64_t, int64_t,
+                                     const double*, int64_t, int64_t, double2*, int64_t, int64_t, int64_t);
 template hipError_t cher2k_lower<double>(hipStream_t, int64_t, int64_t, const double2*, int64_t, int64_t,
                                          const double2*, int64_t, int64_t, double2*, int64_t, int64_t,
                                          int64_t);

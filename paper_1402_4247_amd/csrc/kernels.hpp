@@ -38,6 +38,11 @@ hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t
                  const cx<R>* A, int64_t lda, int64_t sA, const cx<R>* B, int64_t ldb, int64_t sB,
                  cx<R> beta, cx<R>* C, int64_t ldc, int64_t sC, int64_t batch, bool lower);
 
+// C = A B with A complex (m x k) and B real (k x n; ldb, sB in real elements)
+template <typename R>
+hipError_t cgemm_rb(hipStream_t st, int64_t m, int64_t n, int64_t k, const cx<R>* A, int64_t lda, int64_t sA,
+                    const R* B, int64_t ldb, int64_t sB, cx<R>* C, int64_t ldc, int64_t sC, int64_t batch);
+
 // C(lower) -= V W^H + W V^H   (m x m, inner dimension k)
 // C_L = alpha op(A_L) op(B_L) + beta C_L for L = (l1, l2), l1 < batch,
 // l2 < batch2, operands at base + l1 * s + l2 * s2
@@ -152,10 +157,13 @@ struct RefineWs {
 // `iters` refinement sweeps; lam_out (n per problem) gets the refined eigenvalues
 hipError_t refine(hipStream_t st, const RefineWs& ws, int64_t nk, int iters, double* lam_out);
 
-// back-transformation U <- Q U (unmtr.hip); work: see unmtr_work_elems
+// back-transformation U <- Q U, or U <- U Q with right (util.hip); work: see
+// unmtr_work_elems
 template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
-                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk);
+                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk, bool right = false);
+// unit 2-norm columns of a real n x n matrix
+hipError_t normalize_cols_real(hipStream_t st, int64_t n, double* Z, int64_t ldz, int64_t sz, int64_t nk);
 int64_t unmtr_work_elems(int64_t n, int kb);   // complex elements per problem
 
 // ---------------------------------------------------------------------------

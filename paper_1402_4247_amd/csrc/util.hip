@@ -110,6 +110,20 @@ __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, i
     for (int64_t i = threadIdx.x; i < n; i += 256) u[i] = cscale(u[i], f);
 }
 
+// unit 2-norm columns of a real matrix (n x n, ld ldz, batch stride sz)
+__global__ __launch_bounds__(256) void k_normalize_cols_real(int64_t n, double* Z, int64_t ldz, int64_t sz)
+{
+    __shared__ double sh[4];
+    double* z = Z + (int64_t)blockIdx.y * sz + (int64_t)blockIdx.x * ldz;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc = fma(z[i], z[i], acc);
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double f = 1.0 / sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
+    for (int64_t i = threadIdx.x; i < n; i += 256) z[i] *= f;
+}
+
 // T (kk x kk, upper) for reflectors c0..c0+kk-1 (compact WY):
 // T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V_b^H V_b.
 constexpr int KBMAX = 64;
@@ -254,6 +268,12 @@ hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, in
     return hipGetLastError();
 }
 
+hipError_t normalize_cols_real(hipStream_t st, int64_t n, double* Z, int64_t ldz, int64_t sz, int64_t nk)
+{
+    hipLaunchKernelGGL(k_normalize_cols_real, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, Z, ldz, sz);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Pruned canonical orthogonalisation.  The s_j <= s_tol s_max directions are
 // the first ndrop columns of X (s ascending) and are zero there, so rows and
@@ -384,7 +404,7 @@ __global__ __launch_bounds__(256) void k_pair_t(int kb, int nblk, const cx<R>* T
 
 template <typename R>
 hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx<R>* tau, int64_t stau, cx<R>* U,
-                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk)
+                 int64_t ldu, int64_t sU, cx<R>* work, int kb, int64_t nk, bool right)
 {
     const int64_t nref = n - 1;
     if (nref <= 0) return hipSuccess;
@@ -450,6 +470,24 @@ hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx
                      TB + q * 4 * kb2 + kb * ld2, ld2, sw, nk, false);
         if (e != hipSuccess) return e;
     }
+    if (right) {
+        // U <- U Q = U B_0 B_1 ..., B_q = I - V_q T_q V_q^H: first block first
+        for (int64_t q = 0; q < npair; ++q) {
+            const int64_t c0 = 2 * q * kb;
+            const int kk = (int)((nref - c0) < 2 * kb ? (nref - c0) : 2 * kb);
+            const int64_t r0 = c0 + 1, m = n - r0;
+            const cx<R>* Vb = V + r0 + c0 * n;
+            // W1 = U(:, r0:n) V_q (n x kk), W2 = W1 T_q, U(:, r0:n) -= W2 V_q^H
+            e = cgemm<R>(st, 'N', 'N', n, kk, m, one, U + r0 * ldu, ldu, sU, Vb, n, sV, zero, W1, n, sw, nk, false);
+            if (e != hipSuccess) return e;
+            e = cgemm<R>(st, 'N', 'N', n, kk, kk, one, W1, n, sw, TB + q * 4 * kb2, ld2, sw, zero, W2, n, sw, nk,
+                         false);
+            if (e != hipSuccess) return e;
+            e = cgemm<R>(st, 'N', 'C', n, m, kk, mone, W2, n, sw, Vb, n, sV, one, U + r0 * ldu, ldu, sU, nk, false);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     // apply the 2kb-blocks, last first
     for (int64_t q = npair - 1; q >= 0; --q) {
         const int64_t c0 = 2 * q * kb;
@@ -467,8 +505,8 @@ hipError_t unmtr(hipStream_t st, int64_t n, const cx<R>* V, int64_t sV, const cx
 }
 
 template hipError_t unmtr<double>(hipStream_t, int64_t, const double2*, int64_t, const double2*, int64_t, double2*,
-                                  int64_t, int64_t, double2*, int, int64_t);
+                                  int64_t, int64_t, double2*, int, int64_t, bool);
 template hipError_t unmtr<float>(hipStream_t, int64_t, const float2*, int64_t, const float2*, int64_t, float2*,
-                                 int64_t, int64_t, float2*, int, int64_t);
+                                 int64_t, int64_t, float2*, int, int64_t, bool);
 
 }  // namespace kgev

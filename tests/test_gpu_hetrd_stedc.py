@@ -37,8 +37,10 @@ def gpu_hetrd(As, nb=0):
     return dd.cpu().numpy(), de.cpu().numpy(), dtau.cpu().numpy(), host(dV)
 
 
-@pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (3, 0), (17, 0), (64, 0), (65, 0), (130, 0), (200, 0),
-                                  (200, 8), (97, 64)])
+# n <= 128 runs entirely in the LDS-resident tail kernel; larger n hands over
+# to it at the first panel start whose trailing order is at most 128
+@pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (3, 0), (17, 0), (64, 0), (65, 0), (128, 0), (129, 0), (130, 0),
+                                  (161, 0), (200, 0), (200, 8), (97, 64), (250, 24), (300, 48)])
 def test_hetrd_matches_oracle(n, nb):
     rng = np.random.default_rng(n + 7 * nb)
     nk = 2
