@@ -9,7 +9,9 @@
  *   Part 2  diagonalise S and rearrange it:  S = U diag(s) U^H,
  *           X = U diag(s)^(-1/2)  (canonical orthogonalisation);
  *   Part 3  form "S^H H S" = X^H H X  (matrix products);
- *   Part 4  diagonalise it with Eigen_HH and one matrix product C = X Y.
+ *   Part 4  diagonalise it with Eigen_HH and one matrix product C = X Y
+ *           (evaluated as (X Q) Z, Q the Householder reflectors and Z the
+ *           tridiagonal eigenvectors: the same C).
  * Eigen_HH (Section III) is: Householder tridiagonalisation (Procedures 1-6),
  * a tridiagonal eigensolve, back-transformation ("rearrangement of
  * eigenvectors") and normalisation.  Every step runs in HIP kernels on the

@@ -4,8 +4,9 @@
 //   Part 2: S -> tridiagonal (blocked Householder) -> divide and conquer ->
 //           back-transformation -> X = U diag(s)^(-1/2) (+ definiteness check)
 //   Part 3: G = H X, A = X^H G (lower half)
-//   Part 4: A -> tridiagonal -> divide and conquer -> back-transformation ->
-//           normalisation -> C = X Y
+//   Part 4: A -> tridiagonal -> divide and conquer -> normalisation ->
+//           C = X Y with Y = Q_A Z taken as (X Q_A) Z: the back-transformation
+//           applied to a copy of X from the right, then the real Z
 // Every step is a HIP kernel enqueued on the caller's stream; the host only
 // sizes the workspace and issues launches.
 #include <stdio.h>
