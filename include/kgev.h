@@ -193,6 +193,37 @@ kgev_status kgev_solve_k_x_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z*
                                   void* stream);
 
 /*
+ * A batch of systems of uneven order: problem q is solved exactly as
+ * kgev_solve_k_device would solve it (all of its k-points in one batched
+ * call, with the same opts), the problems one after another on `stream`,
+ * sharing one workspace.  With opts.use_graph and a non-null stream, the
+ * whole batch is captured once as one HIP graph and replayed by later calls
+ * with the same problems, buffers, workspace, options and stream.
+ *   probs  : host array of count problem descriptors (read during the call
+ *            only); each field as the argument of kgev_solve_k_device of the
+ *            same name (d_status may be NULL).
+ *   dwork  : device workspace of work_bytes >= kgev_batch_workspace_bytes(
+ *            probs, count, opts), or NULL for the context's workspace.
+ * Returns -1 ctx, -2 probs, -3 count < 1, -4 work too small, -5 opts
+ * invalid, -(1000 + q) for an invalid descriptor q (n < 1, ld < n, nk < 1,
+ * a required pointer NULL, ldc < n with vectors), else KGEV_OK once every
+ * kernel is enqueued; per-k statuses land in each problem's d_status.
+ */
+typedef struct kgev_problem {
+    int64_t n, ld, nk;
+    const kgev_z* dH;
+    const kgev_z* dS;
+    double* dw;
+    kgev_z* dC;
+    int64_t ldc;
+    int32_t* d_status;
+} kgev_problem;
+/* the largest per-problem workspace of the batch (0 if none is valid) */
+size_t kgev_batch_workspace_bytes(const kgev_problem* probs, int64_t count, const kgev_opts* opts);
+kgev_status kgev_solve_batch_device(kgev_ctx* ctx, const kgev_problem* probs, int64_t count, void* dwork,
+                                    size_t work_bytes, const kgev_opts* opts, void* stream);
+
+/*
  * Stage entry points.  Each runs one step of the path on nk problems and
  * exists so that every step can be checked on its own; all are device-pointer
  * and asynchronous on `stream`, with the argument conventions above.

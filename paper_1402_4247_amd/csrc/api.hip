@@ -45,6 +45,7 @@ struct kgev_ctx {
     std::vector<hipEvent_t> ev;        // ev[0]: fork, ev[q]: join of group q
     kgev::Profiler* prof;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // most recent last
+    std::vector<std::pair<std::vector<uintptr_t>, hipGraphExec_t>> batch_graphs;   // most recent last
     std::map<std::pair<int64_t, int>, int> tuned_nb;            // (n, precision) -> panel width
     void* work;
     size_t work_bytes;
@@ -509,10 +510,12 @@ kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, vo
 // Destroy every cached graph of the context (after the device is idle).
 void drop_graphs(kgev_ctx* ctx)
 {
-    if (ctx->graphs.empty()) return;
+    if (ctx->graphs.empty() && ctx->batch_graphs.empty()) return;
     (void)hipDeviceSynchronize();
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.second);
     ctx->graphs.clear();
+    for (auto& e : ctx->batch_graphs) (void)hipGraphExecDestroy(e.second);
+    ctx->batch_graphs.clear();
 }
 
 }  // namespace
@@ -572,6 +575,7 @@ void kgev_destroy(kgev_ctx* ctx)
     (void)hipDeviceSynchronize();
     if (ctx->prof) prof_stop(ctx->prof, nullptr, nullptr, nullptr, nullptr, nullptr);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.second);
+    for (auto& e : ctx->batch_graphs) (void)hipGraphExecDestroy(e.second);
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -662,6 +666,103 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
         ctx->graphs.erase(ctx->graphs.begin());
     }
     ctx->graphs.push_back({key, exec});
+    KCHECK(hipGraphLaunch(exec, st));
+    return KGEV_OK;
+}
+
+size_t kgev_batch_workspace_bytes(const kgev_problem* probs, int64_t count, const kgev_opts* opts)
+{
+    if (!probs || count < 1) return 0;
+    size_t mx = 0;
+    for (int64_t q = 0; q < count; ++q)
+        if (probs[q].n >= 1 && probs[q].nk >= 1)
+            mx = std::max(mx, kgev_workspace_bytes(probs[q].n, probs[q].nk, opts));
+    return mx;
+}
+
+kgev_status kgev_solve_batch_device(kgev_ctx* ctx, const kgev_problem* probs, int64_t count, void* dwork,
+                                    size_t work_bytes, const kgev_opts* opts, void* stream)
+{
+    if (!ctx) return -1;
+    if (!probs) return -2;
+    if (count < 1) return -3;
+    const kgev_opts o = resolve_opts(opts);
+    if (!opts_valid(o)) return -5;
+    for (int64_t q = 0; q < count; ++q) {
+        const kgev_problem& pr = probs[q];
+        const bool bad = pr.n < 1 || pr.ld < pr.n || pr.nk < 1 || !pr.dH || !pr.dS || !pr.dw ||
+                         (o.want_vectors && (!pr.dC || pr.ldc < pr.n));
+        if (bad) return (kgev_status)(-(1000 + q));
+    }
+    DevGuard g(ctx->device);
+    const size_t need = kgev_batch_workspace_bytes(probs, count, opts);
+    void* w = dwork;
+    if (w) {
+        if (work_bytes < need) return -4;
+    } else {
+        const kgev_status r = ensure_work(ctx, need);
+        if (r != KGEV_OK) return r;
+        w = ctx->work;
+    }
+    kgev_opts oe = o;     // each problem's call launches its kernels directly
+    oe.use_graph = 0;
+    auto run_all = [&](hipStream_t st) -> kgev_status {
+        for (int64_t q = 0; q < count; ++q) {
+            const kgev_problem& pr = probs[q];
+            const kgev_status r = kgev_solve_k_device(ctx, pr.dH, pr.dS, pr.n, pr.ld, pr.nk, pr.dw, pr.dC, pr.ldc, w,
+                                                      need, pr.d_status, &oe, st);
+            if (r != KGEV_OK) return r;
+        }
+        return KGEV_OK;
+    };
+    hipStream_t st = (hipStream_t)stream;
+    if (!o.use_graph || st == nullptr) return run_all(st);
+    // the graph of this exact batch (problems, buffers, workspace, options, stream)
+    std::vector<uintptr_t> key;
+    key.reserve((size_t)count * 9 + 16);
+    key.push_back((uintptr_t)count);
+    key.push_back((uintptr_t)w);
+    key.push_back((uintptr_t)stream);
+    const unsigned char* ob = reinterpret_cast<const unsigned char*>(&o);
+    for (size_t b = 0; b < sizeof(o); b += sizeof(uintptr_t)) {
+        uintptr_t v = 0;
+        memcpy(&v, ob + b, std::min(sizeof(uintptr_t), sizeof(o) - b));
+        key.push_back(v);
+    }
+    for (int64_t q = 0; q < count; ++q) {
+        const kgev_problem& pr = probs[q];
+        key.push_back((uintptr_t)pr.n); key.push_back((uintptr_t)pr.ld); key.push_back((uintptr_t)pr.nk);
+        key.push_back((uintptr_t)pr.dH); key.push_back((uintptr_t)pr.dS); key.push_back((uintptr_t)pr.dw);
+        key.push_back((uintptr_t)(o.want_vectors ? pr.dC : nullptr));
+        key.push_back((uintptr_t)(o.want_vectors ? pr.ldc : 0)); key.push_back((uintptr_t)pr.d_status);
+    }
+    for (size_t q = 0; q < ctx->batch_graphs.size(); ++q)
+        if (ctx->batch_graphs[q].first == key) {
+            auto e = ctx->batch_graphs[q];
+            ctx->batch_graphs.erase(ctx->batch_graphs.begin() + q);
+            ctx->batch_graphs.push_back(e);
+            KCHECK(hipGraphLaunch(e.second, st));
+            return KGEV_OK;
+        }
+    KCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const kgev_status r = run_all(st);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (r != KGEV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (ec != hipSuccess) return KGEV_EDEVICE;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return KGEV_EDEVICE;
+    if (ctx->batch_graphs.size() >= 4) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(ctx->batch_graphs.front().second);
+        ctx->batch_graphs.erase(ctx->batch_graphs.begin());
+    }
+    ctx->batch_graphs.push_back({key, exec});
     KCHECK(hipGraphLaunch(exec, st));
     return KGEV_OK;
 }

@@ -51,13 +51,20 @@ class Opts(ctypes.Structure):
                 ("s_method", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
+class Problem(ctypes.Structure):
+    """kgev_problem: one system of a kgev_solve_batch_device call."""
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("nk", ctypes.c_int64),
+                ("dH", ctypes.c_void_p), ("dS", ctypes.c_void_p), ("dw", ctypes.c_void_p),
+                ("dC", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("d_status", ctypes.c_void_p)]
+
+
 EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy",
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
            "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device",
-           "kgev_solve_k_x_device"]
+           "kgev_solve_k_x_device", "kgev_batch_workspace_bytes", "kgev_solve_batch_device"]
 PHASE_HEMV, PHASE_GEMM = 1, 2
 S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
 
@@ -107,6 +114,11 @@ def _load():
     lib.kgev_solve_k_x_device.argtypes = [P, P, P, I64, I64, I64, P, P, I64, P, I32, P, ctypes.c_size_t, P,
                                           ctypes.POINTER(Opts), P]
     lib.kgev_solve_k_x_device.restype = I32
+    lib.kgev_batch_workspace_bytes.argtypes = [ctypes.POINTER(Problem), I64, ctypes.POINTER(Opts)]
+    lib.kgev_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.kgev_solve_batch_device.argtypes = [P, ctypes.POINTER(Problem), I64, P, ctypes.c_size_t,
+                                            ctypes.POINTER(Opts), P]
+    lib.kgev_solve_batch_device.restype = I32
     lib.kgev_zgemm_device.argtypes = [P, ctypes.c_char, ctypes.c_char, I64, I64, I64, Z, P, I64, I64,
                                       P, I64, I64, Z, P, I64, I64, I64, I32, P]
     lib.kgev_zgemm_device.restype = I32
@@ -226,6 +238,26 @@ def solve_k_x_device(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, dX, x_mode, d
     return lib.kgev_solve_k_x_device(ctx.handle, _ptr(dH), _ptr(dS), n, ld, nk, _ptr(dw), _ptr(dC), ldc, _ptr(dX),
                                      int(x_mode), _ptr(dwork), work_bytes, _ptr(d_status),
                                      None if opts is None else ctypes.byref(opts), _stream(stream))
+
+
+def problem(dH, dS, n, ld, nk, dw, dC=None, ldc=0, d_status=None) -> Problem:
+    """One kgev_problem from device tensors (column-major per k)."""
+    def addr(t):
+        return None if t is None else t.data_ptr()
+    return Problem(n, ld, nk, addr(dH), addr(dS), addr(dw), addr(dC), ldc, addr(d_status))
+
+
+def batch_workspace_bytes(problems, opts: Opts | None = None) -> int:
+    arr = (Problem * len(problems))(*problems)
+    return lib.kgev_batch_workspace_bytes(arr, len(problems), None if opts is None else ctypes.byref(opts))
+
+
+def solve_batch_device(ctx: Context, problems, dwork=None, work_bytes=0, opts: Opts | None = None,
+                       stream=None) -> int:
+    """kgev_solve_batch_device: systems of uneven order in one call."""
+    arr = (Problem * len(problems))(*problems)
+    return lib.kgev_solve_batch_device(ctx.handle, arr, len(problems), _ptr(dwork), work_bytes,
+                                       None if opts is None else ctypes.byref(opts), _stream(stream))
 
 
 def solve_k(ctx: Context, H, S, n, nk, w, C, opts: Opts | None = None):

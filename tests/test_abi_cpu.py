@@ -64,3 +64,12 @@ def test_host_api_rejects_null_context():
     bad = ctypes.c_int64(7)
     st = K.lib.kgev_solve_k(None, None, None, 4, 1, None, None, None, ctypes.byref(bad))
     assert st == -1 and bad.value == -1
+
+
+def test_batch_workspace_is_the_largest_problem_and_null_ctx_rejected():
+    ps = [K.Problem(70, 70, 2), K.Problem(130, 130, 1), K.Problem(33, 40, 3)]
+    arr = (K.Problem * 3)(*ps)
+    got = K.lib.kgev_batch_workspace_bytes(arr, 3, None)
+    assert got == max(K.lib.kgev_workspace_bytes(p.n, p.nk, None) for p in ps) > 0
+    assert K.lib.kgev_batch_workspace_bytes(arr, 0, None) == 0
+    assert K.lib.kgev_solve_batch_device(None, arr, 3, None, 0, None, None) == -1

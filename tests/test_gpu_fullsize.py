@@ -3,8 +3,8 @@ benchmark times (one batched call per system, default options unless the
 form says otherwise):
 
 * the magnetite-like LCAO system at n = 2000 with 16 k-points (the benchmark
-  batch), and at n = 3000 and n = 6000 (the serving stream's largest order)
-  with one k-point;
+  batch), and at n = 3000, n = 6000 (the serving stream's largest order) and
+  n = 12000 (one matrix over 2 GiB) with one k-point;
 * the batched form: n = 1024, all 64 k-points of the 4x4x4 grid in one
   captured-graph call with the autotuned panel width;
 * the mixed-precision form: n = 4096, the 8 k-points of the 2x2x2 grid,
@@ -112,6 +112,20 @@ def test_lcao_n6000_one_k():
     with kg.Context(0) as ctx:
         dw, dC, st = solve(ctx, dH, dS, n, nk, kg.make_opts())
     check_all(dH, dS, dw, dC, st, "n=6000 x1")
+
+
+@pytest.mark.timeout(900)
+def test_lcao_n12000_one_k_over_2gib():
+    # one matrix over 2 GiB: the Hermitian product takes its plain-load path
+    # (32-bit buffer offsets no longer cover the matrix)
+    kg = K()
+    n, nk = 12000, 1
+    Hs, Ss = G.config2(n, nk, 2002)
+    dH, dS = to_dev(Hs), to_dev(Ss)
+    del Hs, Ss
+    with kg.Context(0) as ctx:
+        dw, dC, st = solve(ctx, dH, dS, n, nk, kg.make_opts())
+    check_all(dH, dS, dw, dC, st, "n=12000 x1")
 
 
 @pytest.mark.timeout(600)
