@@ -25,6 +25,8 @@
 //       partials.
 // After the panel the trailing matrix takes the rank-2nb update
 // A22 -= V W^H + W V^H (Procedure 6, on MFMA).
+// Once a panel's trailing matrix has at most 128 rows, the rest of the
+// reduction runs in one launch, unblocked, with the matrix in LDS (tail).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible run to run.
 #include <stdlib.h>
