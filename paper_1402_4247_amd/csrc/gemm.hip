@@ -40,17 +40,31 @@ struct CGemmArgs {
     int64_t batch2;            // inner batch: product L -> (L / batch2, L % batch2)
     int64_t sA2[2], sB2[2], sC2;   // strides of the inner batch index
     int remap;
+    int tri;                   // enumerate only the tiles on or below the diagonal
 };
 
 // Work item of this workgroup.  Consecutive workgroups are dispatched round
 // robin over the 8 XCDs, so the 1-D id is remapped to give each XCD a
 // contiguous range of tiles (one L2 sees neighbouring tiles); inside a
 // problem tiles go in groups of 4 tile-rows so the tiles running together
-// share A row panels and B column panels.
-__device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_n, int remap, int64_t& b, int& tm,
-                               int& tn)
+// share A row panels and B column panels.  A lower-triangle product of a
+// square C (tri) launches only the tiles on or below the diagonal, taken
+// row by row (row tm holds tiles 0..tm, starting at tm (tm + 1) / 2).
+__device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_n, int remap, int tri, int64_t& b,
+                               int& tm, int& tn)
 {
     const int64_t logical = (remap && total % 8 == 0) ? (L % 8) * (total / 8) + L / 8 : L;
+    if (tri) {
+        const int64_t T = (int64_t)tiles_m * (tiles_m + 1) / 2;
+        b = logical / T;
+        const int64_t t = logical % T;
+        int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while (r > 0 && (int64_t)r * (r + 1) / 2 > t) --r;
+        while ((int64_t)(r + 1) * (r + 2) / 2 <= t) ++r;
+        tm = r;
+        tn = (int)(t - (int64_t)r * (r + 1) / 2);
+        return;
+    }
     const int64_t T = (int64_t)tiles_m * tiles_n;
     b = logical / T;
     const int t = (int)(logical % T);
@@ -156,10 +170,10 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
     __shared__ R sAr[NST][GB_K][BM + 1], sAi[NST][GB_K][BM + 1];
     __shared__ R sBr[NST][GB_K][BN + 1], sBi[NST][GB_K][BN + 1];
 
-    const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
+    const int64_t total = (p.tri ? (int64_t)p.tiles_m * (p.tiles_m + 1) / 2 : (int64_t)p.tiles_m * p.tiles_n) * p.batch;
     int64_t bz;
     int tm, tn;
-    tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, p.remap, bz, tm, tn);
+    tile_of(blockIdx.x, total, p.tiles_m, p.tiles_n, p.remap, p.tri, bz, tm, tn);
     const int64_t bo = bz / p.batch2, bi = bz - bo * p.batch2;
     const int64_t m = p.m, n = p.n, K = p.k;
     const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
@@ -303,7 +317,8 @@ hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st, const ProfLaunch& pl)
 {
     p.tiles_m = (int)((p.m + BM - 1) / BM);
     p.tiles_n = (int)((p.n + BN - 1) / BN);
-    const int64_t total = (int64_t)p.tiles_m * p.tiles_n * p.batch;
+    p.tri = (p.lower && BM == BN && p.tiles_m == p.tiles_n) ? 1 : 0;
+    const int64_t total = (p.tri ? (int64_t)p.tiles_m * (p.tiles_m + 1) / 2 : (int64_t)p.tiles_m * p.tiles_n) * p.batch;
     launch_timed(pl, cgemm_kernel<R, BM, BN, G3, TA, TB, NST>, dim3((unsigned)total), dim3(G_THREADS), st, p);
     return hipGetLastError();
 }
