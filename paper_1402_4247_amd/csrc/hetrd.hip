@@ -39,6 +39,7 @@ namespace kgev {
 namespace {
 
 constexpr int ZT = 64;          // ZHEMV tile edge
+constexpr int NT_LOAD = 2;      // buffer-load cache policy: non-temporal
 constexpr int ZCH = 4;          // tiles per ZHEMV chunk: one per wave of the workgroup
 constexpr int RB = 64;          // rows per workgroup in the column kernels
 
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // reduction, or, by default, column sums through LDS that leave the registers
 // free for the next group's loads), and the four waves' column sums are added
 // once.
-template <typename R, int MINW, bool BUF, int PF>
+template <typename R, int MINW, bool BUF, int PF, int AUX = 0>
 __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
 {
     __shared__ cx<R> svC[ZT];
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
     // Matrices under 2 GiB are read with buffer loads: one 32-bit row offset
     // per lane shared by every load of the tile, the column offset in a
     // scalar register (fewer vector registers and no 64-bit address
-    // arithmetic); larger ones with plain global loads.
+    // arithmetic); larger ones with plain global loads.  AUX is the buffer
+    // loads' cache policy (0 default, NT_LOAD non-temporal).
     const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
@@ -183,10 +185,10 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
             if constexpr (BUF) {
                 const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
                 if constexpr (sizeof(R) == 8) {
-                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, AUX);
                     a[cc] = __builtin_bit_cast(cx<R>, v);
                 } else {
-                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, AUX);
                     a[cc] = __builtin_bit_cast(cx<R>, v);
                 }
             } else {
@@ -717,6 +719,17 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
         const int t = v ? atoi(v) : TAIL_M;
         return t < 0 ? 0 : (t > TAIL_M ? TAIL_M : t);
     }();
+    // The tile loads take the non-temporal policy once a launch's lower
+    // triangles (all k-points) exceed 1.5 x the 256 MB memory-side cache:
+    // below that the default policy keeps part of the trailing matrices in
+    // that cache from one column to the next (measured 13% faster at
+    // n = 2000 x 16, m = 1250..1500), above it nothing survives a column and
+    // the non-temporal loads stream faster (5% at m >= 1750).
+    // KGEV_HEMV_NT_MB overrides the threshold (MiB; 0: always).
+    static const double nt_bytes = [] {
+        const char* v = getenv("KGEV_HEMV_NT_MB");
+        return (v ? atof(v) : 384.0) * 1048576.0;
+    }();
     for (int p = 0; p <= n - 1; p += nb) {
         if (n - p <= tail_m && p < n - 1) {
             hipLaunchKernelGGL(hetrd_tail<R>, dim3((unsigned)nk), dim3(TAIL_T), 0, st, ws, p);
@@ -736,6 +749,8 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
                 launch_timed(pl, hetrd_zhemv<R, 1, false, 1>, gz, dim3(256), st, ws, i);
             else if (variant == 30)
                 launch_timed(pl, hetrd_zhemv<R, 3, true, 0>, gz, dim3(256), st, ws, i);
+            else if ((double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk >= nt_bytes)
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 3, NT_LOAD>, gz, dim3(256), st, ws, i);
             else
                 launch_timed(pl, hetrd_zhemv<R, 3, true, 3>, gz, dim3(256), st, ws, i);
             prof_launch_end(PH_HEMV, st, pl,
