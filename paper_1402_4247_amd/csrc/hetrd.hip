@@ -137,20 +137,24 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // free for the next group's loads), and the four waves' column sums are added
 // once.
 template <typename R, int MINW, bool BUF, int PF, int AUX = 0>
-__global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
+__global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, int rev)
 {
     __shared__ cx<R> svC[ZT];
     __shared__ cx<R> sT[ZCH][ZT];
     // per-wave staging of one group's products (PF == 3)
     __shared__ cx<R> sP[PF == 3 ? ZCH : 1][8][ZT + 1];
-    const int64_t b = blockIdx.y;
+    // rev: the workgroups take the chunks in reverse order (last k-point's
+    // last chunk first), so that a launch after a forward one starts on the
+    // tiles its predecessor read last
+    const int64_t b = rev ? (int64_t)(gridDim.y - 1 - blockIdx.y) : (int64_t)blockIdx.y;
+    const int lid = rev ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
     const int n = ws.n;
     const int o = i + 1;
     const int m = n - o;
     const int NB = (m + ZT - 1) / ZT;
 
     // which (block column C, chunk ch) is ours
-    int bid = blockIdx.x, C = 0;
+    int bid = lid, C = 0;
     for (; C < NB; ++C) {
         const int nc = nchunks(NB, C);
         if (bid < nc) break;
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i)
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
         R qt = svC[tid].x * s.x + svC[tid].y * s.y;
         qt = wave_sum(qt);
-        if (tid == 0) ws.qpart[b * ws.s_qpart + blockIdx.x] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
+        if (tid == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
 }
 
@@ -719,16 +723,23 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
         const int t = v ? atoi(v) : TAIL_M;
         return t < 0 ? 0 : (t > TAIL_M ? TAIL_M : t);
     }();
-    // The tile loads take the non-temporal policy once a launch's lower
-    // triangles (all k-points) exceed 1.5 x the 256 MB memory-side cache:
-    // below that the default policy keeps part of the trailing matrices in
-    // that cache from one column to the next (measured 13% faster at
-    // n = 2000 x 16, m = 1250..1500), above it nothing survives a column and
-    // the non-temporal loads stream faster (5% at m >= 1750).
-    // KGEV_HEMV_NT_MB overrides the threshold (MiB; 0: always).
+    // Consecutive columns traverse their tiles in opposite orders (odd columns
+    // from the last k-point's last chunk back), so each launch starts on the
+    // tiles its predecessor read last, which the 256 MB memory-side cache still
+    // holds once the lower triangles of all k-points exceed it (n = 2000 x 16:
+    // 9% faster at m = 1500..1750, 3.4% over the step's products).
+    // KGEV_HEMV_ZIGZAG=0 keeps every launch in forward order.
+    static const int zigzag = [] {
+        const char* v = getenv("KGEV_HEMV_ZIGZAG");
+        return v ? atoi(v) : 1;
+    }();
+    // KGEV_HEMV_NT_MB (MiB): tile loads take the non-temporal policy when a
+    // launch's lower triangles exceed this size (default: never).  Without the
+    // alternating order that was 5% faster from m = 1750 at n = 2000 x 16;
+    // with it the default policy is faster.
     static const double nt_bytes = [] {
         const char* v = getenv("KGEV_HEMV_NT_MB");
-        return (v ? atof(v) : 384.0) * 1048576.0;
+        return v ? atof(v) * 1048576.0 : 1e300;
     }();
     for (int p = 0; p <= n - 1; p += nb) {
         if (n - p <= tail_m && p < n - 1) {
@@ -743,16 +754,17 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int NB = (m + ZT - 1) / ZT;
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
+            const int rev = zigzag ? (i & 1) : 0;
             const ProfLaunch pl = prof_launch_begin(PH_HEMV, st);
             const dim3 gz((unsigned)nch, (unsigned)nk);
             if (!buf)
-                launch_timed(pl, hetrd_zhemv<R, 1, false, 1>, gz, dim3(256), st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 1, false, 1>, gz, dim3(256), st, ws, i, rev);
             else if (variant == 30)
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 0>, gz, dim3(256), st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 0>, gz, dim3(256), st, ws, i, rev);
             else if ((double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk >= nt_bytes)
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 3, NT_LOAD>, gz, dim3(256), st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 3, NT_LOAD>, gz, dim3(256), st, ws, i, rev);
             else
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 3>, gz, dim3(256), st, ws, i);
+                launch_timed(pl, hetrd_zhemv<R, 3, true, 3>, gz, dim3(256), st, ws, i, rev);
             prof_launch_end(PH_HEMV, st, pl,
                             (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
