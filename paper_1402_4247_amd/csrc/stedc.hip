@@ -363,23 +363,30 @@ __global__ __launch_bounds__(64) void dc_zhat(DcWs ws, int t)
     if (g.e - g.s < 2) return;
     const int64_t s = g.s;
     const int K = ws.kcnt[b * n + s];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= K) return;
+    // SEC_LANES lanes per index i: lane `sub` multiplies the factors
+    // q = sub mod SEC_LANES, a butterfly of products combines them (bitwise
+    // equal in every lane of the group)
+    const int gt = blockIdx.x * 64 + threadIdx.x;
+    const int i = gt / SEC_LANES, sub = gt % SEC_LANES;
+    if (i >= K) return;          // the lanes of an index leave together
     const double* dl = ws.ndd + b * n + s;
     const double* zl = ws.ndz + b * n + s;
     const int* org = ws.orgi + b * n + s;
     const double* tv = ws.tauv + b * n + s;
     const double rho = ws.rho[b * n + s];
     const double di = dl[i];
-    double p = ((dl[org[i]] - di) + tv[i]) / rho;
-    for (int q = 0; q < K; ++q) {
+    double p = sub == 0 ? ((dl[org[i]] - di) + tv[i]) / rho : 1.0;
+    for (int q = sub; q < K; q += SEC_LANES) {
         if (q == i) continue;
         p *= ((dl[org[q]] - di) + tv[q]) / (dl[q] - di);
     }
-    ws.zhat[b * n + s + i] = copysign(sqrt(fmax(p, 0.0)), zl[i]);
+#pragma unroll
+    for (int m = 1; m < SEC_LANES; m <<= 1) p *= __shfl_xor(p, m, WAVE);
+    if (sub == 0) ws.zhat[b * n + s + i] = copysign(sqrt(fmax(p, 0.0)), zl[i]);
 }
 
 // Eigenvectors of D + rho z z^T: column j = zhat / (d - lambda_j), normalised.
+// One wave per column, the lanes over its rows (coalesced stores).
 __global__ __launch_bounds__(64) void dc_vectors(DcWs ws, int t)
 {
     const int64_t b = blockIdx.z;
@@ -388,21 +395,24 @@ __global__ __launch_bounds__(64) void dc_vectors(DcWs ws, int t)
     if (g.e - g.s < 2) return;
     const int64_t s = g.s;
     const int K = ws.kcnt[b * n + s];
-    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.x;
     if (j >= K) return;
+    const int lane = threadIdx.x;
     const double* dl = ws.ndd + b * n + s;
     const double* zh = ws.zhat + b * n + s;
     const int oj = ws.orgi[b * n + s + j];
     const double tj = ws.tauv[b * n + s + j];
     const double dorg = dl[oj];
     double ss = 0.0;
-    for (int i = 0; i < K; ++i) {
+    for (int i = lane; i < K; i += 64) {
         const double v = zh[i] / ((dl[i] - dorg) - tj);
         ss += v * v;
     }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) ss += __shfl_xor(ss, m, WAVE);
     const double inv = 1.0 / sqrt(ss);
     double* Vc = ws.Vsec + b * ws.sQ + (s + j) * n + s;
-    for (int i = 0; i < K; ++i) Vc[i] = zh[i] / ((dl[i] - dorg) - tj) * inv;
+    for (int i = lane; i < K; i += 64) Vc[i] = zh[i] / ((dl[i] - dorg) - tj) * inv;
 }
 
 // Final ascending order of the merged eigenvalues (secular roots and deflated
@@ -604,8 +614,8 @@ hipError_t stedc(hipStream_t st, const DcWs& ws0, double* w, double* Z, double* 
         hipLaunchKernelGGL(dc_deflate, dim3(segs, (unsigned)nk), dim3(256), dyn_bytes, st, ws, t, rb, cap);
         const unsigned gxs = (unsigned)((nsmax * SEC_LANES + 63) / 64);
         hipLaunchKernelGGL(dc_secular, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
-        hipLaunchKernelGGL(dc_zhat, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
-        hipLaunchKernelGGL(dc_vectors, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
+        hipLaunchKernelGGL(dc_zhat, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
+        hipLaunchKernelGGL(dc_vectors, dim3((unsigned)nsmax, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_order, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t, wb);
         hipLaunchKernelGGL(dc_place, dim3((unsigned)nsmax, segs, (unsigned)nk), dim3(256), 0, st, ws, t, rb, wb);
         const int tiles = (int)((nsmax + DB - 1) / DB);
