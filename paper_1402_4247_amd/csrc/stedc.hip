@@ -427,16 +427,21 @@ __global__ __launch_bounds__(64) void dc_order(DcWs ws, int t, int wb)
     const int64_t s = g.s;
     const int K = ws.kcnt[b * n + s];
     const int nd = ws.ndcnt[b * n + s];
-    const int q = blockIdx.x * 64 + threadIdx.x;
-    if (q >= K + nd) return;
+    // SEC_LANES lanes per value, each counting a strided share of the others
+    const int gt = blockIdx.x * 64 + threadIdx.x;
+    const int q = gt / SEC_LANES, sub = gt % SEC_LANES;
+    if (q >= K + nd) return;          // the lanes of a value leave together
     const double* lam = ws.lam + b * n + s;
     const double* dfd = ws.dfd + b * n + s;
     const double v = (q < K) ? lam[q] : dfd[q - K];
     int rank = 0;
-    for (int r = 0; r < K + nd; ++r) {
+    for (int r = sub; r < K + nd; r += SEC_LANES) {
         const double u = (r < K) ? lam[r] : dfd[r - K];
         if (u < v || (u == v && r < q)) ++rank;
     }
+#pragma unroll
+    for (int m = 1; m < SEC_LANES; m <<= 1) rank += __shfl_xor(rank, m, WAVE);
+    if (sub != 0) return;
     rank = min(rank, ns - 1);
     ws.D[wb][b * n + s + rank] = v;
     ws.cmap[b * n + s + q] = rank;      // entries [0,K): product columns, [K,K+nd): deflated
@@ -608,7 +613,6 @@ hipError_t stedc(hipStream_t st, const DcWs& ws0, double* w, double* Z, double* 
         const int rb = (L - t - 1) & 1, wb = (L - t) & 1;
         const unsigned segs = 1u << t;
         const int64_t nsmax = ((n + segs - 1) / segs) + 1;
-        const unsigned gx = (unsigned)((nsmax + 63) / 64);
         const int cap = (int)std::min<int64_t>(nsmax, 3200);
         const size_t dyn_bytes = (size_t)cap * (2 * sizeof(double) + sizeof(int));
         hipLaunchKernelGGL(dc_deflate, dim3(segs, (unsigned)nk), dim3(256), dyn_bytes, st, ws, t, rb, cap);
@@ -616,7 +620,7 @@ hipError_t stedc(hipStream_t st, const DcWs& ws0, double* w, double* Z, double* 
         hipLaunchKernelGGL(dc_secular, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_zhat, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
         hipLaunchKernelGGL(dc_vectors, dim3((unsigned)nsmax, segs, (unsigned)nk), dim3(64), 0, st, ws, t);
-        hipLaunchKernelGGL(dc_order, dim3(gx, segs, (unsigned)nk), dim3(64), 0, st, ws, t, wb);
+        hipLaunchKernelGGL(dc_order, dim3(gxs, segs, (unsigned)nk), dim3(64), 0, st, ws, t, wb);
         hipLaunchKernelGGL(dc_place, dim3((unsigned)nsmax, segs, (unsigned)nk), dim3(256), 0, st, ws, t, rb, wb);
         const int tiles = (int)((nsmax + DB - 1) / DB);
         hipLaunchKernelGGL(dc_gemm, dim3((unsigned)(tiles * tiles), segs, (unsigned)nk), dim3(256), 0, st, ws, t, rb, wb,
