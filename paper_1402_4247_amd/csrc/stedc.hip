@@ -176,28 +176,33 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb, int ld
         if (rho * zmx <= tol) {
             for (int q = 0; q < ns; ++q) { dfx[nd] = perm[q]; dfd[nd] = sd[q]; ++nd; }
         } else {
-            int prev = -1;
+            // the pending kept candidate (pole d_p, component z_p, column c_p)
+            // is carried in registers; a rotation folds it into the next one
+            bool have = false;
+            double zp = 0.0, dpv = 0.0;
+            int cp = 0;
             for (int q = 0; q < ns; ++q) {
-                if (rho * fabs(sz[q]) <= tol) { dfx[nd] = perm[q]; dfd[nd] = sd[q]; ++nd; continue; }
-                if (prev < 0) { prev = q; continue; }
-                const double zs = sz[prev], zc2 = sz[q];
-                const double tau = hypot(zc2, zs);
-                const double c = zc2 / tau, sn = -zs / tau;
-                const double gap = sd[q] - sd[prev];
-                if (fabs(gap * c * sn) <= tol) {
-                    sz[q] = tau;
-                    sz[prev] = 0.0;
-                    rota[nr] = perm[prev]; rotb[nr] = perm[q]; rotc[nr] = c; rots[nr] = sn; ++nr;
-                    const double dp = sd[prev], dq = sd[q];
-                    sd[prev] = dp * c * c + dq * sn * sn;
-                    sd[q] = dp * sn * sn + dq * c * c;
-                    dfx[nd] = perm[prev]; dfd[nd] = sd[prev]; ++nd;
+                const double zq = sz[q], dq = sd[q];
+                const int cq = perm[q];
+                if (rho * fabs(zq) <= tol) { dfx[nd] = cq; dfd[nd] = dq; ++nd; continue; }
+                if (!have) { have = true; zp = zq; dpv = dq; cp = cq; continue; }
+                // |gap c s| <= tol with c = z_q / tau, s = -z_p / tau, tau^2 = z_q^2 + z_p^2,
+                // tested without the square root and the divisions
+                const double gap = dq - dpv;
+                if (fabs(gap * zq * zp) <= tol * (zq * zq + zp * zp)) {
+                    const double tau = hypot(zq, zp);
+                    const double c = zq / tau, sn = -zp / tau;
+                    rota[nr] = cp; rotb[nr] = cq; rotc[nr] = c; rots[nr] = sn; ++nr;
+                    dfx[nd] = cp; dfd[nd] = dpv * c * c + dq * sn * sn; ++nd;
+                    zp = tau;
+                    dpv = dpv * sn * sn + dq * c * c;
+                    cp = cq;
                 } else {
-                    ndx[K] = perm[prev]; ndd[K] = sd[prev]; ndz[K] = sz[prev]; ++K;
+                    ndx[K] = cp; ndd[K] = dpv; ndz[K] = zp; ++K;
+                    zp = zq; dpv = dq; cp = cq;
                 }
-                prev = q;
             }
-            if (prev >= 0) { ndx[K] = perm[prev]; ndd[K] = sd[prev]; ndz[K] = sz[prev]; ++K; }
+            if (have) { ndx[K] = cp; ndd[K] = dpv; ndz[K] = zp; ++K; }
         }
         kc[s] = K;
         ndc[s] = nd;
