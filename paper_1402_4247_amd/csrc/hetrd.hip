@@ -572,6 +572,7 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
 // dominates at this size, by one launch for all of them.
 constexpr int TAIL_M = 128;
 constexpr int TAIL_T = 1024;
+static_assert(TAIL_T / 8 >= TAIL_M, "eight threads per row of the tail's trailing matrix");
 
 template <typename R>
 __device__ inline R block_sum_tail(R v, R* red, int tid)
@@ -679,13 +680,18 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
         const cx<R> k = cscale(cmul(tau, dot), (R)0.5);
         if (tid < mm) sw[tid] = csub(sy[tid], cmul(k, sv[tid]));
         __syncthreads();
-        // Procedure 6: A22 -= v w^H + w v^H (lower triangle)
-        for (int e = tid; e < mm * mm; e += TAIL_T) {
-            const int r = e / mm, s2 = e % mm;
-            if (s2 <= r) {
-                const int gr = c + 1 + r, gs = c + 1 + s2;
-                cx<R>& a = P[gr * (gr + 1) / 2 + gs];
-                a = csub(a, cadd(cmulc(sw[s2], sv[r]), cmulc(sv[s2], sw[r])));
+        // Procedure 6: A22 -= v w^H + w v^H (lower triangle), eight threads per
+        // row as in Procedure 4 (no index divisions)
+        {
+            const int r = tid >> 3, q = tid & 7;
+            if (r < mm) {
+                const int gr = c + 1 + r;
+                const cx<R> vr = sv[r], wr = sw[r];
+                cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                for (int s2 = q; s2 <= r; s2 += 8) {
+                    cx<R>& a = Prow[s2];
+                    a = csub(a, cadd(cmulc(sw[s2], vr), cmulc(sv[s2], wr)));
+                }
             }
         }
         __syncthreads();
