@@ -652,10 +652,14 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
             cx<R> acc = zero;
             if (r < mm) {
                 const int gr = c + 1 + r;
-                for (int s2 = q; s2 < mm; s2 += 8) {
+                // the row's stored part, then the mirrored part read down column gr
+                // (same terms in the same order as one pass over s2)
+                const cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                int s2 = q;
+                for (; s2 <= r; s2 += 8) acc = cfma(Prow[s2], sv[s2], acc);
+                for (; s2 < mm; s2 += 8) {
                     const int gs = c + 1 + s2;
-                    const cx<R> a = s2 <= r ? P[gr * (gr + 1) / 2 + gs] : cconj(P[gs * (gs + 1) / 2 + gr]);
-                    acc = cfma(a, sv[s2], acc);
+                    acc = cfma(cconj(P[gs * (gs + 1) / 2 + gr]), sv[s2], acc);
                 }
             }
             acc.x += __shfl_xor(acc.x, 1, WAVE);
