@@ -12,15 +12,27 @@ Extra fields:
                 extended launch; the events are stamped when the kernel starts
                 and ends, on the stream it is enqueued on), over the timed
                 steps;
+  roofline_gemm the complex products on FP64 MFMA timed the same way over one
+                untimed step after the timed region (algorithmic flops,
+                8 m n k per complex product);
   graph_replay  the same batch with the whole solve captured once as a HIP
                 graph and replayed (the kernels are the same; host launch
                 work disappears);
   cpu_baseline  the plain FP64 oracle on a bounded sample of the same work
-                (one of the k-points), timed on the host cores;
+                (one of the k-points), timed on the host cores, plus one
+                single-threaded k-point at --cpu-single-n and the host model;
   latency_ms    p50/p99 of single-k-point calls (nk = 1, kernel by kernel);
+  latency_n128_ms
+                p50/p99 of single calls on the dense n = 128 pencil;
+  serving       the request loop on a stream of --serve requests (n
+                log-uniform in [256, --serve-nmax], 1..16 k-points) at 80% of
+                its closed-loop saturation rate: p50/p99 latency, solves/s;
   fp32_refine, cholesky_s
                 the mixed-precision form and the Cholesky form of Part 2 on
                 the same batch (kernel by kernel), with their residuals;
+  eigenvalues_only
+                the same batch without eigenvectors (Band_DFT_Col's first
+                pass: Part 4's tridiagonal step by bisection);
   x_reuse       the batch with Part 2's X(k) exported by an earlier call and
                 reused (an SCF iteration after the first: S(k) unchanged);
   host_path     the host-pointer entry point (kgev_solve_k) on the same batch
@@ -74,6 +86,47 @@ def counter_traffic(n, nk):
     if fields.get("source_sha256") != h.hexdigest():
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def host_cpu_model():
+    """The host CPU's model name and logical CPU count (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")]
+        return {"model": names[0] if names else None, "logical_cpus": len(names), "affinity": len(os.sched_getaffinity(0))}
+    except OSError:
+        return None
+
+
+def roofline_object(prof, phase, elapsed, note, traffic, K):
+    """Roofline object of one phase from the library's sampled launch timing:
+    achieved = algorithmic work per timed launch / mean timed duration."""
+    hemv = phase == K.PHASE_HEMV
+    base = {"bound": "hbm" if hemv else "mfma", "kernel": "hetrd_zhemv" if hemv else "cgemm_kernel",
+            "peak": PEAK_HBM_GBS if hemv else PEAK_FP64_TFLOPS, "unit": "GB/s" if hemv else "TFLOP/s"}
+    if prof is None:
+        return {**base, "achieved": None, "frac": None, "traffic": None,
+                "measured_on": "not measured (kernel timing off)"}
+    if prof["launches"] == 0:
+        # at orders up to 128 the LDS-resident tail kernel reduces the whole
+        # matrix, so there is no Hermitian-product launch
+        return {**base, "achieved": None, "frac": None, "traffic": None, "launches": 0, "timed_launches": 0,
+                "measured_on": "no launch of the kernel at this order", "share_of_step": 0.0}
+    avg_ms = prof["ms"] / prof["launches"]
+    share = avg_ms * prof["phase_launches"] / (1e3 * elapsed)
+    if hemv:
+        per_launch = prof["bytes"] / prof["launches"]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        extra = {"alg_bytes_per_launch": per_launch}
+    else:
+        per_launch = prof["flops"] / prof["launches"]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        extra = {"alg_flops_per_launch": per_launch,
+                 "flop_count": "8 m n k per complex product (half for lower-only outputs, 4 m n k for a real "
+                               "right operand), whatever the kernel's own form"}
+    return {**base, "achieved": achieved, "frac": achieved / base["peak"], "traffic": traffic,
+            "launches": prof["phase_launches"], "timed_launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
+            **extra, "measured_on": note, "share_of_step": share}
 
 
 def serve_stream(args, K, G, torch, dev):
@@ -169,6 +222,16 @@ def main():
     ap.add_argument("--roofline-phase", choices=["hemv", "gemm"], default="hemv")
     ap.add_argument("--time-stride", type=int, default=17,
                     help="time every N-th launch of the roofline kernel with HIP events")
+    ap.add_argument("--kernel-timing", choices=["on", "off"], default="on",
+                    help="off: no launch carries timing events (for runs under a counter-collecting "
+                         "profiler); the roofline objects are then null")
+    ap.add_argument("--gemm-steps", type=int, default=1,
+                    help="untimed steps after the timed region whose complex products are timed for the "
+                         "second roofline object (0 skips it)")
+    ap.add_argument("--latency128-reps", type=int, default=200,
+                    help="single-pencil latency of the dense n = 128 pencil (seed 1001), repetitions (0 skips)")
+    ap.add_argument("--cpu-single-n", type=int, default=1024,
+                    help="order of the single-threaded oracle sample (0 skips it)")
     ap.add_argument("--latency-reps", type=int, default=50, help="0 skips the latency measurement")
     ap.add_argument("--reuse-steps", type=int, default=2,
                     help="timed calls reusing Part 2's X from an earlier call (0 skips them)")
@@ -177,12 +240,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed steps of the FP32+refine form (0 skips it)")
+    ap.add_argument("--values-steps", type=int, default=2,
+                    help="timed steps of the eigenvalues-only solve (Band_DFT_Col's first pass; 0 skips it)")
     ap.add_argument("--cholesky-steps", type=int, default=2,
                     help="steps of the Cholesky form of Part 2 on the same batch (0 skips it)")
-    ap.add_argument("--serve", type=int, default=0,
+    ap.add_argument("--serve", type=int, default=64,
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--serve-nmax", type=int, default=6000)
+    ap.add_argument("--serve-nmax", type=int, default=2000)
     ap.add_argument("--panel-nb", type=int, default=0,
                     help="Householder panel width (0: the library default, or the tuned width with --autotune)")
     ap.add_argument("--graph-steps", type=int, default=3,
@@ -242,7 +307,9 @@ def main():
         step()
     torch.cuda.synchronize()
     phase = K.PHASE_HEMV if args.roofline_phase == "hemv" else K.PHASE_GEMM
-    K.profile_begin(ctx, phase, args.time_stride)
+    timing = args.kernel_timing == "on"
+    if timing:
+        K.profile_begin(ctx, phase, args.time_stride)
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -254,44 +321,32 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_ms = np.diff(np.array([t0] + marks)) * 1e3
-    prof = K.profile_end(ctx)
+    prof = K.profile_end(ctx) if timing else None
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = nk * args.steps / elapsed
     status = dst.cpu().numpy()
     log(f"[bench] {ms_per_step:.1f} ms/step, {value:.2f} solves/s, status {set(status.tolist())}")
-    prof_elapsed = elapsed
-    prof_note = (f"every {args.time_stride}-th launch of the timed steps" if args.time_stride > 1
-                 else "every launch of the timed steps")
+    note = (f"every {args.time_stride}-th launch of the timed steps" if args.time_stride > 1
+            else "every launch of the timed steps")
+    roof = roofline_object(prof, phase, elapsed, note, counter_traffic(n, nk) if phase == K.PHASE_HEMV else None, K)
 
-    avg_ms = prof["ms"] / max(prof["launches"], 1)
-    # the phase's share of the step, from the sampled mean duration
-    share = avg_ms * prof["phase_launches"] / (1e3 * prof_elapsed)
-    if prof["launches"] == 0:
-        # nothing of the phase ran: at orders up to 128 the LDS-resident tail
-        # kernel reduces the whole matrix, so there is no Hermitian-product launch
-        roof = {"bound": "hbm" if phase == K.PHASE_HEMV else "mfma",
-                "kernel": "hetrd_zhemv" if phase == K.PHASE_HEMV else "cgemm_kernel",
-                "achieved": None, "peak": PEAK_HBM_GBS if phase == K.PHASE_HEMV else PEAK_FP64_TFLOPS,
-                "unit": "GB/s" if phase == K.PHASE_HEMV else "TFLOP/s", "frac": None, "traffic": None,
-                "launches": 0, "timed_launches": 0, "measured_on": "no launch of the kernel at this order",
-                "share_of_step": 0.0}
-    elif phase == K.PHASE_HEMV:
-        per_launch = prof["bytes"] / max(prof["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "hetrd_zhemv", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(n, nk),
-                "launches": prof["phase_launches"], "timed_launches": prof["launches"],
-                "avg_launch_us": 1e3 * avg_ms, "alg_bytes_per_launch": per_launch, "measured_on": prof_note,
-                "share_of_step": share}
-    else:
-        per_launch = prof["flops"] / max(prof["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "cgemm_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "launches": prof["phase_launches"], "timed_launches": prof["launches"],
-                "avg_launch_us": 1e3 * avg_ms, "alg_flops_per_launch": per_launch, "measured_on": prof_note,
-                "share_of_step": share}
+    # the other phase (the complex products on MFMA, or the Hermitian
+    # product), timed the same way over untimed steps after the timed region
+    roof2 = None
+    if timing and args.gemm_steps > 0:
+        ph2 = K.PHASE_GEMM if phase == K.PHASE_HEMV else K.PHASE_HEMV
+        K.profile_begin(ctx, ph2, args.time_stride)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.gemm_steps):
+            step()
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - a
+        prof2 = K.profile_end(ctx)
+        roof2 = roofline_object(prof2, ph2, el2, f"every {args.time_stride}-th launch of {args.gemm_steps} "
+                                "untimed step(s) after the timed region", None, K)
+        log(f"[bench] second roofline: {roof2['kernel']} {roof2['achieved']} {roof2['unit']}")
 
     # latency of single-k-point calls
     lat = []
@@ -309,6 +364,34 @@ def main():
             lat.append(1e3 * (time.perf_counter() - a))
     lat = np.array(lat) if lat else np.array([float("nan")])
     log(f"[bench] latency p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+
+    # single-pencil latency of the dense n = 128 pencil: the whole solve of
+    # one small system, back-to-back calls with inputs in HBM
+    lat128 = None
+    if args.latency128_reps > 0:
+        H1, S1 = G.config1(128, 1001)
+        dH1 = torch.from_numpy(G.colmajor(H1[None])).to(dev)
+        dS1 = torch.from_numpy(G.colmajor(S1[None])).to(dev)
+        w128 = torch.zeros((1, 128), dtype=torch.float64, device=dev)
+        C128 = torch.zeros((1, 128, 128), dtype=torch.complex128, device=dev)
+        t128 = []
+        for r in range(args.latency128_reps + 5):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = K.solve_k_device(ctx, dH1, dS1, 128, 128, 1, w128, C128, 128, opts=K.make_opts())
+            torch.cuda.synchronize()
+            if st != 0:
+                raise RuntimeError(f"n = 128 latency call returned {st}")
+            if r >= 5:
+                t128.append(1e3 * (time.perf_counter() - a))
+        t128 = np.array(t128)
+        C1h = C128[0].cpu().numpy().T
+        w1h = w128[0].cpu().numpy()
+        lat128 = {"p50": float(np.percentile(t128, 50)), "p99": float(np.percentile(t128, 99)), "reps": int(t128.size),
+                  "workload": "dense pencil n = 128 (S = I + 0.05 (A + A^H)/2, H = Q diag(l) Q^H, seed 1001), nk = 1",
+                  "r_res": float(np.linalg.norm(H1 @ C1h - S1 @ C1h * w1h) / np.linalg.norm(H1)),
+                  "r_orth": float(np.abs(C1h.conj().T @ S1 @ C1h - np.eye(128)).max())}
+        log(f"[bench] n = 128 latency p50 {lat128['p50']:.3f} ms p99 {lat128['p99']:.3f} ms")
 
     # accuracy of k-point 0 of the timed batch
     w0 = dw[0].cpu().numpy()
@@ -348,6 +431,32 @@ def main():
                  "r_orth": float(np.abs(Cmk.conj().T @ S0 @ Cmk - np.eye(n)).max()),
                  "eig_diff_vs_fp64_rel": float(np.abs(wmk - w0).max() / np.abs(w0).max())}
         log(f"[bench] FP32+refine {mixed['value']:.2f} solves/s")
+
+    # Band_DFT_Col's eigenvalue pass: the same batch without eigenvectors
+    # (Part 4's tridiagonal step by bisection)
+    values = None
+    if args.values_steps > 0:
+        ov = K.make_opts(want_vectors=False)
+        wv = torch.zeros_like(dw)
+        stv = torch.zeros_like(dst)
+
+        def vstep():
+            st = K.solve_k_device(ctx, dH, dS, n, n, nk, wv, None, n, d_status=stv, opts=ov)
+            if st != 0:
+                raise RuntimeError(f"eigenvalues-only solve returned {st}")
+
+        log(f"[bench] eigenvalues only: warmup 1, timing {args.values_steps} steps")
+        vstep()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.values_steps):
+            vstep()
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - a
+        values = {"value": nk * args.values_steps / tv, "unit": "solves/s", "ms_per_step": 1e3 * tv / args.values_steps,
+                  "steps": args.values_steps, "status_all_ok": bool(np.all(stv.cpu().numpy() == 0)),
+                  "eig_diff_vs_vectors_solve_rel": float((wv - dw).abs().max().item() / dw.abs().max().item())}
+        log(f"[bench] eigenvalues only {values['value']:.2f} solves/s")
 
     # Part 2 in Cholesky form (X = L^-H) on the same batch, same accuracy gate
     chol = None
@@ -477,11 +586,23 @@ def main():
         st0, wor, _ = O.solve_k(H0, S0)
         t_or = time.perf_counter() - a
         cpu = {"value": 1.0 / t_or, "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": f"1 of the {nk} k-points (k index 0) at n={n}, all eigenpairs; {t_or:.1f} s"}
+               "sample": f"1 of the {nk} k-points (k index 0) at n={n}, all eigenpairs; {t_or:.1f} s",
+               "host_cpu": host_cpu_model()}
         check["eig_err_vs_oracle_rel"] = float(np.abs(w0 - wor).max() / np.abs(wor).max())
         if mixed is not None:
             mixed["eig_err_vs_oracle_rel"] = float(np.abs(wmk - wor).max() / np.abs(wor).max())
         check["oracle_status"] = int(st0)
+        if args.cpu_single_n > 0:
+            ns = args.cpu_single_n
+            Hq, Sq = G.lcao_batch(ns, G.mp_grid(4)[:1], args.seed)
+            log(f"[bench] cpu baseline: oracle on one k-point at n={ns} with 1 thread")
+            O.set_threads(1)
+            a = time.perf_counter()
+            O.solve_k(Hq[0], Sq[0])
+            t1t = time.perf_counter() - a
+            O.set_threads(threads)
+            cpu["single_thread"] = {"value": 1.0 / t1t, "unit": "solves/s", "cores": 1,
+                                    "sample": f"1 k-point of the LCAO pencil at n={ns}, all eigenpairs; {t1t:.1f} s"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -495,10 +616,11 @@ def main():
                                 "eigenpairs"),
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
                    "panel_nb": args.panel_nb or tuned_nb or 32},
-        "roofline": roof, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "cholesky_s": chol,
+        "roofline": roof, "roofline_gemm": roof2, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "eigenvalues_only": values, "cholesky_s": chol,
         "host_path": host, "x_reuse": xreuse, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
+        "latency_n128_ms": lat128,
         "check": check,
     }
     ctx.close()

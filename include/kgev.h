@@ -108,6 +108,8 @@ const char* kgev_status_str(kgev_status st);
  * Create a context bound to HIP device `device`.  The context owns an
  * internal device workspace (grown on demand when callers pass no
  * workspace), the tuned panel/tile table and a few small device buffers.
+ * The first call for a device also looks up that device's address of the
+ * static workspace of kgev_solve_k_device_noalloc.
  * Returns KGEV_OK, -1 (ctx NULL), -2 (no such device) or KGEV_EDEVICE.
  */
 kgev_status kgev_create(kgev_ctx** ctx, int device);
@@ -167,6 +169,33 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
                                 int64_t ld, int64_t nk, double* dw, kgev_z* dC, int64_t ldc,
                                 void* dwork, size_t work_bytes, int32_t* d_status,
                                 const kgev_opts* opts, void* stream);
+
+/*
+ * kgev_solve_k_device for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It calls no hipMalloc, hipFree or other allocating routine; its
+ * workspace is a static device array of KGEV_NOALLOC_SCRATCH_BYTES per GPU,
+ * reserved when the library's device code is loaded on that GPU and held
+ * until the process ends.  The caller still passes inputs and outputs, with
+ * the meanings of kgev_solve_k_device; the results are bitwise those of
+ * kgev_solve_k_device with the same options.
+ *   Limit: kgev_workspace_bytes(n, nk, opts) <= KGEV_NOALLOC_SCRATCH_BYTES
+ *   (for example n = 1024 with one k-point, n = 512 with four, n = 128 with up
+ *   to 43); larger sizes return -9 and nothing is enqueued.
+ *   opts.use_graph = 1 or opts.streams > 1 return KGEV_EUNSUPPORTED.
+ *   Launches of this entry point are not timed by kgev_profile_begin.
+ * Every call on a GPU uses that GPU's one array, which keeps the last call's
+ * contents (the solve initialises everything it reads): two calls whose stream
+ * work overlaps on one GPU race and give undefined results; serialise them
+ * (one stream, or events between streams).
+ * Returns -1 ctx, -2 dH, -3 dS, -4 n, -5 ld, -6 nk, -7 dw, -8 dC/ldc, -9 the
+ * workspace exceeds the array, -10 opts invalid, KGEV_EUNSUPPORTED, else
+ * KGEV_OK once every kernel is enqueued.
+ */
+#define KGEV_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+kgev_status kgev_solve_k_device_noalloc(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
+                                        int64_t nk, double* dw, kgev_z* dC, int64_t ldc, int32_t* d_status,
+                                        const kgev_opts* opts, void* stream);
 
 /*
  * The per-k solve with the S-orthonormaliser X of Part 2 exported or reused.
@@ -257,6 +286,21 @@ kgev_status kgev_stedc_device(kgev_ctx* ctx, const double* dd, const double* de,
                               int64_t nk, double* dw, double* dZ, int32_t* d_status, void* stream);
 
 /*
+ * Eigenvalues only of real symmetric tridiagonals (the tridiagonal step of
+ * Eigen_HH, Section III, in the form Band_DFT_Col's eigenvalue pass needs), by
+ * bisection on Sturm counts: the number of eigenvalues below x is the number
+ * of negative pivots of T - x I.  The solve uses it whenever eigenvectors are
+ * not requested (opts.want_vectors = 0, FP64).
+ *   dd, de : in, nk*n doubles each (layout as kgev_hetrd_device); not modified.
+ *   dw     : out, nk*n eigenvalues ascending (k-point q at dw + q*n).
+ * Asynchronous on `stream`; uses the context's internal workspace.  Returns
+ * -1 ctx, -2 dd, -3 de, -4 n, -5 nk, -6 dw, KGEV_ENOMEM / KGEV_EDEVICE, else
+ * KGEV_OK.
+ */
+kgev_status kgev_stebz_device(kgev_ctx* ctx, const double* dd, const double* de, int64_t n, int64_t nk,
+                              double* dw, void* stream);
+
+/*
  * Back-transformation ("rearrangement of eigenvectors", Section III):
  * dU <- Q dU for nk problems, with Q = H_0 ... H_{n-2} given by dV, dtau as
  * produced by kgev_hetrd_device.  dU: in/out, nk matrices n x n (ld ldu).
@@ -267,8 +311,8 @@ kgev_status kgev_unmtr_device(kgev_ctx* ctx, const kgev_z* dV, const kgev_z* dta
 /*
  * Eigen_HH (Section III): eigenvalues (ascending, dw: nk*n) and unit-norm
  * eigenvectors (dY: nk matrices n x n, ld n; may be NULL for eigenvalues
- * only) of the Hermitian matrices whose lower triangles are dA (ld lda; not
- * modified).
+ * only, then by bisection) of the Hermitian matrices whose lower triangles are
+ * dA (ld lda; not modified).
  */
 kgev_status kgev_eigh_device(kgev_ctx* ctx, const kgev_z* dA, int64_t n, int64_t lda, int64_t nk,
                              double* dw, kgev_z* dY, int32_t* d_status, const kgev_opts* opts,

@@ -53,7 +53,7 @@ def _L():
         lib.or_bisect_eigs.argtypes = [I, P, P, P]
         lib.or_tridiag_ql.argtypes = [I, P, P, P, I]
         lib.or_apply_q.argtypes = [I, P, P, I, P, I]
-        lib.or_normalize_cols.argtypes = [I, I, P, I, P]
+        lib.or_normalize_cols.argtypes = [I, I, P, I]
         lib.or_eigen_hh.argtypes = [I, P, I, P, P, P, P]
         lib.or_solve_k.argtypes = [I, P, I, P, I, D, P, P, I, P, P, P, P, P, P, P]
         lib.or_zgemm_ri.argtypes = [ctypes.c_char, ctypes.c_char, I, I, I, D, D, P, I, P, I, D, D,
@@ -151,11 +151,10 @@ def apply_q(V, tau, U):
     return U
 
 
-def normalize_cols(U, s=None):
-    """Unit 2-norm columns, optionally also scaled by s_j^(-1/2)."""
+def normalize_cols(U):
+    """Unit 2-norm columns."""
     U = _colmajor(U).copy(order="F")
-    sp = None if s is None else np.ascontiguousarray(s, dtype=np.float64)
-    _L().or_normalize_cols(U.shape[0], U.shape[1], _p(U), U.shape[0], _p(sp))
+    _L().or_normalize_cols(U.shape[0], U.shape[1], _p(U), U.shape[0])
     return U
 
 

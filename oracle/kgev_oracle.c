@@ -292,8 +292,9 @@ static int keyed_cmp(const void* a, const void* b)
  * eigenvalues in ascending order; e (n-1) is read only.  If Z is not NULL it
  * receives the orthonormal eigenvectors (column j for eigenvalue j), n x n
  * with leading dimension ldz.  A sub-diagonal entry counts as zero when
- * |e_m| <= eps (|d_m| + |d_{m+1}|).  Returns OR_ENOCONV after 30 sweeps on one
- * eigenvalue without convergence.
+ * |e_m| <= eps * tst1, tst1 the running maximum of |d_l| + |e_l| over the rows
+ * reached so far (the normwise test of the published algorithm, tql2).
+ * Returns OR_ENOCONV after 30 sweeps on one eigenvalue without convergence.
  */
 int or_tridiag_ql(int n, double* d, const double* e_in, double* Z, int ldz)
 {
@@ -412,11 +413,10 @@ void or_apply_q(int n, const zc* V, const zc* tau, int ncols, zc* U, int ldu)
 }
 
 /*
- * Normalisation: each column j of U (nrows x ncols) is divided by its 2-norm
- * and, when s is not NULL, additionally by sqrt(s_j) (Part 2's rearranged S,
- * X = U diag(s)^(-1/2)).
+ * Normalisation (Eigen_HH's last step): each column j of U (nrows x ncols)
+ * is divided by its 2-norm.
  */
-void or_normalize_cols(int nrows, int ncols, zc* U, int ldu, const double* s)
+void or_normalize_cols(int nrows, int ncols, zc* U, int ldu)
 {
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ncols; ++j) {
@@ -425,8 +425,7 @@ void or_normalize_cols(int nrows, int ncols, zc* U, int ldu, const double* s)
             zc x = U[IX(i, j, ldu)];
             ss += creal(x) * creal(x) + cimag(x) * cimag(x);
         }
-        double f = 1.0 / sqrt(ss);
-        if (s) f /= sqrt(s[j]);
+        const double f = 1.0 / sqrt(ss);
         for (int i = 0; i < nrows; ++i) U[IX(i, j, ldu)] *= f;
     }
 }
@@ -459,7 +458,7 @@ int or_eigen_hh(int n, const zc* A, int lda, double* w, zc* Y, double* d_out, do
     if (st != OR_OK || !Y) goto out;
     for (size_t q = 0; q < (size_t)n * n; ++q) Y[q] = Z[q];
     or_apply_q(n, V, tau, n, Y, n);
-    or_normalize_cols(n, n, Y, n, NULL);
+    or_normalize_cols(n, n, Y, n);
 out:
     free(B); free(V); free(tau); free(e); free(Z);
     return st;

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -83,7 +84,7 @@ struct SolvePlan {
     size_t dc_es, dc_onrm, dc_D0, dc_D1, dc_sd, dc_sz, dc_ndd, dc_ndz, dc_dfd, dc_rotc, dc_rots, dc_rho, dc_tauv,
         dc_lam, dc_zhat;
     size_t dc_kcnt, dc_ndcnt, dc_nrot, dc_perm, dc_ndx, dc_dfx, dc_rota, dc_rotb, dc_orgi, dc_cmap;
-    size_t status;
+    size_t status, bz;
     // mixed precision: complex64 tridiagonalisation / back-transformation
     // buffers and the FP64 refinement scratch (size 0 in the FP64 form)
     bool mixed;
@@ -140,6 +141,7 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
                     &p.dc_orgi, &p.dc_cmap};
     for (size_t* q : iv) *q = L.add(i4 * n * nk);
     p.status = L.add(i4 * nk);
+    p.bz = L.add(stebz_work_bytes(nk));
     const size_t m = mixed ? 1 : 0;
     const size_t c = sizeof(float2), f = sizeof(float);
     p.f_A = L.add(m * c * nn * nk);
@@ -315,8 +317,10 @@ struct DevGuard {
 };
 
 // Eigen_HH on the batch whose working copies are in Aw (lower, ld n):
-// eigenvalues -> wout (stride n); vectors (if Y) -> Y (ld n).
-kgev_status eigen_hh(const SolvePlan& p, void* w, hipStream_t st, double* wout, double2* Y, int* status)
+// eigenvalues -> wout (stride n); vectors (if Y) -> Y (ld n).  values_only:
+// the tridiagonal step by bisection, eigenvalues only (no Z; Y must be null).
+kgev_status eigen_hh(const SolvePlan& p, void* w, hipStream_t st, double* wout, double2* Y, int* status,
+                     bool values_only = false)
 {
     const int64_t n = p.n, nk = p.nk, nn = n * n;
     double2* Aw = at<double2>(w, p.Aw);
@@ -326,6 +330,10 @@ kgev_status eigen_hh(const SolvePlan& p, void* w, hipStream_t st, double* wout, 
     double2* tau = at<double2>(w, p.tau);
     KCHECK(fill_zero(st, Vs, sizeof(double2) * (size_t)nn * nk));
     KCHECK(hetrd<double>(st, hetrd_ws(p, w, Aw, n, nn, Vs, d, e, tau), nk));
+    if (values_only) {
+        KCHECK(stebz(st, d, e, n, n, nk, wout, n, at<void>(w, p.bz)));
+        return KGEV_OK;
+    }
     double* Zr = at<double>(w, p.Zr);
     KCHECK(stedc(st, dc_ws(p, w, d, e, status), wout, Zr, at<double>(w, p.Qs), nk));
     if (!Y) return KGEV_OK;
@@ -428,8 +436,10 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     } else {
         // eigenvalues and Z; with vectors, C = (X Q_A) Z: the reflectors are
         // applied to a copy of X from the right, and the last product takes
-        // the real Z as it is (two real products instead of three)
-        r = eigen_hh(p, w, st, dw, nullptr, status);
+        // the real Z as it is (two real products instead of three).  Without
+        // vectors (Band_DFT_Col's eigenvalue pass) the tridiagonal step is
+        // bisection for the eigenvalues alone.
+        r = eigen_hh(p, w, st, dw, nullptr, status, !o.want_vectors);
         if (r != KGEV_OK) return r;
         if (o.want_vectors) {
             double* Zr = at<double>(w, p.Zr);
@@ -518,7 +528,40 @@ void drop_graphs(kgev_ctx* ctx)
     ctx->batch_graphs.clear();
 }
 
+// Workspace of kgev_solve_k_device_noalloc: one static array per GPU, reserved
+// when the library's device code is loaded on that GPU and held until the
+// process ends.  Host code never uses the array's name as an address: its
+// device address on each GPU comes from hipGetSymbolAddress (taken once per
+// device, with that device current, in kgev_create) and is kept in
+// g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[KGEV_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the device address of this device's scratch array (the device is current)
+kgev_status scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return KGEV_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        KCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return KGEV_EDEVICE;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return KGEV_OK;
+}
+
 }  // namespace
+
+namespace kgev {
+// suspends launch timing for the calling thread (profile.hip)
+void* prof_suspend();
+void prof_resume(void* saved);
+}  // namespace kgev
 
 extern "C" {
 
@@ -556,6 +599,9 @@ kgev_status kgev_create(kgev_ctx** ctx, int device)
     KCHECK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return -2;
     DevGuard g(device);
+    void* sp = nullptr;
+    const kgev_status ss = scratch_address(device, &sp);
+    if (ss != KGEV_OK) return ss;
     kgev_ctx* c = new kgev_ctx{};
     c->device = device;
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -668,6 +714,39 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     ctx->graphs.push_back({key, exec});
     KCHECK(hipGraphLaunch(exec, st));
     return KGEV_OK;
+}
+
+kgev_status kgev_solve_k_device_noalloc(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* dS, int64_t n, int64_t ld,
+                                        int64_t nk, double* dw, kgev_z* dC, int64_t ldc, int32_t* d_status,
+                                        const kgev_opts* opts, void* stream)
+{
+    if (!ctx) return -1;
+    if (!dH) return -2;
+    if (!dS) return -3;
+    if (n < 1) return -4;
+    if (ld < n) return -5;
+    if (nk < 1) return -6;
+    if (!dw) return -7;
+    kgev_opts o = resolve_opts(opts);
+    if ((!opts || opts->panel_nb == 0)) {
+        auto it = ctx->tuned_nb.find({n, o.precision});
+        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
+    }
+    if (!opts_valid(o)) return -10;
+    if (o.want_vectors && (!dC || ldc < n)) return -8;
+    if (o.use_graph || o.streams > 1) return KGEV_EUNSUPPORTED;
+    const Groups grp = make_groups(n, nk, o);
+    if (grp.region * (size_t)grp.G > KGEV_NOALLOC_SCRATCH_BYTES) return -9;
+    DevGuard g(ctx->device);
+    void* w = nullptr;
+    const kgev_status rs = scratch_address(ctx->device, &w);
+    if (rs != KGEV_OK) return rs;
+    // no launch of this call is timed (timing may create events)
+    void* saved = prof_suspend();
+    const kgev_status r = solve_device(grp.p, o, w, (hipStream_t)stream, (const double2*)dH, (const double2*)dS, ld,
+                                       dw, o.want_vectors ? (double2*)dC : nullptr, ldc, d_status);
+    prof_resume(saved);
+    return r;
 }
 
 size_t kgev_batch_workspace_bytes(const kgev_problem* probs, int64_t count, const kgev_opts* opts)
@@ -902,6 +981,22 @@ kgev_status kgev_stedc_device(kgev_ctx* ctx, const double* dd, const double* de,
     return KGEV_OK;
 }
 
+kgev_status kgev_stebz_device(kgev_ctx* ctx, const double* dd, const double* de, int64_t n, int64_t nk, double* dw,
+                              void* stream)
+{
+    if (!ctx) return -1;
+    if (!dd) return -2;
+    if (!de) return -3;
+    if (n < 1) return -4;
+    if (nk < 1) return -5;
+    if (!dw) return -6;
+    DevGuard g(ctx->device);
+    const kgev_status r = ensure_work(ctx, stebz_work_bytes(nk));
+    if (r != KGEV_OK) return r;
+    KCHECK(stebz((hipStream_t)stream, dd, de, n, n, nk, dw, n, ctx->work));
+    return KGEV_OK;
+}
+
 kgev_status kgev_unmtr_device(kgev_ctx* ctx, const kgev_z* dV, const kgev_z* dtau, int64_t n, int64_t nk, kgev_z* dU,
                               int64_t ldu, void* stream)
 {
@@ -943,7 +1038,7 @@ kgev_status kgev_eigh_device(kgev_ctx* ctx, const kgev_z* dA, int64_t n, int64_t
     const int64_t nn = n * n;
     KCHECK(status_init(st, status, nk));
     KCHECK(copy_lower_check<double>(st, n, (const double2*)dA, lda, lda * n, at<double2>(w, p.Aw), n, nn, status, nk));
-    r = eigen_hh(p, w, st, dw, (double2*)dY, status);
+    r = eigen_hh(p, w, st, dw, (double2*)dY, status, dY == nullptr);
     if (r != KGEV_OK) return r;
     if (dY) KCHECK(normalize_cols(st, n, (double2*)dY, n, nn, nullptr, 0, 0.0, nullptr, nk));
     if (d_status) KCHECK(status_finish(st, status, d_status, nk));

@@ -11,8 +11,6 @@
 // im = (ar + ai)(br + bi) - ar br - ai bi, which saves a quarter of the MFMA
 // work at a normwise (not componentwise) error bound of the same order;
 // op(A) = A^H is folded into the global->LDS copy.
-#include <stdlib.h>
-
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -156,19 +154,16 @@ __device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const 
 
 // BM x BN workgroup tile, four waves in a 2 x 2 arrangement, each owning a
 // (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  While one K step is
-// multiplied out of LDS, the next is fetched into registers.  NST = 2: two
-// LDS stages, the registers go to the other stage, one barrier per K step.
-// NST = 1: one stage (half the LDS, so twice the workgroups per CU), the
-// registers are stored after a barrier that ends the reads, two barriers
-// per K step.
-template <typename R, int BM, int BN, bool G3, int TA, int TB, int NST>
-__global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CGemmArgs<R> p)
+// multiplied out of LDS, the next is fetched into registers; two LDS stages,
+// the registers go to the other stage, one barrier per K step.
+template <typename R, int BM, int BN, bool G3, int TA, int TB>
+__global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
 {
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
     constexpr int TM = BM / 32, TN = BN / 32;      // MFMA tiles per wave
-    __shared__ R sAr[NST][GB_K][BM + 1], sAi[NST][GB_K][BM + 1];
-    __shared__ R sBr[NST][GB_K][BN + 1], sBi[NST][GB_K][BN + 1];
+    __shared__ R sAr[2][GB_K][BM + 1], sAi[2][GB_K][BM + 1];
+    __shared__ R sBr[2][GB_K][BN + 1], sBi[2][GB_K][BN + 1];
 
     const int64_t total = (p.tri ? (int64_t)p.tiles_m * (p.tiles_m + 1) / 2 : (int64_t)p.tiles_m * p.tiles_n) * p.batch;
     int64_t bz;
@@ -277,14 +272,13 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
                 }
             }
         }
-        if constexpr (NST == 1) __syncthreads();
         if (nx < total_k) {
-            const int nxt = NST == 2 ? (cur ^ 1) : 0;
+            const int nxt = cur ^ 1;
             store_a<R, BM, TA>(sAr[nxt], sAi[nxt], tid, ra, oka);
             store_b<R, BN, TB>(sBr[nxt], sBi[nxt], tid, rb, okb);
         }
         __syncthreads();
-        if constexpr (NST == 2) cur ^= 1;
+        cur ^= 1;
     }
 
     cx<R>* C = p.C + bo * p.sC + bi * p.sC2;
@@ -312,28 +306,28 @@ __global__ __launch_bounds__(G_THREADS, (NST == 2 ? 2 : 3)) void cgemm_kernel(CG
             }
 }
 
-template <typename R, int BM, int BN, bool G3, int TA, int TB, int NST>
+template <typename R, int BM, int BN, bool G3, int TA, int TB>
 hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st, const ProfLaunch& pl)
 {
     p.tiles_m = (int)((p.m + BM - 1) / BM);
     p.tiles_n = (int)((p.n + BN - 1) / BN);
     p.tri = (p.lower && BM == BN && p.tiles_m == p.tiles_n) ? 1 : 0;
     const int64_t total = (p.tri ? (int64_t)p.tiles_m * (p.tiles_m + 1) / 2 : (int64_t)p.tiles_m * p.tiles_n) * p.batch;
-    launch_timed(pl, cgemm_kernel<R, BM, BN, G3, TA, TB, NST>, dim3((unsigned)total), dim3(G_THREADS), st, p);
+    launch_timed(pl, cgemm_kernel<R, BM, BN, G3, TA, TB>, dim3((unsigned)total), dim3(G_THREADS), st, p);
     return hipGetLastError();
 }
 
 // the operand forms are compile-time so that the tile loads are straight-line
-template <typename R, bool G3, int NST>
+template <typename R, bool G3>
 hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st, const ProfLaunch& pl)
 {
-    if (p.tb[0] == 2) return launch_tiles<R, 64, 64, false, 0, 2, NST>(p, st, pl);
+    if (p.tb[0] == 2) return launch_tiles<R, 64, 64, false, 0, 2>(p, st, pl);
     const int f = p.ta[0] * 2 + p.tb[0];
     switch (f) {
-    case 0: return launch_tiles<R, 64, 64, G3, 0, 0, NST>(p, st, pl);
-    case 1: return launch_tiles<R, 64, 64, G3, 0, 1, NST>(p, st, pl);
-    case 2: return launch_tiles<R, 64, 64, G3, 1, 0, NST>(p, st, pl);
-    default: return launch_tiles<R, 64, 64, G3, 1, 1, NST>(p, st, pl);
+    case 0: return launch_tiles<R, 64, 64, G3, 0, 0>(p, st, pl);
+    case 1: return launch_tiles<R, 64, 64, G3, 0, 1>(p, st, pl);
+    case 2: return launch_tiles<R, 64, 64, G3, 1, 0>(p, st, pl);
+    default: return launch_tiles<R, 64, 64, G3, 1, 1>(p, st, pl);
     }
 }
 
@@ -348,28 +342,12 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
                    (double)(a.batch2 < 1 ? 1 : a.batch2);
     if (a.lower) flops *= 0.5;
     if (a.tb[0] == 2) flops *= 0.5;   // complex times real: 4 real flops per term
-    // The 3M form is the default: on gfx950 it measured 1.22x the 4M form on
-    // the path's products with unchanged residuals.  KGEV_GEMM_REMAP=0|1 and
-    // KGEV_GEMM_3M=0|1 override the defaults (tuning experiments).
-    static const int remap = [] {
-        const char* v = getenv("KGEV_GEMM_REMAP");
-        return v ? atoi(v) : 1;
-    }();
-    static const int g3 = [] {
-        const char* v = getenv("KGEV_GEMM_3M");
-        return v ? atoi(v) : 1;
-    }();
-    static const int stages = [] {
-        const char* v = getenv("KGEV_GEMM_STAGES");
-        return v ? atoi(v) : 2;
-    }();
-    p.remap = remap;
+    // Tiles are remapped so each XCD sees a contiguous range; complex tile
+    // products in the 3M form (1.22x the four-product form on gfx950 on the
+    // path's products, with unchanged residuals).
+    p.remap = 1;
     const ProfLaunch pl = prof_launch_begin(PH_GEMM, st);
-    hipError_t e;
-    if (stages == 1)
-        e = g3 ? launch_forms<R, true, 1>(p, st, pl) : launch_forms<R, false, 1>(p, st, pl);
-    else
-        e = g3 ? launch_forms<R, true, 2>(p, st, pl) : launch_forms<R, false, 2>(p, st, pl);
+    const hipError_t e = launch_forms<R, true>(p, st, pl);
     prof_launch_end(PH_GEMM, st, pl, 0.0, flops);
     return e;
 }

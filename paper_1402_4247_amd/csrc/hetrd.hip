@@ -29,8 +29,6 @@
 // reduction runs in one launch, unblocked, with the matrix in LDS (tail).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible run to run.
-#include <stdlib.h>
-
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -39,7 +37,6 @@ namespace kgev {
 namespace {
 
 constexpr int ZT = 64;          // ZHEMV tile edge
-constexpr int NT_LOAD = 2;      // buffer-load cache policy: non-temporal
 constexpr int ZCH = 4;          // tiles per ZHEMV chunk: one per wave of the workgroup
 constexpr int RB = 64;          // rows per workgroup in the column kernels
 
@@ -132,17 +129,17 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 // One chunk of z = A22 u.  A chunk is up to four 64x64 tiles (R0..R0+3, C) of
 // one block column of the lower triangle; wave w owns tile R0 + w whole: the
 // direct part z_R += A_RC u_C comes out complete per row, the transposed part
-// z_C += A_RC^H u_R per column after a wave reduction (a transposing shuffle
-// reduction, or, by default, column sums through LDS that leave the registers
-// free for the next group's loads), and the four waves' column sums are added
-// once.
-template <typename R, int MINW, bool BUF, int PF, int AUX = 0>
-__global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, int rev)
+// z_C += A_RC^H u_R per column.  Each group of 8 columns is multiplied, its
+// products go to the wave's LDS block, the next group is requested into the
+// same registers, and the column sums are taken from LDS while it is in
+// flight; the four waves' column sums are added once.  Three workgroups per
+// CU.
+template <typename R, bool BUF>
+__global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int rev)
 {
     __shared__ cx<R> svC[ZT];
     __shared__ cx<R> sT[ZCH][ZT];
-    // per-wave staging of one group's products (PF == 3)
-    __shared__ cx<R> sP[PF == 3 ? ZCH : 1][8][ZT + 1];
+    __shared__ cx<R> sP[ZCH][8][ZT + 1];      // per-wave staging of one group's products
     // rev: the workgroups take the chunks in reverse order (last k-point's
     // last chunk first), so that a launch after a forward one starts on the
     // tiles its predecessor read last
@@ -176,8 +173,7 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, i
     // Matrices under 2 GiB are read with buffer loads: one 32-bit row offset
     // per lane shared by every load of the tile, the column offset in a
     // scalar register (fewer vector registers and no 64-bit address
-    // arithmetic); larger ones with plain global loads.  AUX is the buffer
-    // loads' cache policy (0 default, NT_LOAD non-temporal).
+    // arithmetic); larger ones with plain global loads.
     const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
@@ -189,10 +185,10 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, i
             if constexpr (BUF) {
                 const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
                 if constexpr (sizeof(R) == 8) {
-                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, AUX);
+                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
                     a[cc] = __builtin_bit_cast(cx<R>, v);
                 } else {
-                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, AUX);
+                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
                     a[cc] = __builtin_bit_cast(cx<R>, v);
                 }
             } else {
@@ -200,10 +196,7 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, i
             }
         }
     };
-    // PF = 0: each group of 8 columns is requested once the previous one is
-    // reduced; 1: one group ahead (separate registers); 3: requested into
-    // the same registers once the previous group's products are in LDS
-    cx<R> a[8], an[8];
+    cx<R> a[8];
     load_group(0, a);
     if (tid < ZT) {
         const int64_t gc = gcb + tid;
@@ -221,11 +214,6 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, i
         cx<R> yd = czero<cx<R>>();
 #pragma unroll 1
         for (int g = 0; g < 8; ++g) {
-            if constexpr (PF == 1) {
-                if (g + 1 < 8) load_group(g + 1, an);
-            } else if constexpr (PF == 0) {
-                if (g > 0) load_group(g, a);
-            }
             const int64_t gc0 = gcb + g * 8;
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc) {
@@ -239,32 +227,23 @@ __global__ __launch_bounds__(256, MINW) void hetrd_zhemv(HetrdWs<R> ws, int i, i
                 // the diagonal entry is counted once (direct part only)
                 a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
             }
-            if constexpr (PF == 3) {
-                // the products go to this wave's LDS block, the next group is
-                // requested, and the column sums are taken from LDS while it
-                // is in flight: lane l adds rows 8 (l / 8) .. +7 of column
-                // l mod 8, then the eight lanes of a column combine
+            // the products go to this wave's LDS block, the next group is
+            // requested, and the column sums are taken from LDS while it is in
+            // flight: lane l adds rows 8 (l / 8) .. +7 of column l mod 8, then
+            // the eight lanes of a column combine
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
-                if (g + 1 < 8) load_group(g + 1, a);
-                __builtin_amdgcn_wave_barrier();
-                const int c = lane & 7, r0 = (lane >> 3) * 8;
-                cx<R> cs = czero<cx<R>>();
+            for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
+            if (g + 1 < 8) load_group(g + 1, a);
+            __builtin_amdgcn_wave_barrier();
+            const int c = lane & 7, r0 = (lane >> 3) * 8;
+            cx<R> cs = czero<cx<R>>();
 #pragma unroll
-                for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
-                cs = xor_add<8, R>(cs);
-                cs = xor_add<16, R>(cs);
-                cs = xor_add<32, R>(cs);
-                if (lane < 8) sT[w][g * 8 + lane] = cs;
-                __builtin_amdgcn_wave_barrier();
-            } else {
-                const cx<R> r = transpose_sum8<R>(a, lane);
-                if ((lane & 7) == 0) sT[w][g * 8 + (lane >> 3)] = r;
-            }
-            if constexpr (PF == 1) {
-#pragma unroll
-                for (int cc = 0; cc < 8; ++cc) a[cc] = an[cc];
-            }
+            for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
+            cs = xor_add<8, R>(cs);
+            cs = xor_add<16, R>(cs);
+            cs = xor_add<32, R>(cs);
+            if (lane < 8) sT[w][g * 8 + lane] = cs;
+            __builtin_amdgcn_wave_barrier();
         }
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
         qd = uR.x * yd.x + uR.y * yd.y;
@@ -712,47 +691,11 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
 {
     const int n = ws.n, nb = ws.nb;
     if (n < 1 || nk < 1) return hipSuccess;
-    static const bool buf_ok = [] {
-        const char* v = getenv("KGEV_HEMV_BUFFER");
-        return !(v && atoi(v) == 0);
-    }();
-    // buffer offsets are 32-bit: the matrix (ld x n) must stay under 2 GiB
-    const bool buf = buf_ok && (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
-    // KGEV_HEMV_VARIANT: 33 (default: three workgroups per CU, each group of
-    // 8 columns consumed while the next is requested, column sums through
-    // LDS; measured fastest on gfx950) or 30 (shuffle reductions, each group
-    // loaded after the previous one is reduced; 1% slower)
-    static const int variant = [] {
-        const char* v = getenv("KGEV_HEMV_VARIANT");
-        return v ? atoi(v) : 33;
-    }();
-    // trailing matrices of at most this order go to the LDS-resident tail
-    // kernel (KGEV_HETRD_TAIL=0 keeps every column on the blocked path)
-    static const int tail_m = [] {
-        const char* v = getenv("KGEV_HETRD_TAIL");
-        const int t = v ? atoi(v) : TAIL_M;
-        return t < 0 ? 0 : (t > TAIL_M ? TAIL_M : t);
-    }();
-    // Consecutive columns traverse their tiles in opposite orders (odd columns
-    // from the last k-point's last chunk back), so each launch starts on the
-    // tiles its predecessor read last, which the 256 MB memory-side cache still
-    // holds once the lower triangles of all k-points exceed it (n = 2000 x 16:
-    // 9% faster at m = 1500..1750, 3.4% over the step's products).
-    // KGEV_HEMV_ZIGZAG=0 keeps every launch in forward order.
-    static const int zigzag = [] {
-        const char* v = getenv("KGEV_HEMV_ZIGZAG");
-        return v ? atoi(v) : 1;
-    }();
-    // KGEV_HEMV_NT_MB (MiB): tile loads take the non-temporal policy when a
-    // launch's lower triangles exceed this size (default: never).  Without the
-    // alternating order that was 5% faster from m = 1750 at n = 2000 x 16;
-    // with it the default policy is faster.
-    static const double nt_bytes = [] {
-        const char* v = getenv("KGEV_HEMV_NT_MB");
-        return v ? atof(v) * 1048576.0 : 1e300;
-    }();
+    // Buffer offsets are 32-bit: a matrix (ld x n) of 2 GiB or more is read
+    // with plain global loads instead.
+    const bool buf = (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
     for (int p = 0; p <= n - 1; p += nb) {
-        if (n - p <= tail_m && p < n - 1) {
+        if (n - p <= TAIL_M && p < n - 1) {
             hipLaunchKernelGGL(hetrd_tail<R>, dim3((unsigned)nk), dim3(TAIL_T), 0, st, ws, p);
             break;
         }
@@ -764,17 +707,18 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int NB = (m + ZT - 1) / ZT;
             int nch = 0;
             for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
-            const int rev = zigzag ? (i & 1) : 0;
+            // Consecutive columns traverse their tiles in opposite orders (odd
+            // columns from the last k-point's last chunk back), so each launch
+            // starts on the tiles its predecessor read last, which the 256 MB
+            // memory-side cache still holds once the lower triangles of all
+            // k-points exceed it (n = 2000 x 16: 9% faster at m = 1500..1750).
+            const int rev = i & 1;
             const ProfLaunch pl = prof_launch_begin(PH_HEMV, st);
             const dim3 gz((unsigned)nch, (unsigned)nk);
-            if (!buf)
-                launch_timed(pl, hetrd_zhemv<R, 1, false, 1>, gz, dim3(256), st, ws, i, rev);
-            else if (variant == 30)
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 0>, gz, dim3(256), st, ws, i, rev);
-            else if ((double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk >= nt_bytes)
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 3, NT_LOAD>, gz, dim3(256), st, ws, i, rev);
+            if (buf)
+                launch_timed(pl, hetrd_zhemv<R, true>, gz, dim3(256), st, ws, i, rev);
             else
-                launch_timed(pl, hetrd_zhemv<R, 3, true, 3>, gz, dim3(256), st, ws, i, rev);
+                launch_timed(pl, hetrd_zhemv<R, false>, gz, dim3(256), st, ws, i, rev);
             prof_launch_end(PH_HEMV, st, pl,
                             (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);

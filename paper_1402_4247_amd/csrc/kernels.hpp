@@ -107,6 +107,13 @@ struct DcWs {
 int dc_levels(int64_t n);
 hipError_t stedc(hipStream_t st, const DcWs& ws, double* w, double* Z, double* Qscratch, int64_t nk);
 
+// eigenvalues only of nk tridiagonals (d, e with stride sde; e[i] couples
+// rows i and i+1) by bisection on Sturm counts (bisect.hip); w: stride sw,
+// ascending; work: stebz_work_bytes(nk) bytes
+size_t stebz_work_bytes(int64_t nk);
+hipError_t stebz(hipStream_t st, const double* d, const double* e, int64_t sde, int64_t n, int64_t nk, double* w,
+                 int64_t sw, void* work);
+
 // ---------------------------------------------------------------------------
 // small kernels (util.hip)
 hipError_t fill_zero(hipStream_t st, void* p, size_t bytes);

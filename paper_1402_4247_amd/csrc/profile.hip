@@ -66,6 +66,15 @@ void prof_launch_end(int phase, hipStream_t st, const ProfLaunch& pl, double byt
     p->flops += flops;
 }
 
+void* prof_suspend()
+{
+    Profiler* p = g_prof;
+    g_prof = nullptr;
+    return p;
+}
+
+void prof_resume(void* saved) { g_prof = static_cast<Profiler*>(saved); }
+
 Profiler* prof_start(int phase, int stride, size_t reserve)
 {
     Profiler* p = new Profiler;

@@ -23,6 +23,16 @@ build stand-ins with the same shapes and structure:
   S lies in [0.5, 1.5] for every k);
   H_ij = -exp(-r^2/3) v_ij e^{i k.R_ij} (i != j), H_ii ~ U[-0.5, 0.5].
   u, v are seeded unit-modulus phases with u_ji = conj(u_ij).
+  With ``overlap="spectral"`` c = 0.5 / max_k ||W(k)||_2 over the 4x4x4
+  grid instead (the bound is met at the worst k-point, so the overlaps are
+  less well conditioned: lambda(S) reaches 0.5 or 1.5).
+* ``known_spectrum_pencil`` - prescribed overlap condition number and known
+  generalized eigenvalues: S = U diag(s) U^H, s log-spaced in [1/kappa, 1],
+  H = B Q diag(lambda) Q^H B^H with B = U diag(s)^(1/2), so H c = lambda S c
+  for the columns of C = U diag(s)^(-1/2) Q.
+* ``lcao_near_dependent`` - one k-point of the LCAO pencil with the overlap
+  scaled towards linear dependence: S = I + c W(k) with c set so that the
+  smallest eigenvalue of S is delta (kappa(S) about 2 / delta).
 * k-points: a 4x4x4 Monkhorst-Pack grid k = ((2p-5)/8, (2q-5)/8, (2r-5)/8)
   2 pi / a, and a 2x2x2 grid (+-1/4) 2 pi / a.
 
@@ -94,7 +104,9 @@ def mp_grid(m: int):
 class LcaoSystem:
     """Positions, orbital layout and seeded phases of one pseudo-crystal."""
 
-    def __init__(self, n: int, seed: int):
+    def __init__(self, n: int, seed: int, overlap: str = "cw"):
+        if overlap not in ("cw", "spectral"):
+            raise ValueError(f"overlap must be 'cw' or 'spectral', not {overlap!r}")
         rng = np.random.default_rng(seed)
         natom = N_FE + N_O
         pos = []
@@ -151,6 +163,9 @@ class LcaoSystem:
             self.c = 0.5 / float(((magW @ x) / x).max())
         else:
             self.c = 0.5                      # a single orbital: W = 0
+        if overlap == "spectral" and magW.max() > 0.0:
+            # c = 0.5 / max_k ||W(k)||_2 over the 4x4x4 grid
+            self.c = 0.5 / max(float(np.abs(np.linalg.eigvalsh(self.w_matrix(k))).max()) for k in mp_grid(4))
 
     def real_space_blocks(self):
         """The pseudo-crystal in real space, for a Bloch sum (Band_DFT_Col
@@ -186,13 +201,21 @@ class LcaoSystem:
                 sb.append((I, J, r, Sb))
         return off, np.array(Rlist, dtype=np.float64), hb, sb
 
-    def hs(self, kfrac):
-        """(H(k), S(k)) for k = kfrac * 2 pi / a."""
-        n = self.n
+    def _bloch(self, kfrac):
         kvec = 2.0 * np.pi / CELL_A * np.asarray(kfrac, dtype=np.float64)
         a = self.atom_of
         kR_atom = self.R_atom @ kvec                 # (natom, natom), antisymmetric
-        bloch = np.exp(1j * kR_atom[a[:, None], a[None, :]])
+        return np.exp(1j * kR_atom[a[:, None], a[None, :]])
+
+    def w_matrix(self, kfrac):
+        """W(k): the overlap's off-site part before scaling (Hermitian)."""
+        W = np.where(self.same_atom, 0.0, np.exp(-self.r2 / 4.0)) * self.u * self._bloch(kfrac)
+        return np.tril(W, -1) + np.tril(W, -1).conj().T
+
+    def hs(self, kfrac):
+        """(H(k), S(k)) for k = kfrac * 2 pi / a."""
+        n = self.n
+        bloch = self._bloch(kfrac)
         W = np.where(self.same_atom, 0.0, np.exp(-self.r2 / 4.0)) * self.u * bloch
         S = np.eye(n, dtype=np.complex128) + self.c * W
         H = -np.exp(-self.r2 / 3.0) * self.v * bloch
@@ -203,9 +226,9 @@ class LcaoSystem:
         return H, S
 
 
-def lcao_batch(n: int, kfracs, seed: int):
+def lcao_batch(n: int, kfracs, seed: int, overlap: str = "cw"):
     """Stack (nk, n, n) of H(k), S(k) for one pseudo-crystal."""
-    sysm = LcaoSystem(n, seed)
+    sysm = LcaoSystem(n, seed, overlap)
     kf = np.atleast_2d(np.asarray(kfracs, dtype=np.float64))
     Hs = np.empty((len(kf), n, n), dtype=np.complex128)
     Ss = np.empty((len(kf), n, n), dtype=np.complex128)
@@ -227,6 +250,41 @@ def config3(n: int = 1024, nk: int = 64, seed: int = 3003):
 def config4(n: int = 4096, nk: int = 8, seed: int = 4004):
     """The 2x2x2 grid (+-1/4) 2 pi / a, n = 4096."""
     return lcao_batch(n, mp_grid(2)[:nk], seed)
+
+
+def known_spectrum_pencil(n: int, kappa: float, seed: int):
+    """(H, S, lam, C): S = U diag(s) U^H with s log-spaced in [1/kappa, 1] (U
+    Haar, so kappa(S) = kappa), B = U diag(sqrt(s)), H = B Q diag(lam) Q^H B^H
+    with Q Haar and lam uniform in [-1, 1], ascending.  C = U diag(s)^(-1/2) Q
+    satisfies H C = S C diag(lam) and C^H S C = I, so lam are the generalized
+    eigenvalues and C the eigenvectors, exact up to the rounding of the
+    construction."""
+    rng = np.random.default_rng(seed)
+    U = haar_unitary(rng, n)
+    Q = haar_unitary(rng, n)
+    s = np.logspace(0.0, -math.log10(kappa), n) if n > 1 else np.ones(1)
+    lam = np.sort(rng.uniform(-1.0, 1.0, n))
+    B = U * np.sqrt(s)[None, :]
+    BQ = B @ Q
+    H = (BQ * lam[None, :]) @ BQ.conj().T
+    S = (U * s[None, :]) @ U.conj().T
+    H = (H + H.conj().T) / 2.0
+    S = (S + S.conj().T) / 2.0
+    C = (U / np.sqrt(s)[None, :]) @ Q
+    return H, S, lam, C
+
+
+def lcao_near_dependent(n: int, delta: float, seed: int, kfrac=None):
+    """(H, S) of one LCAO k-point (the first 4x4x4 point by default) with
+    S = I + c W(k) and c = (1 - delta) / |lambda_min(W(k))|, so that the
+    smallest eigenvalue of S is delta: an overlap close to linear
+    dependence, as an over-complete atomic basis gives."""
+    sysm = LcaoSystem(n, seed)
+    k = mp_grid(4)[0] if kfrac is None else kfrac
+    W = sysm.w_matrix(k)
+    lmin = float(np.linalg.eigvalsh(W)[0])
+    sysm.c = (1.0 - delta) / abs(lmin)
+    return sysm.hs(k)
 
 
 def request_stream(count: int, seed: int = 5005, n_lo: int = 256, n_hi: int = 6000,

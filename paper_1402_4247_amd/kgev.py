@@ -64,7 +64,9 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
            "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device",
-           "kgev_solve_k_x_device", "kgev_batch_workspace_bytes", "kgev_solve_batch_device"]
+           "kgev_solve_k_x_device", "kgev_batch_workspace_bytes", "kgev_solve_batch_device",
+           "kgev_solve_k_device_noalloc", "kgev_stebz_device"]
+NOALLOC_SCRATCH_BYTES = 128 << 20
 PHASE_HEMV, PHASE_GEMM = 1, 2
 S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
 
@@ -94,10 +96,14 @@ def _load():
     lib.kgev_solve_k_device.argtypes = [P, P, P, I64, I64, I64, P, P, I64, P, ctypes.c_size_t, P,
                                         ctypes.POINTER(Opts), P]
     lib.kgev_solve_k_device.restype = I32
+    lib.kgev_solve_k_device_noalloc.argtypes = [P, P, P, I64, I64, I64, P, P, I64, P, ctypes.POINTER(Opts), P]
+    lib.kgev_solve_k_device_noalloc.restype = I32
     lib.kgev_hetrd_device.argtypes = [P, P, I64, I64, I64, P, P, P, P, ctypes.POINTER(Opts), P]
     lib.kgev_hetrd_device.restype = I32
     lib.kgev_stedc_device.argtypes = [P, P, P, I64, I64, P, P, P, P]
     lib.kgev_stedc_device.restype = I32
+    lib.kgev_stebz_device.argtypes = [P, P, P, I64, I64, P, P]
+    lib.kgev_stebz_device.restype = I32
     lib.kgev_unmtr_device.argtypes = [P, P, P, I64, I64, P, I64, P]
     lib.kgev_unmtr_device.restype = I32
     lib.kgev_eigh_device.argtypes = [P, P, I64, I64, I64, P, P, P, ctypes.POINTER(Opts), P]
@@ -228,6 +234,15 @@ def solve_k_device(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, dwork=None, wor
                                    None if opts is None else ctypes.byref(opts), _stream(stream))
 
 
+def solve_k_device_noalloc(ctx: Context, dH, dS, n, ld, nk, dw, dC, ldc, d_status=None,
+                           opts: Opts | None = None, stream=None) -> int:
+    """kgev_solve_k_device_noalloc: the same solve with the library's static
+    per-GPU workspace (no device allocation)."""
+    return lib.kgev_solve_k_device_noalloc(ctx.handle, _ptr(dH), _ptr(dS), n, ld, nk, _ptr(dw), _ptr(dC), ldc,
+                                           _ptr(d_status), None if opts is None else ctypes.byref(opts),
+                                           _stream(stream))
+
+
 X_EXPORT, X_REUSE = 0, 1
 
 
@@ -279,6 +294,11 @@ def hetrd_device(ctx, dA, n, lda, nk, dd, de, dtau, dV, opts=None, stream=None) 
 def stedc_device(ctx, dd, de, n, nk, dw, dZ, d_status=None, stream=None) -> int:
     return lib.kgev_stedc_device(ctx.handle, _ptr(dd), _ptr(de), n, nk, _ptr(dw), _ptr(dZ), _ptr(d_status),
                                  _stream(stream))
+
+
+def stebz_device(ctx, dd, de, n, nk, dw, stream=None) -> int:
+    """kgev_stebz_device: tridiagonal eigenvalues by bisection."""
+    return lib.kgev_stebz_device(ctx.handle, _ptr(dd), _ptr(de), n, nk, _ptr(dw), _stream(stream))
 
 
 def unmtr_device(ctx, dV, dtau, n, nk, dU, ldu, stream=None) -> int:

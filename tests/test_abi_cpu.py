@@ -73,3 +73,9 @@ def test_batch_workspace_is_the_largest_problem_and_null_ctx_rejected():
     assert got == max(K.lib.kgev_workspace_bytes(p.n, p.nk, None) for p in ps) > 0
     assert K.lib.kgev_batch_workspace_bytes(arr, 0, None) == 0
     assert K.lib.kgev_solve_batch_device(None, arr, 3, None, 0, None, None) == -1
+
+
+def test_noalloc_entry_rejects_null_context():
+    st = K.lib.kgev_solve_k_device_noalloc(None, ctypes.c_void_p(1), ctypes.c_void_p(1), 4, 4, 1,
+                                           ctypes.c_void_p(1), ctypes.c_void_p(1), 4, None, None, None)
+    assert st == -1

@@ -167,3 +167,49 @@ def test_eigen_hh_matches_oracle(n):
         assert np.abs(w[q] - w0).max() <= 1e-10 * max(np.abs(w0).max(), 1e-300)
         assert np.linalg.norm(A @ Y[q] - Y[q] * w[q]) <= 32 * n * EPS * nf
         assert np.abs(Y[q].conj().T @ Y[q] - np.eye(n)).max() <= 32 * n * EPS
+
+
+def gpu_stebz(ds, es):
+    kg = K()
+    nk, n = ds.shape
+    dd = torch.from_numpy(np.ascontiguousarray(ds)).to(DEV)
+    de = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+    de[:, : n - 1] = torch.from_numpy(np.ascontiguousarray(es)).to(DEV)
+    dw = torch.full((nk, n), np.nan, dtype=torch.float64, device=DEV)
+    with kg.Context(0) as ctx:
+        check(kg.stebz_device(ctx, dd, de, n, nk, dw), "stebz")
+        torch.cuda.synchronize()
+    return dw.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,d,e", stedc_cases(), ids=lambda x: x if isinstance(x, str) else "")
+def test_stebz_matches_oracle(name, d, e):
+    # eigenvalues only by bisection: against the oracle's QL and its Sturm
+    # bisection, within the backward-stable bound of a few eps ||T|| per value
+    n = len(d)
+    nk = 2
+    ds = np.stack([d, -3.0 * d])
+    es = np.stack([e, 3.0 * e]) if n > 1 else np.zeros((nk, 0))
+    w = gpu_stebz(ds, es.reshape(nk, max(n - 1, 0)))
+    for q in range(nk):
+        T = tri(ds[q], es[q]) if n > 1 else np.diag(ds[q])
+        nt = max(np.abs(T).max(), 1e-300)
+        w0, _ = O.tridiag_ql(ds[q], es[q])
+        wb = O.bisect_eigs(ds[q], es[q])
+        assert np.all(np.diff(w[q]) >= 0)
+        assert mx(w[q] - w0) <= 8 * n * EPS * nt, f"vs QL: {mx(w[q] - w0)}"
+        assert mx(w[q] - wb) <= 8 * n * EPS * nt, f"vs bisection: {mx(w[q] - wb)}"
+
+
+def test_stebz_closed_forms():
+    # Toeplitz: a + 2 b cos(j pi / (n + 1)); Clement: -(n-1), -(n-3), ..., n-1
+    n = 200
+    a, b = 0.3, -1.7
+    j = np.arange(1, n + 1)
+    toe = np.sort(a + 2 * b * np.cos(j * np.pi / (n + 1)))
+    m = 151
+    cle = np.arange(-(m - 1), m, 2, dtype=float)
+    w1 = gpu_stebz(np.full((1, n), a), np.full((1, n - 1), b))[0]
+    w2 = gpu_stebz(np.zeros((1, m)), np.sqrt(np.arange(1, m) * (m - np.arange(1, m)))[None])[0]
+    assert mx(w1 - toe) <= 8 * EPS * 2 * abs(b) * 4
+    assert mx(w2 - cle) <= 16 * EPS * m

@@ -60,3 +60,48 @@ def test_mixed_eigenvalues_only():
     for q in range(2):
         _, w0, _ = O.solve_k(Hs[q], Ss[q], vectors=False)
         assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+
+
+def cluster_pencil(n, seed):
+    """Known-spectrum pencil (S = B B^H well conditioned, H = B Q diag(lam)
+    Q^H B^H) whose eigenvalues include near-degenerate pairs at relative
+    gaps 1e-10, 1e-8 and 1e-5 and an exactly threefold eigenvalue."""
+    rng = np.random.default_rng(seed)
+    base = np.sort(rng.uniform(-1.0, 1.0, n - 7))
+    lam = np.sort(np.concatenate([base, [0.31, 0.31 + 1e-10, -0.47, -0.47 + 1e-8, 0.83, 0.83 + 1e-5,
+                                         -0.123, -0.123, -0.123]])[:n])
+    B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    Q = G.haar_unitary(rng, n)
+    BQ = B @ Q
+    H = (BQ * lam[None, :]) @ BQ.conj().T
+    S = B @ B.conj().T
+    return 0.5 * (H + H.conj().T), 0.5 * (S + S.conj().T), lam
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_near_degenerate_clusters(precision):
+    # clusters below the refinement's rotation threshold are where a
+    # refinement that only re-orthogonalises inside a cluster would leave the
+    # FP32 mixing of near-degenerate vectors in place
+    n, nk = 160, 2
+    trip = [cluster_pencil(n, 900 + q) for q in range(nk)]
+    Hs = np.stack([t[0] for t in trip])
+    Ss = np.stack([t[1] for t in trip])
+    w, C, st = solve(Hs, Ss, precision=precision)
+    assert np.all(st == 0)
+    for q in range(nk):
+        H, S, lam = trip[q]
+        s0, w0, C0 = O.solve_k(H, S)
+        assert s0 == 0
+        assert np.abs(w[q] - lam).max() <= 1e-10 * np.abs(lam).max()
+        assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+        r_res, r_orth = residuals(H, S, w[q], C[q])
+        assert r_res <= 1e-12 and r_orth <= 1e-12, (r_res, r_orth)
+        # vectors of eigenvalues separated by more than 1e-6 one by one, the
+        # tighter clusters through their S-orthogonal projectors
+        assert vec_mismatch(C0, C[q], S, w0, gap=1e-6) <= 1e-10
+        for centre in (0.31, -0.47, -0.123):
+            sel = np.abs(lam - centre) < 1e-7
+            P = C[q][:, sel] @ C[q][:, sel].conj().T @ S
+            P0 = C0[:, sel] @ C0[:, sel].conj().T @ S
+            assert np.abs(P - P0).max() <= 1e-9, f"cluster at {centre}"

@@ -61,6 +61,54 @@ def test_mix_equals_alone_and_oracle():
             assert rr <= 1e-12 and ro <= 1e-12
 
 
+def make_mix_req(n, nk, seed):
+    # one config-1 pencil per request; its k-points differ by a shift of H
+    # (H + 0.01 q S), which moves every eigenvalue and keeps the cost
+    H, S = G.config1(n, seed)
+    Hs = np.stack([H + 0.01 * q * S for q in range(nk)])
+    Ss = np.broadcast_to(S, (nk, n, n))
+    return dict(n=n, nk=nk, Hs=Hs, Ss=Ss, dH=dev(Hs), dS=dev(Ss),
+                dw=torch.zeros((nk, n), dtype=torch.float64, device=DEV),
+                dC=torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV))
+
+
+def test_mix_equals_alone_serving_mix():
+    # 24 requests drawn from the serving stream's mix (n log-uniform in
+    # [256, 6000], 1..16 k-points, in arrival order), keeping those with
+    # n <= 2100 so that the test stays within a minute
+    kg = K()
+    draws = [r for r in G.request_stream(200, seed=5005) if r[0] <= 2100][:24]
+    assert len(draws) == 24 and max(n for n, _, _ in draws) >= 2000
+    reqs = [make_mix_req(n, nk, seed) for n, nk, seed in draws]
+    torch.cuda.synchronize()
+    with kg.Server(0, 0, 4) as srv:
+        tickets = [srv.submit(r["dH"], r["dS"], r["n"], r["nk"], r["dw"], r["dC"]) for r in reqs]
+        results = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    overlaps = sum(1 for a in results for b in results
+                   if a is not b and a.t_admit < b.t_done and b.t_admit < a.t_done)
+    assert overlaps > 0
+    with kg.Context(0) as ctx:
+        for r, res in zip(reqs, results):
+            assert res.status == 0 and res.t_submit <= res.t_admit <= res.t_done
+            n, nk = r["n"], r["nk"]
+            w = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+            C = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV)
+            check(kg.solve_k_device(ctx, r["dH"], r["dS"], n, n, nk, w, C, n), "alone")
+            torch.cuda.synchronize()
+            assert torch.equal(r["dw"], w) and torch.equal(r["dC"], C), f"request n={n} nk={nk}"
+            del w, C
+    # the three smallest requests against the oracle
+    for r in sorted(reqs, key=lambda r: r["n"])[:3]:
+        w = r["dw"].cpu().numpy()
+        C = host(r["dC"])
+        for q in (0, r["nk"] - 1):
+            _, w0, _ = O.solve_k(r["Hs"][q], r["Ss"][q])
+            assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+            rr, ro = residuals(r["Hs"][q], r["Ss"][q], w[q], C[q])
+            assert rr <= 1e-12 and ro <= 1e-12
+
+
 def test_budget_limits_and_rejection():
     kg = K()
     small = make_req(80, 1, 11)

@@ -70,13 +70,19 @@ def test_panel_width_does_not_change_result_beyond_rounding():
     assert np.abs(w1 - w2).max() <= 1e-12 * np.abs(w1).max()
 
 
-def test_eigenvalues_only():
-    Hs, Ss = G.config1_batch(96, 2, 77)
+@pytest.mark.parametrize("gen,n,nk", [("config1", 96, 2), ("lcao", 1, 1), ("lcao", 2, 2), ("lcao", 333, 3),
+                                      ("config1", 129, 2)])
+def test_eigenvalues_only(gen, n, nk):
+    # Band_DFT_Col's eigenvalue pass: Part 4's tridiagonal step by bisection
+    Hs, Ss = G.config1_batch(n, nk, 77) if gen == "config1" else G.config2(n, nk, 2002)
     w, _, st = gpu_solve(Hs, Ss, vectors=False)
     assert np.all(st == 0)
-    for q in range(2):
+    wv, _, _ = gpu_solve(Hs, Ss)
+    for q in range(nk):
         _, w0, _ = O.solve_k(Hs[q], Ss[q], vectors=False)
         assert np.abs(w[q] - w0).max() <= 1e-10 * np.abs(w0).max()
+        assert np.all(np.diff(w[q]) >= 0)
+        assert np.abs(w[q] - wv[q]).max() <= 1e-12 * np.abs(wv[q]).max()
 
 
 def test_statuses_isolated_per_k():

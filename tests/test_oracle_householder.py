@@ -109,3 +109,20 @@ def test_zgemm_matches_definition():
     assert np.allclose(got, A.conj().T @ A, atol=1e-13)
     got = O.zgemm("N", "C", B, B)
     assert np.allclose(got, B @ B.conj().T, atol=1e-13)
+
+
+def test_normalize_cols_unit_norm_same_direction():
+    # Eigen_HH's normalisation: every column leaves with unit 2-norm and
+    # points the same way as it came in (a 3-4-5 triangle, then columns whose
+    # norms span twelve orders of magnitude)
+    eps = np.finfo(float).eps
+    got = O.normalize_cols(np.array([[3.0], [4.0j]]))
+    assert np.abs(got - np.array([[0.6], [0.8j]])).max() <= 2 * eps
+    rng = np.random.default_rng(13)
+    U = (rng.standard_normal((9, 6)) + 1j * rng.standard_normal((9, 6))) * np.logspace(-6, 6, 6)
+    got = O.normalize_cols(U)
+    assert np.abs(np.linalg.norm(got, axis=0) - 1.0).max() <= 8 * eps
+    for j in range(U.shape[1]):
+        u = U[:, j] / np.linalg.norm(U[:, j])
+        assert abs(abs(np.vdot(u, got[:, j])) - 1.0) <= 8 * eps
+        assert np.abs(got[:, j] - u).max() <= 8 * eps

@@ -241,3 +241,19 @@ def test_values_only_equals_vectors_eigenvalues():
     st1, w1, _ = O.solve_k(H, S, vectors=False)
     st2, w2, _ = O.solve_k(H, S, vectors=True)
     assert st1 == st2 == O.OK and np.array_equal(w1, w2)
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_known_spectrum_ill_conditioned_overlap(kappa):
+    # S = U diag(s) U^H with kappa(S) = kappa and known generalized eigenpairs:
+    # the eigenvalues must lie within the first-order perturbation bound
+    # 4 n eps (||H|| + |lambda| ||S||) ||c_j||^2 of the exact ones
+    n = 120
+    H, S, lam, Cex = G.known_spectrum_pencil(n, kappa, 31)
+    eps = np.finfo(float).eps
+    tol = 4 * n * eps * (np.linalg.norm(H, 2) + np.abs(lam) * np.linalg.norm(S, 2)) * np.linalg.norm(Cex, axis=0) ** 2
+    st, w, C = O.solve_k(H, S)
+    assert st == 0
+    assert np.all(np.abs(w - lam) <= tol)
+    assert np.abs(C.conj().T @ S @ C - np.eye(n)).max() <= 4 * n * eps * kappa
+    assert np.linalg.norm(H @ C - S @ C * w) / np.linalg.norm(H) <= 4 * n * eps * kappa
