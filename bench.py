@@ -59,33 +59,44 @@ METRIC = "k-point eigensolves/s at n=2000 (FP64 vs FP32+refine); p50/p99 latency
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hetrd_zhemv_n2000_nk16_traffic.md")
-TRAFFIC_SOURCES = [os.path.join(HERE, "paper_1402_4247_amd", "csrc", f) for f in ("hetrd.hip", "common.hpp")]
+CSRC = os.path.join(HERE, "paper_1402_4247_amd", "csrc")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def zhemv_source_sha256():
+    """SHA-256 of the Hermitian-product kernel's own source text (the
+    hetrd_zhemv template in hetrd.hip, from its template line to its closing
+    brace) followed by common.hpp, whose helpers it uses."""
+    import hashlib
+    with open(os.path.join(CSRC, "hetrd.hip")) as fh:
+        text = fh.read()
+    i0 = text.index("template <typename R, bool BUF>\n__global__ __launch_bounds__(256, 3) void hetrd_zhemv(")
+    i1 = text.index("\n}\n", i0) + 3
+    h = hashlib.sha256(text[i0:i1].encode())
+    with open(os.path.join(CSRC, "common.hpp"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
 def counter_traffic(n, nk):
     """HBM bytes per launch of the Hermitian-product kernel from the committed
     rocprofv3 counter summary, or None when the workload differs or the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel's source has changed since the counters were taken."""
     if (n, nk) != (2000, 16) or not os.path.exists(TRAFFIC_FILE):
         return None
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
     fields = {}
     with open(TRAFFIC_FILE) as fh:
         for line in fh:
             if ":" in line:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("source_sha256") != h.hexdigest():
+    if fields.get("source_sha256") != zhemv_source_sha256():
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return {"bytes": float(fields["traffic_bytes_per_launch"]), "counters": fields.get("counters"),
+            "ratio_to_algorithmic": float(fields["ratio_to_algorithmic"])}
 
 
 def host_cpu_model():
@@ -124,7 +135,11 @@ def roofline_object(prof, phase, elapsed, note, traffic, K):
         extra = {"alg_flops_per_launch": per_launch,
                  "flop_count": "8 m n k per complex product (half for lower-only outputs, 4 m n k for a real "
                                "right operand), whatever the kernel's own form"}
-    return {**base, "achieved": achieved, "frac": achieved / base["peak"], "traffic": traffic,
+    if traffic is not None:
+        extra["traffic_counters"] = traffic["counters"]
+        extra["traffic_ratio_to_algorithmic"] = traffic["ratio_to_algorithmic"]
+    return {**base, "achieved": achieved, "frac": achieved / base["peak"],
+            "traffic": None if traffic is None else traffic["bytes"],
             "launches": prof["phase_launches"], "timed_launches": prof["launches"], "avg_launch_us": 1e3 * avg_ms,
             **extra, "measured_on": note, "share_of_step": share}
 

@@ -85,7 +85,8 @@ typedef struct {
                              (and joined back into) the caller's stream: 0 = default, 1..8 */
     int32_t s_method;     /* Part 2: KGEV_S_EIG (default, the paper's diagonalisation of S,
                              X = U s^-1/2, KGEV_ENOTPD when s_min <= s_tol s_max),
-                             KGEV_S_CHOLESKY (S = L L^H, X = L^-H: the same eigenpairs with a cheaper
+                             KGEV_S_CHOLESKY (S = L L^H, X = L^-H with its columns in reverse order:
+                             the same eigenpairs with a cheaper
                              S side; a pivot <= s_tol * max_i S_ii gives KGEV_ENOTPD), or
                              KGEV_S_PRUNE (the paper's diagonalisation; the n - n' directions with
                              s_j <= s_tol s_max are dropped instead of failing: w[0:n'] are the
@@ -222,12 +223,22 @@ kgev_status kgev_solve_k_x_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z*
                                   void* stream);
 
 /*
- * A batch of systems of uneven order: problem q is solved exactly as
- * kgev_solve_k_device would solve it (all of its k-points in one batched
- * call, with the same opts), the problems one after another on `stream`,
- * sharing one workspace.  With opts.use_graph and a non-null stream, the
- * whole batch is captured once as one HIP graph and replayed by later calls
- * with the same problems, buffers, workspace, options and stream.
+ * A batch of systems of uneven order (the k-point loop of Band_DFT_Col,
+ * Section III, over pencils of different sizes).  The problems are grouped
+ * into size classes, largest order first: a problem joins the current class
+ * when the class order N is at most 256 or at most 1.26 times its own order.
+ * Every k-point of a class is embedded in a pencil of order N,
+ * H' = [[H, 0], [0, 0]], S' = [[S, 0], [0, s I]] with s = max_i S_ii, and
+ * the class is solved as one batched solve (each launch covers all of its
+ * k-points); the pencil's eigenpairs are exactly the embedded ones that
+ * vanish on the padded rows, and they are written to the problem's buffers
+ * in ascending order.  A class of a single problem of the class order is
+ * solved in place, bitwise as kgev_solve_k_device would solve it; others
+ * agree with their own calls to rounding.  Classes run one after another on
+ * `stream`, sharing one workspace.  With opts.use_graph and a non-null
+ * stream, the whole batch is captured once as one HIP graph and replayed by
+ * later calls with the same problems, buffers, workspace, options and
+ * stream.
  *   probs  : host array of count problem descriptors (read during the call
  *            only); each field as the argument of kgev_solve_k_device of the
  *            same name (d_status may be NULL).
@@ -247,7 +258,9 @@ typedef struct kgev_problem {
     int64_t ldc;
     int32_t* d_status;
 } kgev_problem;
-/* the largest per-problem workspace of the batch (0 if none is valid) */
+/* the largest workspace of the batch's size classes: a class's solve
+ * workspace plus, when it embeds, the embedded H', S' (and C' with vectors),
+ * eigenvalues, statuses and column map (0 if a descriptor has n < 1 or nk < 1) */
 size_t kgev_batch_workspace_bytes(const kgev_problem* probs, int64_t count, const kgev_opts* opts);
 kgev_status kgev_solve_batch_device(kgev_ctx* ctx, const kgev_problem* probs, int64_t count, void* dwork,
                                     size_t work_bytes, const kgev_opts* opts, void* stream);

@@ -89,7 +89,7 @@ struct SolvePlan {
     // buffers and the FP64 refinement scratch (size 0 in the FP64 form)
     bool mixed;
     size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_pvv, f_qpart, f_uwork, f_d, f_e, f_pnorm;
-    size_t r_Ynext, r_G, r_S, r_F, r_pS, r_pR, r_delta;
+    size_t r_Ynext, r_G, r_S, r_F, r_pS, r_pR, r_delta, r_cid;
     size_t total;
 };
 
@@ -165,6 +165,7 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
     p.r_pS = L.add(m * r * n * nk);
     p.r_pR = L.add(m * r * n * nk);
     p.r_delta = L.add(m * r * nk);
+    p.r_cid = L.add(m * i4 * n * nk);
     p.total = L.total;
     return p;
 }
@@ -380,15 +381,19 @@ kgev_status eigen_hh_mixed(const SolvePlan& p, void* w, hipStream_t st, double* 
     rw.pS = at<double>(w, p.r_pS);
     rw.pR = at<double>(w, p.r_pR);
     rw.delta = at<double>(w, p.r_delta);
+    rw.cid = at<int>(w, p.r_cid);
+    rw.status = status;
     KCHECK(refine(st, rw, nk, iters, wout));
     return KGEV_OK;
 }
 
 // Xin: Part 2 skipped and this X (n x n per k, ld n) used; Xout: the X of
 // Part 2 also written there.
+// nreal: per problem, the order of an embedded pencil (its padded
+// directions of S sort last), or nullptr
 kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStream_t st, const double2* H,
                          const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status,
-                         const double2* Xin = nullptr, double2* Xout = nullptr)
+                         const double2* Xin = nullptr, double2* Xout = nullptr, const int* nreal = nullptr)
 {
     const int64_t n = p.n, nk = p.nk, nn = n * n;
     int* status = at<int>(w, p.status);
@@ -406,14 +411,15 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     } else {
         KCHECK(copy_lower_check<double>(st, n, S, ld, ld * n, Aw, n, nn, status, nk));
         if (o.s_method == KGEV_S_CHOLESKY) {
-            // Part 2 in Cholesky form: S = L L^H, X = L^(-H) (L in Vs, L^(-1) in G)
+            // Part 2 in Cholesky form: S = L L^H, X = L^(-H) J, J the column
+            // reversal (L in Vs, L^(-1) in G)
             KCHECK(cholesky_x(st, n, Aw, n, nn, Vs, G, X, at<double2>(w, p.cwork), sS, o.s_tol, status, nk));
         } else {
             // Part 2: S = U diag(s) U^H, X = U diag(s)^(-1/2) (pruned: the
             // columns with s_j <= s_tol s_max are zero)
             r = eigen_hh(p, w, st, sS, X, status);
             if (r != KGEV_OK) return r;
-            KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk, o.s_method == KGEV_S_PRUNE));
+            KCHECK(normalize_cols(st, n, X, n, nn, sS, n, o.s_tol, status, nk, o.s_method == KGEV_S_PRUNE, nreal));
         }
     }
     if (Xout) KCHECK(hipMemcpyAsync(Xout, X, sizeof(double2) * (size_t)nn * nk, hipMemcpyDeviceToDevice, st));
@@ -423,7 +429,7 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
     KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, Vs, n, nn, X, n, nn, zero, G, n, nn, nk, false));
     KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, X, n, nn, G, n, nn, zero, Aw, n, nn, nk, true));
     if (o.s_method == KGEV_S_PRUNE)
-        KCHECK(prune_shift(st, n, Aw, nn, at<double>(w, p.ppart), sS, n, o.s_tol, at<int>(w, p.ndrop), nk));
+        KCHECK(prune_shift(st, n, Aw, nn, at<double>(w, p.ppart), sS, n, o.s_tol, at<int>(w, p.ndrop), nk, nreal));
     // Part 4: A = Y diag(lambda) Y^H with Y = Q_A Z (Householder reflectors
     // Q_A, real tridiagonal eigenvectors Z), C = X Y
     if (o.precision == KGEV_PREC_FP32_REFINE) {
@@ -496,10 +502,10 @@ kgev_status ensure_aux(kgev_ctx* ctx, int G)
 
 kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, void* w, hipStream_t st,
                           const double2* H, const double2* S, int64_t ld, int64_t nk, double* dw, double2* dC,
-                          int64_t ldc, int32_t* d_status)
+                          int64_t ldc, int32_t* d_status, const int* nreal = nullptr)
 {
     const int64_t n = g.p.n;
-    if (g.G == 1) return solve_device(g.p, o, w, st, H, S, ld, dw, dC, ldc, d_status);
+    if (g.G == 1) return solve_device(g.p, o, w, st, H, S, ld, dw, dC, ldc, d_status, nullptr, nullptr, nreal);
     kgev_status r = ensure_aux(ctx, g.G);
     if (r != KGEV_OK) return r;
     KCHECK(hipEventRecord(ctx->ev[0], st));
@@ -509,7 +515,8 @@ kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, vo
         hipStream_t s = q == 0 ? st : ctx->aux[q - 1];
         if (q > 0) KCHECK(hipStreamWaitEvent(s, ctx->ev[0], 0));
         r = solve_device(pq, o, static_cast<char*>(w) + (size_t)q * g.region, s, H + k0 * ld * n, S + k0 * ld * n,
-                         ld, dw + k0 * n, dC ? dC + k0 * ldc * n : nullptr, ldc, d_status ? d_status + k0 : nullptr);
+                         ld, dw + k0 * n, dC ? dC + k0 * ldc * n : nullptr, ldc, d_status ? d_status + k0 : nullptr,
+                         nullptr, nullptr, nreal ? nreal + k0 : nullptr);
         if (r != KGEV_OK) return r;
         if (q > 0) KCHECK(hipEventRecord(ctx->ev[q], s));
     }
@@ -526,6 +533,126 @@ void drop_graphs(kgev_ctx* ctx)
     ctx->graphs.clear();
     for (auto& e : ctx->batch_graphs) (void)hipGraphExecDestroy(e.second);
     ctx->batch_graphs.clear();
+}
+
+// Size classes of a batch of uneven order, largest order first: a problem
+// joins the current class when the class order N is at most 256 (small
+// pencils, where launches rather than arithmetic set the cost) or at most
+// 1.26 n (at most twice its own arithmetic).
+struct BatchClass {
+    int64_t N = 0, K = 0;
+    std::vector<int64_t> members;
+};
+
+std::vector<BatchClass> batch_classes(const kgev_problem* probs, int64_t count)
+{
+    std::vector<int64_t> idx((size_t)count);
+    for (int64_t q = 0; q < count; ++q) idx[(size_t)q] = q;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return probs[a].n > probs[b].n; });
+    std::vector<BatchClass> cls;
+    for (int64_t q : idx) {
+        const int64_t n = probs[q].n;
+        if (cls.empty() || !(cls.back().N <= 256 || (double)cls.back().N <= 1.26 * (double)n)) {
+            cls.emplace_back();
+            cls.back().N = n;
+        }
+        cls.back().members.push_back(q);
+        cls.back().K += probs[q].nk;
+    }
+    return cls;
+}
+
+// A class of one problem of the class order is solved in place; any other
+// is embedded (batch.hip): packed H', S', the embedded eigenvalues, vectors
+// and statuses, the column map, then the solve's own workspace.
+struct ClassLayout {
+    bool direct;
+    size_t Hp, Sp, wp, Cp, stp, map, spad, nreal, solve, total;
+    Groups grp;
+};
+
+ClassLayout class_layout(const kgev_problem* probs, const BatchClass& c, const kgev_opts& o)
+{
+    ClassLayout L{};
+    const int64_t N = c.N, K = c.K;
+    L.direct = c.members.size() == 1 && probs[c.members[0]].n == N;
+    L.grp = make_groups(N, K, o);
+    Layout a;
+    if (!L.direct) {
+        const size_t nn = (size_t)N * N;
+        L.Hp = a.add(sizeof(double2) * nn * K);
+        L.Sp = a.add(sizeof(double2) * nn * K);
+        L.wp = a.add(sizeof(double) * (size_t)N * K);
+        L.Cp = a.add(o.want_vectors ? sizeof(double2) * nn * K : 0);
+        L.stp = a.add(sizeof(int32_t) * (size_t)K);
+        L.map = a.add(sizeof(int) * (size_t)N * K);
+        L.spad = a.add(sizeof(double) * (size_t)K);
+        L.nreal = a.add(sizeof(int) * (size_t)K);
+    }
+    L.solve = a.add(L.grp.region * (size_t)L.grp.G);
+    L.total = a.total;
+    return L;
+}
+
+kgev_status solve_class(kgev_ctx* ctx, const kgev_problem* probs, const BatchClass& c, const kgev_opts& o0,
+                        void* w, hipStream_t st, bool tuned)
+{
+    kgev_opts o = o0;
+    if (tuned) {
+        auto it = ctx->tuned_nb.find({c.N, o.precision});
+        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
+    }
+    const ClassLayout L = class_layout(probs, c, o);
+    char* base = static_cast<char*>(w);
+    if (L.direct) {
+        const kgev_problem& pr = probs[c.members[0]];
+        return solve_grouped(ctx, L.grp, o, base + L.solve, st, (const double2*)pr.dH, (const double2*)pr.dS, pr.ld,
+                             pr.nk, pr.dw, o.want_vectors ? (double2*)pr.dC : nullptr, pr.ldc, pr.d_status);
+    }
+    const int64_t N = c.N;
+    double2* Hp = reinterpret_cast<double2*>(base + L.Hp);
+    double2* Sp = reinterpret_cast<double2*>(base + L.Sp);
+    double* wp = reinterpret_cast<double*>(base + L.wp);
+    double2* Cp = o.want_vectors ? reinterpret_cast<double2*>(base + L.Cp) : nullptr;
+    int32_t* stp = reinterpret_cast<int32_t*>(base + L.stp);
+    int* map = reinterpret_cast<int*>(base + L.map);
+    double* spad = reinterpret_cast<double*>(base + L.spad);
+    int* nreal = reinterpret_cast<int*>(base + L.nreal);
+    // Cholesky form: no ordering by eigenvalue, the padding keeps the pivot
+    // threshold (max_i S_ii); otherwise the padded directions must sort after
+    // the pencil's own
+    const int mode = o.s_method == KGEV_S_CHOLESKY ? 0 : 1;
+    std::vector<std::pair<BatchDescs, int64_t>> chunks;
+    int64_t slot = 0;
+    for (size_t q0 = 0; q0 < c.members.size(); q0 += BATCH_DESC) {
+        BatchDescs ds;
+        memset(&ds, 0, sizeof(ds));
+        ds.slot_base = slot;
+        int rel = 0;
+        for (size_t q = q0; q < c.members.size() && q < q0 + BATCH_DESC; ++q) {
+            const kgev_problem& pr = probs[c.members[q]];
+            BatchDesc& d = ds.d[ds.count++];
+            d.H = (const double2*)pr.dH;
+            d.S = (const double2*)pr.dS;
+            d.w = pr.dw;
+            d.C = (double2*)pr.dC;
+            d.status = pr.d_status;
+            d.n = pr.n;
+            d.ld = pr.ld;
+            d.ldc = pr.ldc;
+            d.slot0 = rel;
+            rel += (int)pr.nk;
+        }
+        KCHECK(batch_prep(st, ds, rel, mode, spad, nreal));
+        KCHECK(batch_embed(st, ds, rel, N, spad, Hp, Sp));
+        chunks.push_back({ds, rel});
+        slot += rel;
+    }
+    const kgev_status r = solve_grouped(ctx, L.grp, o, base + L.solve, st, Hp, Sp, N, c.K, wp, Cp, N, stp,
+                                        mode == 1 ? nreal : nullptr);
+    if (r != KGEV_OK) return r;
+    for (const auto& ch : chunks) KCHECK(batch_extract(st, ch.first, ch.second, N, Cp, wp, map, stp, o.want_vectors != 0));
+    return KGEV_OK;
 }
 
 // Workspace of kgev_solve_k_device_noalloc: one static array per GPU, reserved
@@ -752,10 +879,11 @@ kgev_status kgev_solve_k_device_noalloc(kgev_ctx* ctx, const kgev_z* dH, const k
 size_t kgev_batch_workspace_bytes(const kgev_problem* probs, int64_t count, const kgev_opts* opts)
 {
     if (!probs || count < 1) return 0;
-    size_t mx = 0;
     for (int64_t q = 0; q < count; ++q)
-        if (probs[q].n >= 1 && probs[q].nk >= 1)
-            mx = std::max(mx, kgev_workspace_bytes(probs[q].n, probs[q].nk, opts));
+        if (probs[q].n < 1 || probs[q].nk < 1) return 0;
+    const kgev_opts o = resolve_opts(opts);
+    size_t mx = 0;
+    for (const BatchClass& c : batch_classes(probs, count)) mx = std::max(mx, class_layout(probs, c, o).total);
     return mx;
 }
 
@@ -783,13 +911,12 @@ kgev_status kgev_solve_batch_device(kgev_ctx* ctx, const kgev_problem* probs, in
         if (r != KGEV_OK) return r;
         w = ctx->work;
     }
-    kgev_opts oe = o;     // each problem's call launches its kernels directly
+    kgev_opts oe = o;     // the kernels are launched directly (a graph, if any, is taken around all of them)
     oe.use_graph = 0;
+    const std::vector<BatchClass> classes = batch_classes(probs, count);
     auto run_all = [&](hipStream_t st) -> kgev_status {
-        for (int64_t q = 0; q < count; ++q) {
-            const kgev_problem& pr = probs[q];
-            const kgev_status r = kgev_solve_k_device(ctx, pr.dH, pr.dS, pr.n, pr.ld, pr.nk, pr.dw, pr.dC, pr.ldc, w,
-                                                      need, pr.d_status, &oe, st);
+        for (const BatchClass& c : classes) {
+            const kgev_status r = solve_class(ctx, probs, c, oe, w, st, !opts || opts->panel_nb == 0);
             if (r != KGEV_OK) return r;
         }
         return KGEV_OK;

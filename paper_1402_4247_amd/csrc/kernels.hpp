@@ -129,15 +129,18 @@ template <typename R>
 hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t ss, cx<R>* dst, int64_t ldd,
                            int64_t sd, int64_t nk);
 // columns to unit 2-norm, optionally divided by sqrt(s_j); with s given, also
-// sets status 1 when s_0 <= s_tol * s_{n-1}
-// (prune: a column with s_j <= s_tol s_{n-1} is zeroed instead, no status)
+// sets status 1 when s_0 <= s_tol * s_max
+// (prune: a column with s_j <= s_tol s_max is zeroed instead, no status);
+// s_max = s_{n-1}, or s_{nreal[k]-1} for problem k when nreal is given (an
+// embedded problem whose padded directions sort last)
 hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
-                          int64_t ss, double s_tol, int* status, int64_t nk, int prune = 0);
+                          int64_t ss, double s_tol, int* status, int64_t nk, int prune = 0,
+                          const int* nreal = nullptr);
 // pruned canonical orthogonalisation (util.hip): shift the dropped directions
 // of A above its spectrum; afterwards set their eigenvalues to +inf and
 // eigenvector columns to zero.  part: n doubles per k; ndrop: nk ints.
 hipError_t prune_shift(hipStream_t st, int64_t n, double2* A, int64_t sA, double* part, const double* s, int64_t sst,
-                       double s_tol, int* ndrop, int64_t nk);
+                       double s_tol, int* ndrop, int64_t nk, const int* nreal = nullptr);
 hipError_t prune_finish(hipStream_t st, int64_t n, double* w, double2* C, int64_t ldc, const int* ndrop, int64_t nk);
 hipError_t status_init(hipStream_t st, int* status, int64_t nk);
 // nk synthetic matrices (entries in [-1, 1), real diagonal) for timing runs
@@ -160,9 +163,38 @@ struct RefineWs {
     double2* G; double2* P; double2* S; double2* F;   // n x n scratch each
     double* pS; double* pR;   // n per problem
     double* delta;            // one per problem
+    int* cid;                 // n per problem: cluster index of each eigenvalue
+    int* status;              // per problem (ST_NOCONV when the last sweep was still far from converged)
 };
 // `iters` refinement sweeps; lam_out (n per problem) gets the refined eigenvalues
 hipError_t refine(hipStream_t st, const RefineWs& ws, int64_t nk, int iters, double* lam_out);
+
+// systems of uneven order embedded in one order N (batch.hip).  A chunk of
+// at most BATCH_DESC problems travels by value in the kernel arguments;
+// problem p of the chunk owns slots slot_base + slot0 .. + nk - 1 of the
+// embedded batch.
+struct BatchDesc {
+    const double2* H;
+    const double2* S;
+    double* w;
+    double2* C;
+    int32_t* status;
+    int64_t n, ld, ldc;
+    int slot0;
+};
+constexpr int BATCH_DESC = 32;
+struct BatchDescs {
+    BatchDesc d[BATCH_DESC];
+    int count;
+    int64_t slot_base;
+};
+// per slot: the padding of S (mode 0: max_i S_ii; mode 1: 2 ||S||_F, above
+// every eigenvalue of S, so the padded directions sort last) and the order
+hipError_t batch_prep(hipStream_t st, const BatchDescs& ds, int64_t slots, int mode, double* spad, int* nreal);
+hipError_t batch_embed(hipStream_t st, const BatchDescs& ds, int64_t slots, int64_t N, const double* spad, double2* Hp,
+                       double2* Sp);
+hipError_t batch_extract(hipStream_t st, const BatchDescs& ds, int64_t slots, int64_t N, const double2* Cp,
+                         const double* wp, int* map, int* stp, bool with_vectors);
 
 // back-transformation U <- Q U, or U <- U Q with right (util.hip); work: see
 // unmtr_work_elems

@@ -79,8 +79,12 @@ __global__ __launch_bounds__(256) void k_real_to_complex(int64_t n, const double
 }
 
 // one workgroup per column
+// s (when given): the ascending eigenvalues of S; the largest of the
+// problem's own is s[nreal[b] - 1] when nreal is given (an embedded problem
+// whose padded directions sort last), else s[n - 1]
 __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, int64_t ldu, int64_t su, const double* s,
-                                                       int64_t sst, double s_tol, int* status, int prune)
+                                                       int64_t sst, double s_tol, int* status, int prune,
+                                                       const int* nreal)
 {
     __shared__ double sh[4];
     const int64_t b = blockIdx.y;
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, i
     double f = 1.0 / sqrt(ss);
     if (s) {
         const double sj = s[b * sst + j];
-        const double smax = s[b * sst + n - 1];
+        const double smax = s[b * sst + (nreal ? nreal[b] : n) - 1];
         f = f / sqrt(sj);
         if (prune) {
             // a pruned direction: its column of X is zero
@@ -261,10 +265,10 @@ hipError_t real_to_complex(hipStream_t st, int64_t n, const double* src, int64_t
 }
 
 hipError_t normalize_cols(hipStream_t st, int64_t n, double2* U, int64_t ldu, int64_t su, const double* s, int64_t ss,
-                          double s_tol, int* status, int64_t nk, int prune)
+                          double s_tol, int* status, int64_t nk, int prune, const int* nreal)
 {
     hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, U, ldu, su, s, ss,
-                       s_tol, status, prune);
+                       s_tol, status, prune, nreal);
     return hipGetLastError();
 }
 
@@ -299,12 +303,13 @@ __global__ __launch_bounds__(256) void k_prune_colnorm(int64_t n, const double2*
 }
 
 __global__ __launch_bounds__(256) void k_prune_shift(int64_t n, double2* A, int64_t sA, const double* part,
-                                                     const double* s, int64_t sst, double s_tol, int* ndrop)
+                                                     const double* s, int64_t sst, double s_tol, int* ndrop,
+                                                     const int* nreal)
 {
     __shared__ double sh[4];
     __shared__ int sc[4];
     const int64_t b = blockIdx.x;
-    const double smax = s[b * sst + n - 1];
+    const double smax = s[b * sst + (nreal ? nreal[b] : n) - 1];
     double acc = 0.0;
     int cnt = 0;
     for (int64_t j = threadIdx.x; j < n; j += 256) {
@@ -335,10 +340,11 @@ __global__ __launch_bounds__(256) void k_prune_finish(int64_t n, double* w, doub
 }  // namespace
 
 hipError_t prune_shift(hipStream_t st, int64_t n, double2* A, int64_t sA, double* part, const double* s, int64_t sst,
-                       double s_tol, int* ndrop, int64_t nk)
+                       double s_tol, int* ndrop, int64_t nk, const int* nreal)
 {
     hipLaunchKernelGGL(k_prune_colnorm, dim3((unsigned)n, (unsigned)nk), dim3(256), 0, st, n, A, sA, part);
-    hipLaunchKernelGGL(k_prune_shift, dim3((unsigned)nk), dim3(256), 0, st, n, A, sA, part, s, sst, s_tol, ndrop);
+    hipLaunchKernelGGL(k_prune_shift, dim3((unsigned)nk), dim3(256), 0, st, n, A, sA, part, s, sst, s_tol, ndrop,
+                       nreal);
     return hipGetLastError();
 }
 

@@ -66,11 +66,19 @@ def test_host_api_rejects_null_context():
     assert st == -1 and bad.value == -1
 
 
-def test_batch_workspace_is_the_largest_problem_and_null_ctx_rejected():
+def test_batch_workspace_covers_the_embedded_class_and_null_ctx_rejected():
+    # orders up to 256 form one class of the largest order (here 130) holding
+    # all 6 k-points: its solve workspace plus the embedded H, S, C (16 B per
+    # entry each), eigenvalues, statuses and column map
     ps = [K.Problem(70, 70, 2), K.Problem(130, 130, 1), K.Problem(33, 40, 3)]
     arr = (K.Problem * 3)(*ps)
     got = K.lib.kgev_batch_workspace_bytes(arr, 3, None)
-    assert got == max(K.lib.kgev_workspace_bytes(p.n, p.nk, None) for p in ps) > 0
+    N, Kc = 130, 6
+    assert got >= K.lib.kgev_workspace_bytes(N, Kc, None) + 3 * 16 * N * N * Kc
+    assert got <= K.lib.kgev_workspace_bytes(N, Kc, None) + 3 * 16 * N * N * Kc + 16 * N * Kc + 7 * 256
+    # a class of one problem of its own order is solved in place
+    one = (K.Problem * 1)(K.Problem(130, 130, 2))
+    assert K.lib.kgev_batch_workspace_bytes(one, 1, None) == K.lib.kgev_workspace_bytes(130, 2, None)
     assert K.lib.kgev_batch_workspace_bytes(arr, 0, None) == 0
     assert K.lib.kgev_solve_batch_device(None, arr, 3, None, 0, None, None) == -1
 

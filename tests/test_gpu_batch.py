@@ -1,9 +1,14 @@
-"""Systems of uneven order in one call (kgev_solve_batch_device): every
-problem's eigenvalues and vectors are bitwise those of its own
-kgev_solve_k_device call with the same options, and match the oracle; the
-captured-graph form replays to the same results (with the program's own work
-and synchronisations between replays); bad descriptors and a short workspace
-are rejected."""
+"""Systems of uneven order in one call (kgev_solve_batch_device).  The
+problems are grouped into size classes; a class's pencils are embedded in
+pencils of the class order and solved by one batched solve, whose
+eigenpairs restricted to the pencil are exactly the pencil's (the padded
+blocks stay apart in exact zeros).  Checked: every problem against the
+oracle (eigenvalues within 1e-10 relative, residual and S-orthonormality
+<= 1e-12), a class of one problem of its own order bitwise equal to that
+problem's own kgev_solve_k_device call, run-to-run bitwise determinism,
+per-k statuses, the eigenvalues-only form, captured-graph replays (with
+the program's own work and synchronisations between replays), bad
+descriptors and a short workspace."""
 import numpy as np
 import pytest
 import torch
@@ -16,9 +21,9 @@ pytestmark = pytest.mark.gpu
 from paper_1402_4247_amd import inputs as G  # noqa: E402
 
 
-def systems():
+def systems(spec=((70, 2, 31), (130, 1, 32), (33, 3, 33), (1, 2, 34))):
     out = []
-    for n, nk, seed in [(70, 2, 31), (130, 1, 32), (33, 3, 33), (1, 2, 34)]:
+    for n, nk, seed in spec:
         Hs, Ss = G.config1_batch(n, nk, seed)
         out.append((n, nk, Hs, Ss))
     return out
@@ -30,31 +35,80 @@ def buffers(n, nk):
             torch.full((nk,), -9, dtype=torch.int32, device=DEV))
 
 
-def test_batch_equals_single_calls_and_oracle():
+def run_batch(ctx, sy, dev_in, opts=None, vectors=True):
     kg = K()
-    sy = systems()
+    outs, probs = [], []
+    for (n, nk, _, _), (dH, dS) in zip(sy, dev_in):
+        w, C, st = buffers(n, nk)
+        outs.append((w, C if vectors else None, st))
+        probs.append(kg.problem(dH, dS, n, n, nk, w, C if vectors else None, n if vectors else 0, st))
+    check(kg.solve_batch_device(ctx, probs, opts=opts), "batch")
+    torch.cuda.synchronize()
+    return outs
+
+
+def check_oracle(sy, outs, vectors=True):
+    for (n, nk, Hs, Ss), (w, C, st) in zip(sy, outs):
+        sth = st.cpu().numpy()
+        wh = w.cpu().numpy()
+        Ch = host(C) if vectors else None
+        for q in range(nk):
+            s0, w0, _ = O.solve_k(Hs[q], Ss[q], vectors=False)
+            assert sth[q] == s0, (n, q, sth[q], s0)
+            if s0 != 0:
+                continue
+            assert np.all(np.diff(wh[q]) >= 0)
+            assert np.abs(wh[q] - w0).max() <= 1e-10 * max(np.abs(w0).max(), 1e-300), (n, q)
+            if vectors:
+                r_res, r_orth = residuals(Hs[q], Ss[q], wh[q], Ch[q])
+                assert r_res <= 1e-12 and r_orth <= 1e-12, (n, q, r_res, r_orth)
+
+
+@pytest.mark.parametrize("spec", [
+    ((70, 2, 31), (130, 1, 32), (33, 3, 33), (1, 2, 34)),
+    ((1, 1, 41), (17, 2, 42), (64, 1, 43), (100, 2, 44), (128, 1, 45)),
+    ((300, 1, 51), (250, 2, 52), (130, 1, 53), (20, 3, 54)),
+], ids=["small", "orders-1-to-128", "two-classes"])
+def test_batch_matches_oracle(spec):
+    kg = K()
+    sy = systems(spec)
     dev_in = [(dev(Hs), dev(Ss)) for _, _, Hs, Ss in sy]
     with kg.Context(0) as ctx:
-        outs, probs = [], []
-        for (n, nk, _, _), (dH, dS) in zip(sy, dev_in):
-            w, C, st = buffers(n, nk)
-            outs.append((w, C, st))
-            probs.append(kg.problem(dH, dS, n, n, nk, w, C, n, st))
-        check(kg.solve_batch_device(ctx, probs), "batch")
+        outs = run_batch(ctx, sy, dev_in)
+        check_oracle(sy, outs)
+        again = run_batch(ctx, sy, dev_in)
+        for (w, C, st), (w2, C2, st2) in zip(outs, again):
+            assert torch.equal(w, w2) and torch.equal(C, C2) and torch.equal(st, st2)
+
+
+def test_batch_single_problem_class_is_the_plain_solve():
+    # 300 and 250 share a class (300 <= 1.26 x 250); 600 is a class of its own
+    kg = K()
+    sy = systems(((600, 1, 61), (300, 1, 62), (250, 1, 63)))
+    dev_in = [(dev(Hs), dev(Ss)) for _, _, Hs, Ss in sy]
+    with kg.Context(0) as ctx:
+        outs = run_batch(ctx, sy, dev_in)
+        n, nk, _, _ = sy[0]
+        w1, C1, st1 = buffers(n, nk)
+        check(kg.solve_k_device(ctx, dev_in[0][0], dev_in[0][1], n, n, nk, w1, C1, n, d_status=st1), "single")
         torch.cuda.synchronize()
-        for (n, nk, Hs, Ss), (dH, dS), (w, C, st) in zip(sy, dev_in, outs):
-            w1, C1, st1 = buffers(n, nk)
-            check(kg.solve_k_device(ctx, dH, dS, n, n, nk, w1, C1, n, d_status=st1), "single")
-            torch.cuda.synchronize()
-            assert torch.equal(w, w1) and torch.equal(C, C1) and torch.equal(st, st1)
-            assert bool((st == 0).all())
-            wh, Ch = w.cpu().numpy(), host(C)
-            for q in range(nk):
-                s0, w0, _ = O.solve_k(Hs[q], Ss[q])
-                assert s0 == 0
-                assert np.abs(wh[q] - w0).max() <= 1e-10 * max(np.abs(w0).max(), 1e-300)
-                r_res, r_orth = residuals(Hs[q], Ss[q], wh[q], Ch[q])
-                assert r_res <= 1e-12 and r_orth <= 1e-12
+        assert torch.equal(outs[0][0], w1) and torch.equal(outs[0][1], C1)
+        check_oracle(sy, outs)
+
+
+def test_batch_statuses_and_eigenvalues_only():
+    kg = K()
+    sy = systems(((90, 3, 71), (40, 2, 72), (7, 1, 73)))
+    n, nk, Hs, Ss = sy[0]
+    Ss = Ss.copy()
+    Ss[1] = -Ss[1]                         # k = 1 of the first problem: S not positive definite
+    sy[0] = (n, nk, Hs, Ss)
+    dev_in = [(dev(Hs), dev(Ss)) for _, _, Hs, Ss in sy]
+    with kg.Context(0) as ctx:
+        for vectors in (True, False):
+            outs = run_batch(ctx, sy, dev_in, opts=kg.make_opts(want_vectors=vectors), vectors=vectors)
+            assert outs[0][2].cpu().tolist() == [0, 1, 0]
+            check_oracle(sy, outs, vectors=vectors)
 
 
 def test_batch_graph_replays():
@@ -63,10 +117,9 @@ def test_batch_graph_replays():
     dev_in = [(dev(Hs), dev(Ss)) for _, _, Hs, Ss in sy]
     stream = torch.cuda.Stream()
     with kg.Context(0) as ctx:
+        eager = run_batch(ctx, sy, dev_in)
         ref, outs, probs = [], [], []
-        for (n, nk, _, _), (dH, dS) in zip(sy, dev_in):
-            w, C, st = buffers(n, nk)
-            check(kg.solve_k_device(ctx, dH, dS, n, n, nk, w, C, n, d_status=st), "single")
+        for (n, nk, _, _), (dH, dS), (w, C, _) in zip(sy, dev_in, eager):
             ref.append((w, C))
             w2, C2, st2 = buffers(n, nk)
             outs.append((w2, C2, st2))

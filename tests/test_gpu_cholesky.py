@@ -1,4 +1,5 @@
-"""The Cholesky form of Part 2 (opts.s_method = KGEV_S_CHOLESKY, X = L^{-H}):
+"""The Cholesky form of Part 2 (opts.s_method = KGEV_S_CHOLESKY, X = L^{-H} J,
+J the reversal of the column order):
 the same eigenpairs as the oracle's (paper's) form to the path's bar
 (eigenvalues within 1e-10 max|l|, residuals <= 1e-12, eigenvectors of
 non-degenerate eigenvalues equal up to phase), its definiteness status, and
@@ -70,3 +71,29 @@ def test_cholesky_form_with_mixed_precision():
         assert np.abs(w[k] - w0).max() <= 1e-10 * np.abs(w0).max()
         r_res, r_orth = residuals(Hs[k], Ss[k], w[k], C[k])
         assert r_res <= 1e-12 and r_orth <= 1e-12
+
+
+@pytest.mark.parametrize("n", [63, 130])
+def test_cholesky_x_matches_oracle_factor(n):
+    # the exported X is the oracle's L^{-H} (textbook Cholesky and forward
+    # substitution) with its columns in reverse order, entry by entry within
+    # the first-order error of a triangular inverse, c n eps |L^{-1}| |L| |L^{-1}|
+    kg = K()
+    nk = 2
+    Hs, Ss = G.config2(n, nk, 40 + n)
+    dH, dS = dev(Hs), dev(Ss)
+    dX = torch.zeros((nk, n, n), dtype=torch.complex128, device=DEV)
+    dw = torch.zeros((nk, n), dtype=torch.float64, device=DEV)
+    st = torch.full((nk,), -9, dtype=torch.int32, device=DEV)
+    with kg.Context(0) as ctx:
+        o = kg.make_opts(want_vectors=False, s_method=kg.S_CHOLESKY)
+        check(kg.solve_k_x_device(ctx, dH, dS, n, n, nk, dw, None, n, dX, kg.X_EXPORT, d_status=st, opts=o), "x")
+        torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    X = host(dX)
+    for k in range(nk):
+        s0, L, Li = O.cholesky_inv(Ss[k])
+        assert s0 == 0
+        Xo = Li.conj().T[:, ::-1]
+        bound = 8 * n * np.finfo(np.float64).eps * (np.abs(Li) @ np.abs(L) @ np.abs(Li)).conj().T[:, ::-1]
+        assert np.all(np.abs(X[k] - Xo) <= bound + 1e-300)

@@ -45,12 +45,23 @@ def test_mixed_matches_oracle(gen, n, nk):
 
 def test_refinement_sweeps_reduce_the_residual():
     Hs, Ss = G.config2(200, 1, 2002)
-    res = []
+    res, orth, sts = [], [], []
     for it in (1, 2, 3):
         w, C, st = solve(Hs, Ss, iters=it)
-        res.append(residuals(Hs[0], Ss[0], w[0], C[0])[0])
-    # one sweep from FP32 vectors is not enough, three reach FP64 accuracy
+        r_res, r_orth = residuals(Hs[0], Ss[0], w[0], C[0])
+        res.append(r_res)
+        orth.append(r_orth)
+        sts.append(int(st[0]))
+    # one sweep from FP32 vectors is not enough, three reach FP64 accuracy;
+    # the final check flags refined vectors that are visibly non-orthogonal
+    # (max |Y^H Y - I| > 1e-11, which C^H S C - I reproduces to rounding)
     assert res[0] > res[2] and res[2] <= 1e-12
+    assert sts[2] == 0
+    for o, s_ in zip(orth, sts):
+        if o > 2e-11:
+            assert s_ == 2, (orth, sts)
+        elif o < 5e-12:
+            assert s_ == 0, (orth, sts)
 
 
 def test_mixed_eigenvalues_only():

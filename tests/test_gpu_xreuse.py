@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from gpu_helpers import DEV, K, check, dev, host
 from paper_1402_4247_amd import inputs as G
 
@@ -65,7 +66,16 @@ def test_eigenvalue_pass_then_vector_pass():
         w1, _, _ = xsolve(ctx, dH, dS, n, nk, dX, kg.X_EXPORT, vectors=False)
         w2, C2, _ = xsolve(ctx, dH, None, n, nk, dX, kg.X_REUSE)
         torch.cuda.synchronize()
-    assert torch.equal(w1, wr) and torch.equal(w2, wr) and torch.equal(C2, Cr)
+    # the vector pass with the exported X is bitwise the plain solve; the
+    # eigenvalue pass finds the eigenvalues of the same tridiagonal matrices
+    # by bisection instead of divide and conquer, so it agrees to rounding
+    assert torch.equal(w2, wr) and torch.equal(C2, Cr)
+    wr_h, w1_h = wr.cpu().numpy(), w1.cpu().numpy()
+    for k in range(nk):
+        scale = np.abs(wr_h[k]).max()
+        assert np.abs(w1_h[k] - wr_h[k]).max() <= 8 * n * np.finfo(np.float64).eps * scale
+        s0, w0, _ = O.solve_k(Hs[k], Ss[k], vectors=False)
+        assert s0 == 0 and np.abs(w1_h[k] - w0).max() <= 1e-10 * np.abs(w0).max()
 
 
 def test_argument_errors():
