@@ -69,12 +69,19 @@ def log(*a):
 def zhemv_source_sha256():
     """SHA-256 of the Hermitian-product kernel's own source text (the
     hetrd_zhemv template in hetrd.hip, from its template line to its closing
-    brace) followed by common.hpp, whose helpers it uses."""
+    brace) followed by common.hpp, whose helpers it uses; None if the kernel
+    is not found."""
     import hashlib
     with open(os.path.join(CSRC, "hetrd.hip")) as fh:
         text = fh.read()
-    i0 = text.index("template <typename R, bool BUF>\n__global__ __launch_bounds__(256, 3) void hetrd_zhemv(")
-    i1 = text.index("\n}\n", i0) + 3
+    k = text.find(" void hetrd_zhemv(")
+    if k < 0:
+        return None
+    i0 = text.rfind("template <", 0, k)
+    i1 = text.find("\n}\n", k)
+    if i0 < 0 or i1 < 0:
+        return None
+    i1 += 3
     h = hashlib.sha256(text[i0:i1].encode())
     with open(os.path.join(CSRC, "common.hpp"), "rb") as fh:
         h.update(fh.read())

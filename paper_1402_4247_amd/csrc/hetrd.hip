@@ -40,17 +40,23 @@ constexpr int ZT = 64;          // ZHEMV tile edge
 constexpr int ZCH = 4;          // tiles per ZHEMV chunk: one per wave of the workgroup
 constexpr int RB = 64;          // rows per workgroup in the column kernels
 
+// chunks of block column C in the four-tile form, and in the form a
+// reduction uses (ws.zch: 4 tiles per chunk, or 1 for the one-tile form)
 __device__ __host__ inline int nchunks(int NB, int C) { return (NB - C + ZCH - 1) / ZCH; }
+__device__ __host__ inline int nchunks_z(int NB, int C, int zch) { return zch == 1 ? NB - C : (NB - C + 3) >> 2; }
 
 // Reflector from the partial norms: returns tau and the scale applied to x.
+// Called by whole waves: the partial norms are summed across the lanes (the
+// same tree in every wave, so every wave holds the same bits).
 template <typename R>
 __device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& tau, cx<R>& scale, R& beta)
 {
     const int n = ws.n;
     const int np = (n - i + RB - 1) / RB;
     const R* pn = ws.pnorm + b * ws.s_pnorm + (i & 1) * ((n + RB - 1) / RB);
-    R sig2 = 0;
-    for (int q = 0; q < np; ++q) sig2 += pn[q];
+    R part = 0;
+    for (int q = (int)(threadIdx.x & 63); q < np; q += 64) part += pn[q];
+    const R sig2 = wave_sum(part);
     const cx<R> alpha = ws.A[b * ws.sA + (int64_t)(i + 1) + (int64_t)i * ws.lda];
     if (sig2 == (R)0 && alpha.y == (R)0) {
         tau = czero<cx<R>>();
@@ -262,6 +268,124 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
     }
 }
 
+// The same product in one-tile chunks, for launches where the four-tile form
+// would give fewer workgroups than three per CU (few k-points): the four
+// waves share one tile, wave w taking column groups 2w and 2w + 1; their
+// direct parts are added in LDS, and each column's sum comes from the one
+// wave that owns it.  Same partial-sum layout with one chunk per tile.
+template <typename R, bool BUF>
+__global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i, int rev)
+{
+    __shared__ cx<R> svC[ZT];
+    __shared__ cx<R> sT[ZCH][ZT];
+    __shared__ cx<R> sP[ZCH][8][ZT + 1];
+    const int64_t b = rev ? (int64_t)(gridDim.y - 1 - blockIdx.y) : (int64_t)blockIdx.y;
+    const int lid = rev ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    const int n = ws.n;
+    const int o = i + 1;
+    const int m = n - o;
+    const int NB = (m + ZT - 1) / ZT;
+    // which tile (Rb, C) of the lower triangle is ours: tiles enumerated down
+    // each block column
+    int bid = lid, C = 0;
+    for (; C < NB; ++C) {
+        const int nc = NB - C;
+        if (bid < nc) break;
+        bid -= nc;
+    }
+    if (C >= NB) return;
+    const int ch = bid;
+    const int Rb = C + ch;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const cx<R>* A = ws.A + b * ws.sA;
+    const cx<R>* Ai = A + (int64_t)i * ws.lda;
+    const int64_t lda = ws.lda;
+    const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
+    const bool row_ok = gr < n;
+    const int rowc = row_ok ? (int)gr : n - 1;
+    const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
+    const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
+    auto load_group = [&](int g, cx<R> (&a)[8]) {
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int64_t gc = gcb + g * 8 + cc;
+            const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
+            if constexpr (BUF) {
+                const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
+                if constexpr (sizeof(R) == 8) {
+                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    a[cc] = __builtin_bit_cast(cx<R>, v);
+                } else {
+                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
+                    a[cc] = __builtin_bit_cast(cx<R>, v);
+                }
+            } else {
+                a[cc] = A[gcc * lda + rowc];
+            }
+        }
+    };
+    const int g0 = 2 * w, g1 = 2 * w + 2;
+    cx<R> a[8];
+    load_group(g0, a);
+    sT[w][lane] = czero<cx<R>>();      // the other waves' columns add zero
+    if (tid < ZT) {
+        const int64_t gc = gcb + tid;
+        const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
+        svC[tid] = csel(gc > o && gc < n, u, czero<cx<R>>());
+    }
+    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
+    if (!(row_ok && gr > o)) uR = czero<cx<R>>();
+    __syncthreads();
+
+    __shared__ R sq[ZCH];
+    const bool diag_tile = (Rb == C);
+    cx<R> yd = czero<cx<R>>();
+#pragma unroll 1
+    for (int g = g0; g < g1; ++g) {
+        const int64_t gc0 = gcb + g * 8;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int64_t gc = gc0 + cc;
+            const bool ok = row_ok && gc < n && (!diag_tile || gr >= gc);
+            const bool diag = diag_tile && (gr == gc);
+            cx<R> x;
+            x.x = ok ? a[cc].x : (R)0;
+            x.y = (ok && !diag) ? a[cc].y : (R)0;
+            yd = cfma(x, svC[g * 8 + cc], yd);
+            a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
+        }
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
+        if (g + 1 < g1) load_group(g + 1, a);
+        __builtin_amdgcn_wave_barrier();
+        const int c = lane & 7, r0 = (lane >> 3) * 8;
+        cx<R> cs = czero<cx<R>>();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
+        cs = xor_add<8, R>(cs);
+        cs = xor_add<16, R>(cs);
+        cs = xor_add<32, R>(cs);
+        if (lane < 8) sT[w][g * 8 + lane] = cs;
+        __builtin_amdgcn_wave_barrier();
+    }
+    // the four waves' shares of the tile's direct part
+    sP[w][0][lane] = yd;
+    R qd = uR.x * yd.x + uR.y * yd.y;
+    qd = wave_sum(qd);
+    if (lane == 0) sq[w] = qd;
+    __syncthreads();
+    if (w == 0) {
+        const cx<R> ys = cadd(cadd(sP[0][0][lane], sP[1][0][lane]), cadd(sP[2][0][lane], sP[3][0][lane]));
+        ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = ys;
+        const cx<R> s = cadd(cadd(sT[0][lane], sT[1][lane]), cadd(sT[2][lane], sT[3][lane]));
+        ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + lane] = s;
+        R qt = svC[lane].x * s.x + svC[lane].y * s.y;
+        qt = wave_sum(qt);
+        if (lane == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // z at one row: the partial sums over the block columns and chunks that
 // touch it, split over the four waves (wave w takes the terms with index =
@@ -271,13 +395,25 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
 template <typename R>
 __device__ inline cx<R> zpart(const HetrdWs<R>& ws, int64_t b, int Rb, int NB, int r, int w)
 {
-    cx<R> y = czero<cx<R>>();
+    // two running sums (terms w, w + 8, ... and w + 4, w + 12, ...) so that
+    // consecutive loads do not wait on each other
+    cx<R> y0 = czero<cx<R>>(), y1 = czero<cx<R>>();
     const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + r;
-    for (int C = w; C <= Rb; C += 4) y = cadd(y, yp[(int64_t)C * ZT]);
-    const int nc = nchunks(NB, Rb);
+    int C = w;
+    for (; C + 4 <= Rb; C += 8) {
+        y0 = cadd(y0, yp[(int64_t)C * ZT]);
+        y1 = cadd(y1, yp[(int64_t)(C + 4) * ZT]);
+    }
+    if (C <= Rb) y0 = cadd(y0, yp[(int64_t)C * ZT]);
+    const int nc = nchunks_z(NB, Rb, ws.zch);
     const cx<R>* yq = ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT + r;
-    for (int ch = w; ch < nc; ch += 4) y = cadd(y, yq[(int64_t)ch * ZT]);
-    return y;
+    int ch = w;
+    for (; ch + 4 < nc; ch += 8) {
+        y0 = cadd(y0, yq[(int64_t)ch * ZT]);
+        y1 = cadd(y1, yq[(int64_t)(ch + 4) * ZT]);
+    }
+    if (ch < nc) y0 = cadd(y0, yq[(int64_t)ch * ZT]);
+    return cadd(y0, y1);
 }
 
 template <typename C>
@@ -294,7 +430,7 @@ __device__ inline C sum4(const C (&s)[4][64], int l)
 // up to 32 wide are held in registers, wider ones reload the rest), which
 // then serve the corrections, the column update and the panel dots.
 template <typename R>
-__global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p, int update_next)
+__global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p, int update_next, int nch)
 {
     __shared__ cx<R> s1[4][64], s2[4][64], sy[4][64];
     __shared__ cx<R> swv[64], svv[64];        // W^H v, V^H v (zero beyond j)
@@ -353,9 +489,7 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     sy[w][lane] = zpart(ws, b, Rb, NB, lane, w);
     if (lane == 0) szo[w] = zpart(ws, b, 0, NB, 0, w);
     {
-        // q = Re(u^H A22 u) from the chunk shares
-        int nch = 0;
-        for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
+        // q = Re(u^H A22 u) from the shares of the nch chunks of the product
         R qa = 0;
         for (int c = tid; c < nch; c += 256) qa += ws.qpart[b * ws.s_qpart + c];
         qa = wave_sum(qa);
@@ -730,10 +864,24 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
 int hetrd_pn(int64_t n) { return (int)((n + RB - 1) / RB); }
 
 template <typename R>
-hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
+hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws0, int64_t nk)
 {
-    const int n = ws.n, nb = ws.nb;
+    const int n = ws0.n, nb = ws0.nb;
     if (n < 1 || nk < 1) return hipSuccess;
+    // The split form (one tile per workgroup) when the wide form's first
+    // Hermitian product would launch fewer workgroups than three per CU; the
+    // choice holds for the whole reduction, so every product and update
+    // kernel agrees on the chunk layout of the partial sums.
+    HetrdWs<R> ws = ws0;
+    {
+        const int NB0 = (n - 1 + ZT - 1) / ZT;
+        int64_t nch4 = 0;
+        for (int C = 0; C < NB0; ++C) nch4 += nchunks(NB0, C);
+        ws.zch = nch4 * nk < 3 * 256 ? 1 : ZCH;
+        // chunks per block column in the partial-sum layout (the buffers hold
+        // the one-tile form's NBmax)
+        ws.CHmax = ws.zch == 1 ? ws0.NBmax : (ws0.NBmax + ZCH - 1) / ZCH;
+    }
     // Buffer offsets are 32-bit: a matrix (ld x n) of 2 GiB or more is read
     // with plain global loads instead.
     const bool buf = (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
@@ -749,7 +897,7 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int o = i + 1, m = n - o;
             const int NB = (m + ZT - 1) / ZT;
             int nch = 0;
-            for (int C = 0; C < NB; ++C) nch += nchunks(NB, C);
+            for (int C = 0; C < NB; ++C) nch += nchunks_z(NB, C, ws.zch);
             // Consecutive columns traverse their tiles in opposite orders (odd
             // columns from the last k-point's last chunk back), so each launch
             // starts on the tiles its predecessor read last, which the 256 MB
@@ -758,14 +906,21 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws, int64_t nk)
             const int rev = i & 1;
             const ProfLaunch pl = prof_launch_begin(PH_HEMV, st);
             const dim3 gz((unsigned)nch, (unsigned)nk);
-            if (buf)
-                launch_timed(pl, hetrd_zhemv<R, true>, gz, dim3(256), st, ws, i, rev);
-            else
-                launch_timed(pl, hetrd_zhemv<R, false>, gz, dim3(256), st, ws, i, rev);
+            if (ws.zch == 1) {
+                if (buf)
+                    launch_timed(pl, hetrd_zhemv_tile<R, true>, gz, dim3(256), st, ws, i, rev);
+                else
+                    launch_timed(pl, hetrd_zhemv_tile<R, false>, gz, dim3(256), st, ws, i, rev);
+            } else {
+                if (buf)
+                    launch_timed(pl, hetrd_zhemv<R, true>, gz, dim3(256), st, ws, i, rev);
+                else
+                    launch_timed(pl, hetrd_zhemv<R, false>, gz, dim3(256), st, ws, i, rev);
+            }
             prof_launch_end(PH_HEMV, st, pl,
                             (double)sizeof(cx<R>) * 0.5 * (double)m * (double)(m + 1) * (double)nk, 0.0);
             const int upd = (i + 1 < p + nb) && (o <= n - 1);
-            hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd);
+            hipLaunchKernelGGL(hetrd_update<R>, dim3((unsigned)NB, (unsigned)nk), dim3(256), 0, st, ws, i, p, upd, nch);
         }
         if (p + nb <= n - 1) {
             const int t0 = p + nb;

@@ -62,6 +62,7 @@ template <typename R>
 struct HetrdWs {
     int n, nb;
     int NBmax, CHmax;          // 64-row blocks of the largest trailing matrix; chunks per block column
+    int zch;                   // tiles per chunk of the Hermitian product (set by hetrd: 4, or 1)
     cx<R>* A; int64_t lda, sA; // matrix (lower), reduced in place
     cx<R>* V; int64_t sV;      // reflectors, n x n, ld n (zero outside the reflector rows)
     cx<R>* W; int64_t sW;      // panel W, n x nb, ld n
@@ -77,7 +78,7 @@ struct HetrdWs {
 };
 
 inline int hetrd_nbmax(int64_t n) { return (int)((n - 1 + 63) / 64) > 0 ? (int)((n - 1 + 63) / 64) : 1; }
-inline int hetrd_chmax(int64_t n) { return (hetrd_nbmax(n) + 3) / 4; }
+inline int hetrd_chmax(int64_t n) { return hetrd_nbmax(n); }   // room for one-tile chunks
 int hetrd_pn(int64_t n);   // partial norms per column (one per 64-row block)
 
 template <typename R>
