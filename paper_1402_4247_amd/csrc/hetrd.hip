@@ -868,20 +868,7 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws0, int64_t nk)
 {
     const int n = ws0.n, nb = ws0.nb;
     if (n < 1 || nk < 1) return hipSuccess;
-    // The split form (one tile per workgroup) when the wide form's first
-    // Hermitian product would launch fewer workgroups than three per CU; the
-    // choice holds for the whole reduction, so every product and update
-    // kernel agrees on the chunk layout of the partial sums.
     HetrdWs<R> ws = ws0;
-    {
-        const int NB0 = (n - 1 + ZT - 1) / ZT;
-        int64_t nch4 = 0;
-        for (int C = 0; C < NB0; ++C) nch4 += nchunks(NB0, C);
-        ws.zch = nch4 * nk < 3 * 256 ? 1 : ZCH;
-        // chunks per block column in the partial-sum layout (the buffers hold
-        // the one-tile form's NBmax)
-        ws.CHmax = ws.zch == 1 ? ws0.NBmax : (ws0.NBmax + ZCH - 1) / ZCH;
-    }
     // Buffer offsets are 32-bit: a matrix (ld x n) of 2 GiB or more is read
     // with plain global loads instead.
     const bool buf = (double)sizeof(cx<R>) * (double)ws.lda * (double)n < 2147483648.0;
@@ -896,8 +883,16 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws0, int64_t nk)
         for (int i = p; i < iend; ++i) {
             const int o = i + 1, m = n - o;
             const int NB = (m + ZT - 1) / ZT;
-            int nch = 0;
-            for (int C = 0; C < NB; ++C) nch += nchunks_z(NB, C, ws.zch);
+            // The one-tile form when the four-tile form would launch fewer
+            // workgroups than three per CU (its chains of loads are a quarter
+            // as long); the product and the update of a column agree on the
+            // chunk layout of the partial sums through ws.zch and ws.CHmax
+            // (the buffers hold the one-tile form's NBmax chunks per column).
+            int nch4 = 0;
+            for (int C = 0; C < NB; ++C) nch4 += nchunks(NB, C);
+            ws.zch = (int64_t)nch4 * nk < 3 * 256 ? 1 : ZCH;
+            ws.CHmax = ws.zch == 1 ? ws0.NBmax : (ws0.NBmax + ZCH - 1) / ZCH;
+            const int nch = ws.zch == 1 ? NB * (NB + 1) / 2 : nch4;
             // Consecutive columns traverse their tiles in opposite orders (odd
             // columns from the last k-point's last chunk back), so each launch
             // starts on the tiles its predecessor read last, which the 256 MB
