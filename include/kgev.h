@@ -350,8 +350,9 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
  * (Band_DFT_Col Parts 2-4, Section III) on its own HIP stream, so requests
  * admitted while others run overlap with them on the device.  Admission is in
  * arrival order; a request is admitted when a slot is free and its workspace
- * footprint (kgev_workspace_bytes + status words) fits the remaining budget.
- * Inputs and outputs stay device-resident: the caller keeps dH, dS, dw and dC
+ * footprint (kgev_workspace_bytes + status words) fits the remaining budget;
+ * the caller's own dH, dS, dw and dC are not counted, since they are allocated
+ * before the request is submitted.  Inputs and outputs stay device-resident: the caller keeps dH, dS, dw and dC
  * (as in kgev_solve_k_device) alive and untouched until kgev_server_wait
  * returns for the request.  The server owns only workspaces, streams and its
  * worker thread; all entry points are thread-safe.

@@ -9,6 +9,7 @@
 //           triangles), as one batched MFMA product per matrix plus a
 //           fixed-order sum over k-points.
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 #include "../../include/kgev.h"
 
@@ -33,7 +34,7 @@ __device__ inline double fermi_dirac(double x, double mu, double kT)
 // gets the result
 __device__ inline double block_sum(double v, double* sh)
 {
-    v = wave_sum(v);
+    v = dpp_wave_sum(v);
     const int w = threadIdx.x / WAVE;
     __syncthreads();
     if ((threadIdx.x & (WAVE - 1)) == 0) sh[w] = v;
@@ -46,7 +47,7 @@ __device__ inline double block_sum(double v, double* sh)
 
 __device__ inline double block_min(double v, double* sh)
 {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+    v = dpp_wave_min(v);
     const int w = threadIdx.x / WAVE;
     __syncthreads();
     if ((threadIdx.x & (WAVE - 1)) == 0) sh[w] = v;

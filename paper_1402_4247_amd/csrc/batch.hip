@@ -24,6 +24,7 @@
 // Descriptors travel by value in the kernel arguments (so a captured graph
 // holds them), at most BATCH_DESC problems per launch.
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchDescs ds, int mode, dou
     double v = mode == 0 ? -1.0e308 : 0.0;
     if (mode == 0) {
         for (int64_t i = threadIdx.x; i < n; i += 256) v = fmax(v, S[i + i * ld].x);
-        v = wave_max(v);
+        v = dpp_wave_max(v);
     } else {
         for (int64_t c = 0; c < n; ++c)
             for (int64_t r = c + threadIdx.x; r < n; r += 256) {
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchDescs ds, int mode, dou
                 const double a = r == c ? x.x * x.x : 2.0 * (x.x * x.x + x.y * x.y);
                 v += a;
             }
-        v = wave_sum(v);
+        v = dpp_wave_sum(v);
     }
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();

@@ -19,6 +19,7 @@
 // within 2 eps of zero is zero.  Every step is a fixed sequence of IEEE
 // operations, so the results are reproducible bit for bit.
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void stebz_prep(const double* __restrict__ d, 
         mx = fmax(mx, fabs(db[i]));
         if (i + 1 < n) mx = fmax(mx, fabs(eb[i]));
     }
-    mx = wave_max(mx);
+    mx = dpp_wave_max(mx);
     if ((tid & 63) == 0) sh[0][w] = mx;
     __syncthreads();
     double s = fmax(fmax(sh[0][0], sh[0][1]), fmax(sh[0][2], sh[0][3]));
@@ -63,9 +64,9 @@ __global__ __launch_bounds__(256) void stebz_prep(const double* __restrict__ d, 
         hi = fmax(hi, di + el + er);
         e2 = fmax(e2, er * er);
     }
-    lo = -wave_max(-lo);
-    hi = wave_max(hi);
-    e2 = wave_max(e2);
+    lo = -dpp_wave_max(-lo);
+    hi = dpp_wave_max(hi);
+    e2 = dpp_wave_max(e2);
     __syncthreads();
     if ((tid & 63) == 0) {
         sh[1][w] = lo;
@@ -135,15 +136,10 @@ __global__ __launch_bounds__(256) void stebz_bisect(const double* __restrict__ d
         if (q == 1) x = mid;                       // the midpoint exactly
         x = fmin(fmax(x, lo), hi);
         const int c = q < 3 ? sturm_count(db, eb, n, inv, x, p.pivmin) : 0;
-        // gather the group's three points and counts
-        const int base = (threadIdx.x & 63) & ~(LANES - 1);
-        double xs[3];
-        int cs[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            xs[k] = __shfl(x, base + k, WAVE);
-            cs[k] = __shfl(c, base + k, WAVE);
-        }
+        // gather the group's three points and counts (quad_perm broadcasts of
+        // lanes 0, 1, 2 of the quad)
+        const double xs[3] = {quad_bcast<0>(x), quad_bcast<1>(x), quad_bcast<2>(x)};
+        const int cs[3] = {quad_bcast<0>(c), quad_bcast<1>(c), quad_bcast<2>(c)};
         double nlo = lo, nhi = hi;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {

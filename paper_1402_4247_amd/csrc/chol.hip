@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_smax(int64_t n, const double2* A, int64
     const int64_t b = blockIdx.x;
     double m = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, A[b * sA + i + i * lda].x);
-    m = wave_max(m);
+    m = dpp_wave_max(m);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) smax[b] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
@@ -94,10 +95,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int j0, const double2*
         double2 s = mk<double>(0, 0);
         if (cc <= r && cc < bs)
             for (int k = cc + part; k < r; k += 4) s = cfma(a[k][r], v[cc][k], s);
-        s.x += __shfl_xor(s.x, 1, WAVE);
-        s.y += __shfl_xor(s.y, 1, WAVE);
-        s.x += __shfl_xor(s.x, 2, WAVE);
-        s.y += __shfl_xor(s.y, 2, WAVE);
+        s.x = dpp_sum<4>(s.x);
+        s.y = dpp_sum<4>(s.y);
         if (part == 0 && cc <= r && cc < bs) {
             const double2 dl = mk<double>(r == cc ? 1.0 : 0.0, 0.0);
             v[cc][r] = cscale(csub(dl, s), 1.0 / a[r][r].x);

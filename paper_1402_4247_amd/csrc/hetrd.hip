@@ -30,6 +30,7 @@
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible run to run.
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -56,7 +57,7 @@ __device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& 
     const R* pn = ws.pnorm + b * ws.s_pnorm + (i & 1) * ((n + RB - 1) / RB);
     R part = 0;
     for (int q = (int)(threadIdx.x & 63); q < np; q += 64) part += pn[q];
-    const R sig2 = wave_sum(part);
+    const R sig2 = dpp_wave_sum(part);
     const cx<R> alpha = ws.A[b * ws.sA + (int64_t)(i + 1) + (int64_t)i * ws.lda];
     if (sig2 == (R)0 && alpha.y == (R)0) {
         tau = czero<cx<R>>();
@@ -84,17 +85,26 @@ __device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV],
         const cx<R> send = csel(up, t[q], t[q + HALF]);
         const cx<R> keep = csel(up, t[q + HALF], t[q]);
         cx<R> rcv;
-        rcv.x = __shfl_xor(send.x, MASK, WAVE);
-        rcv.y = __shfl_xor(send.y, MASK, WAVE);
+        rcv.x = lane_xor<MASK>(send.x);
+        rcv.y = lane_xor<MASK>(send.y);
         t[q] = cadd(keep, rcv);
     }
 }
 
+// r + r(lane ^ MASK): through the LDS unit (the Hermitian-product kernel's
+// column sums), and as vector-ALU lane exchanges (everywhere else)
 template <int MASK, typename R>
 __device__ __attribute__((always_inline)) inline cx<R> xor_add(cx<R> r)
 {
     r.x += __shfl_xor(r.x, MASK, WAVE);
     r.y += __shfl_xor(r.y, MASK, WAVE);
+    return r;
+}
+template <int MASK, typename R>
+__device__ __attribute__((always_inline)) inline cx<R> xor_add_v(cx<R> r)
+{
+    r.x += lane_xor<MASK>(r.x);
+    r.y += lane_xor<MASK>(r.y);
     return r;
 }
 
@@ -108,9 +118,9 @@ __device__ __attribute__((always_inline)) inline cx<R> transpose_sum8(cx<R> (&t)
     halve_step<16, 2, 8, R>(t, (lane & 16) != 0);
     halve_step<8, 1, 8, R>(t, (lane & 8) != 0);
     cx<R> r = t[0];
-    r = xor_add<4, R>(r);
-    r = xor_add<2, R>(r);
-    r = xor_add<1, R>(r);
+    r = xor_add_v<4, R>(r);
+    r = xor_add_v<2, R>(r);
+    r = xor_add_v<1, R>(r);
     return r;
 }
 
@@ -127,7 +137,7 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
         if (r == c) ws.d[b * ws.n + c] = a.x;
         if (r >= c + 2) acc = a.x * a.x + a.y * a.y;
     }
-    acc = wave_sum(acc);
+    acc = dpp_wave_sum(acc);
     if (threadIdx.x == 0) ws.pnorm[b * ws.s_pnorm + (c & 1) * ((ws.n + RB - 1) / RB) + blockIdx.x] = acc;
 }
 
@@ -363,16 +373,16 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
         cx<R> cs = czero<cx<R>>();
 #pragma unroll
         for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
-        cs = xor_add<8, R>(cs);
-        cs = xor_add<16, R>(cs);
-        cs = xor_add<32, R>(cs);
+        cs = xor_add_v<8, R>(cs);
+        cs = xor_add_v<16, R>(cs);
+        cs = xor_add_v<32, R>(cs);
         if (lane < 8) sT[w][g * 8 + lane] = cs;
         __builtin_amdgcn_wave_barrier();
     }
     // the four waves' shares of the tile's direct part
     sP[w][0][lane] = yd;
     R qd = uR.x * yd.x + uR.y * yd.y;
-    qd = wave_sum(qd);
+    qd = dpp_wave_sum(qd);
     if (lane == 0) sq[w] = qd;
     __syncthreads();
     if (w == 0) {
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
         const cx<R> s = cadd(cadd(sT[0][lane], sT[1][lane]), cadd(sT[2][lane], sT[3][lane]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + lane] = s;
         R qt = svC[lane].x * s.x + svC[lane].y * s.y;
-        qt = wave_sum(qt);
+        qt = dpp_wave_sum(qt);
         if (lane == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
 }
@@ -492,7 +502,7 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
         // q = Re(u^H A22 u) from the shares of the nch chunks of the product
         R qa = 0;
         for (int c = tid; c < nch; c += 256) qa += ws.qpart[b * ws.s_qpart + c];
-        qa = wave_sum(qa);
+        qa = dpp_wave_sum(qa);
         if (lane == 0) sqq[w] = qa;
     }
     cx<R> tau, scale;
@@ -525,9 +535,9 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     if (w == 0) {
         cx<R> co = cfma(sVo[lane], swv[lane], cmul(sWo[lane], svv[lane]));
         R cross = svv[lane].x * swv[lane].x + svv[lane].y * swv[lane].y;   // Re(conj(V^H v) W^H v)
-        co.x = wave_sum(co.x);
-        co.y = wave_sum(co.y);
-        cross = wave_sum(cross);
+        co.x = dpp_wave_sum(co.x);
+        co.y = dpp_wave_sum(co.y);
+        cross = dpp_wave_sum(cross);
         if (lane == 0) {
             const cx<R> zo = cadd(cadd(szo[0], szo[1]), cadd(szo[2], szo[3]));
             const R q = (sqq[0] + sqq[1]) + (sqq[2] + sqq[3]);
@@ -624,7 +634,7 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
                 an = a;
             }
         }
-        nrm = wave_sum(nrm);
+        nrm = dpp_wave_sum(nrm);
         if (lane == 0) ws.pnorm[b * ws.s_pnorm + (o & 1) * npn + Rb] = nrm;
         s1[0][lane] = an;
     }
@@ -674,189 +684,189 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
 }
 
 // ---------------------------------------------------------------------------
-// The last columns, once the trailing matrix has at most TAIL_M = 128 rows:
-// one workgroup of 512 threads per problem holds the whole trailing matrix
-// (both triangles) in registers.  The threads form 32 groups of 16 lanes
-// (a quarter of a wave each; group g in wave g mod 8, so the columns left
-// behind by the reduction are spread evenly over the waves); group g owns
-// columns 4g .. 4g + 3 whole, lane l of a group rows 8l .. 8l + 7 of them.
-// Groups whose columns all lie left of the trailing matrix skip their work.
-// Per column c, unblocked, with the same reflector convention as the blocked
-// columns:
-//   the group owning column c forms the reflector (Procedure 2) from its
-//   column with a group sum and publishes v (Procedure 3) in LDS;
-//   y = tau A22 v (Procedure 4) as y_s = sum_r conj(A(r, s)) v_r, which is
-//   (A22 v)_s for the Hermitian A22: a sum down each column, inside the
-//   group that owns it;
-//   w = y - (tau / 2)(y^H v) v (Procedure 5) from per-group partial dots;
-//   A22 -= v w^H + w v^H (Procedure 6) on the registers.
-// Two barriers per column: v, y and the partial dots alternate between two
-// LDS buffers by the parity of the column.  Every sum runs in a fixed order
-// (bitwise reproducible).  Rows and columns beyond the trailing order are
-// zero and stay zero.
+// The last columns, once the trailing matrix has at most TAIL_M rows: one
+// workgroup per problem holds its lower triangle in LDS (packed by rows,
+// element (r, s), r >= s, at r (r + 1) / 2 + s) and reduces it column by
+// column, unblocked: Procedure 2's reflector from the column's norm,
+// y = tau A22 v (Procedure 4), w = y - (tau / 2)(y^H v) v (Procedure 5) and
+// A22 -= v w^H + w v^H (Procedure 6), with the same reflector convention as
+// the blocked columns.  Sums are taken in a fixed order (bitwise
+// reproducible).  It replaces two launches per column, whose fixed cost
+// dominates at this size, by one launch for all of them.
+//
+// The kernel is bound by the latency of its dependent steps, so each column
+// takes five barrier phases: (A) reflector, (B) v, (C) y with the partial
+// sums of y^H v, (D) w, (E) the rank-2 update with the partial squared norms
+// of the next column (rows two and more below its diagonal).  Eight threads
+// share a row in (C) and (E) and take its entries in groups of four, so one
+// LDS round trip serves four of them.
 constexpr int TAIL_M = 128;
-constexpr int TAIL_T = 512;
-constexpr int TAIL_G = 16;                   // lanes per column group
-constexpr int TAIL_RL = TAIL_M / TAIL_G;     // rows per lane
-constexpr int TAIL_NG = TAIL_T / TAIL_G;     // column groups
-static_assert(TAIL_NG * 4 == TAIL_M, "four columns per group");
-
-template <typename R, int N>
-__device__ __attribute__((always_inline)) inline cx<R> pickn(const cx<R> (&x)[N], int q)
-{
-    cx<R> r = x[N - 1];
-#pragma unroll
-    for (int k = N - 2; k >= 0; --k) r = csel(q == k, x[k], r);
-    return r;
-}
+constexpr int TAIL_T = 1024;
+constexpr int TAIL_W = TAIL_T / 64;
+static_assert(TAIL_T / 8 >= TAIL_M, "eight threads per row of the tail's trailing matrix");
 
 template <typename R>
 __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
 {
-    __shared__ cx<R> sv[2][TAIL_M], sy[2][TAIL_M];
-    __shared__ cx<R> sdp[2][TAIL_NG];
-    __shared__ cx<R> stau[2];
+    __shared__ cx<R> P[TAIL_M * (TAIL_M + 1) / 2];
+    __shared__ cx<R> sv[TAIL_M], sy[TAIL_M], sw[TAIL_M];
+    __shared__ R red[TAIL_W];
+    __shared__ cx<R> sred[TAIL_W];
+    __shared__ cx<R> sref[2];       // tau, scale
     const int64_t b = blockIdx.x;
-    const int n = ws.n, M = n - i0, tid = threadIdx.x;
-    const int l = tid % TAIL_G, lane = tid & 63;
-    const int g = (tid >> 6) + (TAIL_T / 64) * ((tid >> 4) & 3);     // wave + 8 x quarter
-    const int r0 = TAIL_RL * l, s0 = 4 * g;
+    const int n = ws.n, M = n - i0, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = tid >> 3, q = tid & 7;      // row share of phases C and E
     const cx<R>* A = ws.A + b * ws.sA;
-    const int64_t lda = ws.lda;
     cx<R>* V = ws.V + b * ws.sV;
     const cx<R> zero = czero<cx<R>>();
-    // a[q][p] = A(r0 + q, s0 + p) of the trailing matrix, the upper triangle
-    // from the stored lower one
-    cx<R> a[TAIL_RL][4];
-#pragma unroll
-    for (int q = 0; q < TAIL_RL; ++q)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int r = r0 + q, c = s0 + p;
-            cx<R> x = zero;
-            if (r < M && c < M) {
-                x = r >= c ? A[(int64_t)(i0 + r) + (int64_t)(i0 + c) * lda]
-                           : cconj(A[(int64_t)(i0 + c) + (int64_t)(i0 + r) * lda]);
-                if (r == c) x.y = (R)0;
-            }
-            a[q][p] = x;
+    for (int e = tid; e < M * M; e += TAIL_T) {
+        const int rr = e % M, c = e / M;
+        if (rr >= c) P[rr * (rr + 1) / 2 + c] = A[(int64_t)(i0 + rr) + (int64_t)(i0 + c) * ws.lda];
+    }
+    __syncthreads();
+    {
+        // squared norm of rows 2.. of column 0
+        R part = 0;
+        if (tid >= 2 && tid < M) {
+            const cx<R> x = P[tid * (tid + 1) / 2];
+            part = x.x * x.x + x.y * x.y;
         }
+        part = dpp_wave_sum(part);
+        if (lane == 0) red[wv] = part;
+    }
+    __syncthreads();
     for (int c = 0; c + 1 < M; ++c) {
-        const int par = c & 1;
-        const int i = i0 + c;
-        if (g == (c >> 2)) {
-            // Procedure 2 on column c (rows of this lane: r0 .. r0 + 7)
-            const int cc = c & 3;
-            cx<R> x[TAIL_RL];
+        const int i = i0 + c, mm = M - c - 1;     // trailing order below column c
+        // (A) Procedure 2
+        if (tid == 0) {
+            R sig2 = 0;
 #pragma unroll
-            for (int q = 0; q < TAIL_RL; ++q) x[q] = pickn<R, 4>(a[q], cc);
-            R part = 0;
-#pragma unroll
-            for (int q = 0; q < TAIL_RL; ++q) {
-                const int r = r0 + q;
-                if (r >= c + 2 && r < M) part += x[q].x * x[q].x + x[q].y * x[q].y;
-            }
-#pragma unroll
-            for (int off = TAIL_G / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off, WAVE);
-            const cx<R> mine = pickn<R, TAIL_RL>(x, (c + 1) % TAIL_RL);
-            const int src = (lane & ~(TAIL_G - 1)) + (c + 1) / TAIL_RL;
-            cx<R> alpha;
-            alpha.x = __shfl(mine.x, src, WAVE);
-            alpha.y = __shfl(mine.y, src, WAVE);
+            for (int t = 0; t < TAIL_W; ++t) sig2 += red[t];
+            const cx<R> alpha = P[(c + 1) * (c + 2) / 2 + c];
             cx<R> tau, scale;
             R beta;
-            if (part == (R)0 && alpha.y == (R)0) {
+            if (sig2 == (R)0 && alpha.y == (R)0) {
                 tau = zero;
                 scale = zero;
                 beta = alpha.x;
             } else {
-                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + part);
+                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
                 beta = (alpha.x >= (R)0) ? -nrm : nrm;
                 tau = mk<R>((beta - alpha.x) / beta, -alpha.y / beta);
                 const R dr = alpha.x - beta, di = alpha.y;
                 const R den = dr * dr + di * di;
                 scale = mk<R>(dr / den, -di / den);
             }
-            // Procedure 3: v = (0 .. 0, 1, scale x_(c+2), ...), stored for the
-            // back-transformation
-#pragma unroll
-            for (int q = 0; q < TAIL_RL; ++q) {
-                const int r = r0 + q;
-                const bool live = r >= c + 1 && r < M;
-                const cx<R> v = live ? (r == c + 1 ? mk<R>(1, 0) : cmul(scale, x[q])) : zero;
-                sv[par][r] = v;
-                if (live) V[(int64_t)(i0 + r) + (int64_t)i * n] = v;
-            }
-            if (l == c / TAIL_RL) ws.d[b * n + i] = pickn<R, TAIL_RL>(x, c % TAIL_RL).x;
-            if (l == 0) {
-                stau[par] = tau;
-                ws.e[b * n + i] = beta;
-                ws.tau[b * n + i] = tau;
-            }
+            sref[0] = tau;
+            sref[1] = scale;
+            ws.d[b * n + i] = P[c * (c + 1) / 2 + c].x;
+            ws.e[b * n + i] = beta;
+            ws.tau[b * n + i] = tau;
         }
         __syncthreads();
-        const cx<R> tau = stau[par];
-        // the group holds trailing columns (uniform over its 16 lanes)
-        const bool gact = s0 + 3 >= c + 1;
-        const int sc = s0 + ((l >> 2) & 3);
-        cx<R> ys = zero, dp = zero;
-        if (gact) {
-            // Procedure 4: this lane's share of y_s = sum_r conj(A(r, s)) v_r
-            // for its group's four columns, summed over the group; lane l
-            // ends with the sum of column s0 + ((l >> 2) & 3)
-            cx<R> t[4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) t[p] = zero;
-#pragma unroll
-            for (int q = 0; q < TAIL_RL; ++q) {
-                const cx<R> vq = sv[par][r0 + q];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) t[p] = cfmac(a[q][p], vq, t[p]);
-            }
-            halve_step<8, 2, 4, R>(t, (lane & 8) != 0);
-            halve_step<4, 1, 4, R>(t, (lane & 4) != 0);
-            ys = t[0];
-            ys = xor_add<2, R>(ys);
-            ys = xor_add<1, R>(ys);
-            ys = (sc >= c + 1 && sc < M) ? cmul(tau, ys) : zero;
-            // the group's share of y^H v over its four columns
-            dp = cmulc(ys, sv[par][sc]);
-            dp = xor_add<4, R>(dp);
-            dp = xor_add<8, R>(dp);
+        const cx<R> tau = sref[0];
+        // (B) Procedure 3: v = (1, scale x_1, ...), stored for the back-transformation
+        if (tid < mm) {
+            const cx<R> v = tid == 0 ? mk<R>(1, 0) : cmul(sref[1], P[(c + 1 + tid) * (c + 2 + tid) / 2 + c]);
+            sv[tid] = v;
+            V[(int64_t)(i + 1 + tid) + (int64_t)i * ws.n] = v;
         }
-        if ((l & 3) == 0) sy[par][sc] = ys;
-        if (l == 0) sdp[par][g] = dp;
         __syncthreads();
-        // Procedure 5: w = y - (tau / 2)(y^H v) v
-        cx<R> dot = zero;
-#pragma unroll 8
-        for (int h = 0; h < TAIL_NG; ++h) dot = cadd(dot, sdp[par][h]);
-        const cx<R> kf = cscale(cmul(tau, dot), (R)0.5);
-        if (gact && r0 + TAIL_RL - 1 >= c + 1) {
-            cx<R> vc[4], wc[4];
+        // (C) Procedure 4: y = tau A22 v, the row's stored part and then its
+        // mirrored part read down column gr (the same terms in the same order
+        // as one pass over s2 = q, q + 8, ...), combined over the eight
+        // threads in a fixed order; and this wave's rows' share of y^H v
+        {
+            cx<R> acc = zero;
+            if (r < mm) {
+                const int gr = c + 1 + r;
+                const cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                int s2 = q;
+                for (; s2 + 24 <= r; s2 += 32) {
+                    cx<R> a4[4], v4[4];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                vc[p] = sv[par][s0 + p];
-                wc[p] = csub(sy[par][s0 + p], cmul(kf, vc[p]));
+                    for (int u = 0; u < 4; ++u) {
+                        a4[u] = Prow[s2 + 8 * u];
+                        v4[u] = sv[s2 + 8 * u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = cfma(a4[u], v4[u], acc);
+                }
+                for (; s2 <= r; s2 += 8) acc = cfma(Prow[s2], sv[s2], acc);
+                for (; s2 + 24 < mm; s2 += 32) {
+                    cx<R> a4[4], v4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int gs = c + 1 + s2 + 8 * u;
+                        a4[u] = P[gs * (gs + 1) / 2 + gr];
+                        v4[u] = sv[s2 + 8 * u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = cfma(cconj(a4[u]), v4[u], acc);
+                }
+                for (; s2 < mm; s2 += 8) {
+                    const int gs = c + 1 + s2;
+                    acc = cfma(cconj(P[gs * (gs + 1) / 2 + gr]), sv[s2], acc);
+                }
             }
-            // Procedure 6: A22 -= v w^H + w v^H
-#pragma unroll
-            for (int q = 0; q < TAIL_RL; ++q) {
-                const cx<R> vq = sv[par][r0 + q];
-                const cx<R> wq = csub(sy[par][r0 + q], cmul(kf, vq));
-#pragma unroll
-                for (int p = 0; p < 4; ++p) a[q][p] = csub(a[q][p], cadd(cmulc(wc[p], vq), cmulc(vc[p], wq)));
+            acc.x = dpp_sum<8>(acc.x);
+            acc.y = dpp_sum<8>(acc.y);
+            cx<R> yv = zero;
+            if (q == 0 && r < mm) {
+                const cx<R> y = cmul(tau, acc);
+                sy[r] = y;
+                yv = cmulc(y, sv[r]);
             }
+            yv.x = dpp_wave_sum(yv.x);
+            yv.y = dpp_wave_sum(yv.y);
+            if (lane == 0) sred[wv] = yv;
         }
-    }
-    // the last diagonal entry
-    const int e1 = M - 1;
-    if (g == (e1 >> 2) && l == e1 / TAIL_RL) {
-        cx<R> x[TAIL_RL];
+        __syncthreads();
+        // (D) Procedure 5: w = y - (tau / 2) (y^H v) v
+        if (tid < mm) {
+            cx<R> dot = zero;
 #pragma unroll
-        for (int q = 0; q < TAIL_RL; ++q) x[q] = pickn<R, 4>(a[q], e1 & 3);
-        ws.d[b * n + n - 1] = pickn<R, TAIL_RL>(x, e1 % TAIL_RL).x;
+            for (int t = 0; t < TAIL_W; ++t) dot = cadd(dot, sred[t]);
+            const cx<R> k = cscale(cmul(tau, dot), (R)0.5);
+            sw[tid] = csub(sy[tid], cmul(k, sv[tid]));
+        }
+        __syncthreads();
+        // (E) Procedure 6: A22 -= v w^H + w v^H (lower triangle), and the
+        // partial squared norms of column c + 1 below its sub-diagonal
+        {
+            R part = 0;
+            if (r < mm) {
+                const int gr = c + 1 + r;
+                const cx<R> vr = sv[r], wr = sw[r];
+                cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                int s2 = q;
+                for (; s2 + 24 <= r; s2 += 32) {
+                    cx<R> a4[4], w4[4], v4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a4[u] = Prow[s2 + 8 * u];
+                        w4[u] = sw[s2 + 8 * u];
+                        v4[u] = sv[s2 + 8 * u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a4[u] = csub(a4[u], cadd(cmulc(w4[u], vr), cmulc(v4[u], wr)));
+                    if (s2 == 0 && r >= 2) part = a4[0].x * a4[0].x + a4[0].y * a4[0].y;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) Prow[s2 + 8 * u] = a4[u];
+                }
+                for (; s2 <= r; s2 += 8) {
+                    cx<R> a = Prow[s2];
+                    a = csub(a, cadd(cmulc(sw[s2], vr), cmulc(sv[s2], wr)));
+                    if (s2 == 0 && r >= 2) part = a.x * a.x + a.y * a.y;
+                    Prow[s2] = a;
+                }
+            }
+            part = dpp_wave_sum(part);
+            if (lane == 0) red[wv] = part;
+        }
+        __syncthreads();
     }
+    if (tid == 0) ws.d[b * n + n - 1] = P[(M - 1) * M / 2 + (M - 1)].x;
 }
 
 }  // namespace

@@ -28,6 +28,7 @@
 // conj(G_ji), conj(S_ji)).  These kernels form lambda, the norms behind delta,
 // the clusters and I + E.  Every sum is taken in a fixed order.
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -59,8 +60,8 @@ __global__ __launch_bounds__(256) void k_refine_stats(int64_t n, const double2* 
         as = fma(wgt, fma(sv.x, sv.x, sv.y * sv.y), as);
         ar = fma(wgt, fma(gv.x, gv.x, gv.y * gv.y), ar);
     }
-    as = wave_sum(as);
-    ar = wave_sum(ar);
+    as = dpp_wave_sum(as);
+    ar = dpp_wave_sum(ar);
     if ((threadIdx.x & 63) == 0) { sh[threadIdx.x >> 6] = as; sh[4 + (threadIdx.x >> 6)] = ar; }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -82,9 +83,9 @@ __global__ __launch_bounds__(256) void k_refine_delta(int64_t n, const double* l
         r += pR[b * n + j];
         lm = fmax(lm, fabs(lam[b * n + j]));
     }
-    s = wave_sum(s);
-    r = wave_sum(r);
-    lm = wave_max(lm);
+    s = dpp_wave_sum(s);
+    r = dpp_wave_sum(r);
+    lm = dpp_wave_max(lm);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) { sh[w] = s; sh[4 + w] = r; sh[8 + w] = lm; }
     __syncthreads();
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(64) void k_refine_rr(int64_t n, const double2* G, c
             const double a2 = v.x * v.x + v.y * v.y;
             if (r == c) dia += a2; else off += a2;
         }
-        off = wave_sum(off);
-        dia = wave_sum(dia);
+        off = dpp_wave_sum(off);
+        dia = dpp_wave_sum(dia);
         // ||off||_F <= k eps ||diag||_F: the rounding level of a rotation (or NaN)
         if (!(off > (double)(k * k) * 4.93e-32 * dia)) break;
         for (int p = 0; p + 1 < k; ++p)
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(256) void k_orth_colmax(int64_t n, const double2* G
         const double a = fmax(fabs(v.x), fabs(v.y));
         m = (a > m || a != a) ? a : m;      // a NaN is kept
     }
-    m = wave_max(m);
+    m = dpp_wave_max(m);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {

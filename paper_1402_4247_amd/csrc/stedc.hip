@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void dc_init(DcWs ws)
         mx = fmax(mx, fabs(d[i]));
         if (i + 1 < n) mx = fmax(mx, fabs(e[i]));
     }
-    mx = wave_max(mx);
+    mx = dpp_wave_max(mx);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
     __syncthreads();
     double org = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
@@ -162,8 +163,8 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb, int ld
         dmx = fmax(dmx, fabs(dc));
         zmx = fmax(zmx, fabs(zc));
     }
-    dmx = wave_max(dmx);
-    zmx = wave_max(zmx);
+    dmx = dpp_wave_max(dmx);
+    zmx = dpp_wave_max(zmx);
     if ((tid & 63) == 0) { sh[tid >> 6] = dmx; sh[4 + (tid >> 6)] = zmx; }
     __syncthreads();
     dmx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
@@ -236,9 +237,7 @@ constexpr int SEC_LANES = 16;
 
 __device__ inline double root_sum(double v)
 {
-#pragma unroll
-    for (int m = 1; m < SEC_LANES; m <<= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    return dpp_sum<SEC_LANES>(v);
 }
 
 __device__ inline void secular_eval(int K, const double* dl, const double* zl, double rho, int j, double dorg,
@@ -385,8 +384,7 @@ __global__ __launch_bounds__(64) void dc_zhat(DcWs ws, int t)
         if (q == i) continue;
         p *= ((dl[org[q]] - di) + tv[q]) / (dl[q] - di);
     }
-#pragma unroll
-    for (int m = 1; m < SEC_LANES; m <<= 1) p *= __shfl_xor(p, m, WAVE);
+    p = dpp_prod<SEC_LANES>(p);
     if (sub == 0) ws.zhat[b * n + s + i] = copysign(sqrt(fmax(p, 0.0)), zl[i]);
 }
 
@@ -413,8 +411,7 @@ __global__ __launch_bounds__(64) void dc_vectors(DcWs ws, int t)
         const double v = zh[i] / ((dl[i] - dorg) - tj);
         ss += v * v;
     }
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) ss += __shfl_xor(ss, m, WAVE);
+    ss = dpp_wave_sum(ss);
     const double inv = 1.0 / sqrt(ss);
     double* Vc = ws.Vsec + b * ws.sQ + (s + j) * n + s;
     for (int i = lane; i < K; i += 64) Vc[i] = zh[i] / ((dl[i] - dorg) - tj) * inv;
@@ -444,8 +441,7 @@ __global__ __launch_bounds__(64) void dc_order(DcWs ws, int t, int wb)
         const double u = (r < K) ? lam[r] : dfd[r - K];
         if (u < v || (u == v && r < q)) ++rank;
     }
-#pragma unroll
-    for (int m = 1; m < SEC_LANES; m <<= 1) rank += __shfl_xor(rank, m, WAVE);
+    rank = dpp_sum<SEC_LANES>(rank);
     if (sub != 0) return;
     rank = min(rank, ns - 1);
     ws.D[wb][b * n + s + rank] = v;

@@ -4,6 +4,7 @@
 // rearrangement of S (x_j = u_j / sqrt(s_j)) and its definiteness check, and
 // the triangular factor of a block of reflectors (compact WY).
 #include "common.hpp"
+#include "lanes.hpp"
 #include "kernels.hpp"
 
 namespace kgev {
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void k_normalize_cols(int64_t n, double2* U, i
         const double2 v = u[i];
         acc = fma(v.x, v.x, fma(v.y, v.y, acc));
     }
-    acc = wave_sum(acc);
+    acc = dpp_wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     const double ss = (sh[0] + sh[1]) + (sh[2] + sh[3]);
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void k_normalize_cols_real(int64_t n, double* 
     double* z = Z + (int64_t)blockIdx.y * sz + (int64_t)blockIdx.x * ldz;
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) acc = fma(z[i], z[i], acc);
-    acc = wave_sum(acc);
+    acc = dpp_wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     const double f = 1.0 / sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
@@ -158,10 +159,8 @@ __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>
         cx<R> acc = czero<cx<R>>();
         if (r < j)
             for (int q = r + part; q < j; q += 4) acc = cfma(sT[q][r], gl[j][q], acc);
-        acc.x += __shfl_xor(acc.x, 1, WAVE);
-        acc.y += __shfl_xor(acc.y, 1, WAVE);
-        acc.x += __shfl_xor(acc.x, 2, WAVE);
-        acc.y += __shfl_xor(acc.y, 2, WAVE);
+        acc.x = dpp_sum<4>(acc.x);
+        acc.y = dpp_sum<4>(acc.y);
         if (part == 0 && r < kk) {
             const cx<R> tj = tl[j];
             sT[j][r] = csel(r < j, cscale(cmul(tj, acc), (R)-1), csel(r == j, tj, czero<cx<R>>()));
@@ -296,7 +295,7 @@ __global__ __launch_bounds__(256) void k_prune_colnorm(int64_t n, const double2*
         const double2 v = a[i];
         acc = fma(i > j ? 2.0 : 1.0, fma(v.x, v.x, v.y * v.y), acc);
     }
-    acc = wave_sum(acc);
+    acc = dpp_wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) part[b * n + j] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
@@ -316,8 +315,8 @@ __global__ __launch_bounds__(256) void k_prune_shift(int64_t n, double2* A, int6
         acc += part[b * n + j];
         cnt += !(s[b * sst + j] > s_tol * smax);
     }
-    acc = wave_sum(acc);
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, WAVE);
+    acc = dpp_wave_sum(acc);
+    cnt = dpp_wave_sum(cnt);
     if ((threadIdx.x & 63) == 0) {
         sh[threadIdx.x >> 6] = acc;
         sc[threadIdx.x >> 6] = cnt;
