@@ -120,7 +120,11 @@ def roofline_object(prof, phase, elapsed, note, traffic, K):
     """Roofline object of one phase from the library's sampled launch timing:
     achieved = algorithmic work per timed launch / mean timed duration."""
     hemv = phase == K.PHASE_HEMV
-    base = {"bound": "hbm" if hemv else "mfma", "kernel": "hetrd_zhemv" if hemv else "cgemm_kernel",
+    # the Hermitian product of a blocked column runs in one of two forms,
+    # four 64 x 64 tiles per workgroup (hetrd_zhemv) or one (hetrd_zhemv_tile),
+    # chosen per column by the workgroup count: the phase covers both
+    base = {"bound": "hbm" if hemv else "mfma",
+            "kernel": "hetrd_zhemv + hetrd_zhemv_tile" if hemv else "cgemm_kernel",
             "peak": PEAK_HBM_GBS if hemv else PEAK_FP64_TFLOPS, "unit": "GB/s" if hemv else "TFLOP/s"}
     if prof is None:
         return {**base, "achieved": None, "frac": None, "traffic": None,
@@ -276,7 +280,8 @@ def main():
                     help="steps of graph replay (the solve captured once as a HIP graph) reported beside the "
                          "kernel-by-kernel headline; 0 skips it")
     ap.add_argument("--autotune", action="store_true",
-                    help="run kgev_autotune for this n before timing (the tuned panel width is then used)")
+                    help="run kgev_autotune for this n before timing (the tuned panel width and "
+                         "Hermitian-product threshold are then used)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of MIB MiB (3 launches) and exit: the "
                          "reference of known size for scaling the HBM byte counters")
@@ -318,6 +323,9 @@ def main():
     if args.autotune:
         tuned_nb = K.autotune(ctx, n)
         log(f"[bench] autotuned panel width {tuned_nb}")
+    _, hemv_slots, gemm_slots, _ = K.tuned_params(ctx, n)
+    if args.autotune:
+        log(f"[bench] autotuned thresholds: Hermitian product {hemv_slots}, products {gemm_slots} workgroups")
 
     def step():
         st = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=dst, opts=opts)
@@ -637,7 +645,8 @@ def main():
                                 f"eigenvalues uniform in [-1, 1]), n={n}, {nk} independent pencils, complex128, all "
                                 "eigenpairs"),
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
-                   "panel_nb": args.panel_nb or tuned_nb or 32},
+                   "panel_nb": args.panel_nb or tuned_nb or 32, "hemv_slots": hemv_slots, "gemm_slots": gemm_slots,
+                   "autotuned": bool(args.autotune)},
         "roofline": roof, "roofline_gemm": roof2, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "eigenvalues_only": values, "cholesky_s": chol,
         "host_path": host, "x_reuse": xreuse, "serving": serving,
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

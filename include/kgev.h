@@ -92,7 +92,16 @@ typedef struct {
                              s_j <= s_tol s_max are dropped instead of failing: w[0:n'] are the
                              reduced pencil's eigenvalues ascending, w[n':n] = +inf and columns
                              n'..n-1 of C are zero) */
-    int32_t reserved[5];  /* must be zero */
+    int32_t hemv_slots;   /* Householder reduction: a column's Hermitian product takes one 64 x 64
+                             tile per workgroup when four tiles per workgroup would launch fewer
+                             than this many workgroups over all k-points of the call, else four;
+                             0 = tuned (kgev_autotune) or the default 768 (three per CU);
+                             1 = always four */
+    int32_t gemm_slots;   /* complex products (Parts 3 and 4, back-transformations): 32 x 32 tiles
+                             when 64 x 64 tiles would launch fewer than this many workgroups, else
+                             64 x 64 (the results are the same bits either way); 0 = tuned or the
+                             default 256 (one per CU); 1 = always 64 x 64 */
+    int32_t reserved[3];  /* must be zero */
 } kgev_opts;
 
 #define KGEV_S_EIG      0
@@ -116,16 +125,39 @@ const char* kgev_status_str(kgev_status st);
 kgev_status kgev_create(kgev_ctx** ctx, int device);
 
 /*
- * Panel-width autotuner.  Times the blocked Householder reduction of
- * synthetic Hermitian matrices of order n for the candidate panel widths
- * 16, 24, 32, 48 and 64 and records the fastest in the context for (n,
- * precision); later calls through this context with opts->panel_nb == 0 use
- * it.  The choice depends only on n and precision, never on the batch, so a
- * k-point's result does not depend on which other k-points share its call.
- * *best_nb (optional) receives the choice.  Synchronous; uses the context's
- * internal workspace.
+ * Autotuner of panel and tile sizes for pencils of order n.  Times, on
+ * synthetic Hermitian matrices of order n (four at a time): the blocked
+ * Householder reduction (Procedures 1-6 of Section III, the largest cost of
+ * Eigen_HH) for the panel widths 16, 24, 32, 48 and 64; at the fastest
+ * width, the reduction for the Hermitian-product tile grouping thresholds
+ * (opts.hemv_slots) 1 (four tiles per workgroup throughout), 256, 768, 2048
+ * and 2^30 (one tile per workgroup throughout); and the n x n x n complex
+ * products of Parts 3 and 4 for the product tile thresholds (opts.gemm_slots)
+ * 1 (64 x 64 tiles throughout), 64, 256, 1024 and 2^30 (32 x 32
+ * throughout).  A threshold other than the default is taken only when it is
+ * more than 2% faster.  The choices are recorded in the context for (n,
+ * precision); later calls through this context leaving the corresponding
+ * option 0 use them.  The tuned values depend only on n and precision, not
+ * on the batch.
+ * Results are bitwise reproducible for the same n, k-point count and
+ * options; the tile grouping of a column follows the launch's workgroup
+ * count, so the same k-point solved in calls of different k-point counts
+ * agrees to rounding, not necessarily bitwise.  *best_nb (optional)
+ * receives the panel width.  Synchronous; uses the context's internal
+ * workspace.
  */
 kgev_status kgev_autotune(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* best_nb);
+
+/*
+ * The panel width and the two tile thresholds that solves of order n and
+ * this precision use through ctx when opts leave them 0: the tuned values
+ * after kgev_autotune(ctx, n, precision, ...), else the defaults (32, 768,
+ * 256).  *tuned (optional) is set to 1 when they come from the tuner.  Any
+ * output pointer may be NULL.  Returns KGEV_OK, -1 (ctx NULL) or -3 (bad
+ * precision).
+ */
+kgev_status kgev_tuned_params(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* panel_nb,
+                              int32_t* hemv_slots, int32_t* gemm_slots, int32_t* tuned);
 
 /* Release a context and everything it owns.  NULL is allowed. */
 void kgev_destroy(kgev_ctx* ctx);

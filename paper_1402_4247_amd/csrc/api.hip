@@ -40,6 +40,12 @@ struct GraphKey {
     bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
+namespace kgev {
+struct TunedParams {
+    int nb, hemv_slots, gemm_slots;
+};
+}  // namespace kgev
+
 struct kgev_ctx {
     int device;
     std::vector<hipStream_t> aux;      // streams of the concurrent k-point groups 1..
@@ -47,7 +53,7 @@ struct kgev_ctx {
     kgev::Profiler* prof;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // most recent last
     std::vector<std::pair<std::vector<uintptr_t>, hipGraphExec_t>> batch_graphs;   // most recent last
-    std::map<std::pair<int64_t, int>, int> tuned_nb;            // (n, precision) -> panel width
+    std::map<std::pair<int64_t, int>, kgev::TunedParams> tuned;   // (n, precision) -> tuned options
     void* work;
     size_t work_bytes;
     // host-pointer API staging buffers
@@ -59,6 +65,7 @@ struct kgev_ctx {
 namespace {
 
 constexpr int DEFAULT_NB = 32;
+constexpr int DEFAULT_SLOTS = 3 * 256;   // Hermitian-product workgroups below which one tile per workgroup
 constexpr int DEFAULT_STREAMS = 1;
 constexpr int UNMTR_KB = 64;
 
@@ -76,6 +83,7 @@ struct Layout {
 struct SolvePlan {
     int64_t n, nk;
     int nb, kb;
+    int slots1;                // Hermitian-product tile grouping threshold (HetrdWs::slots1)
     int NBmax, CHmax, PN;
     // complex128 arrays
     size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, qpart, uwork, cwork, ppart, ndrop;
@@ -93,9 +101,10 @@ struct SolvePlan {
     size_t total;
 };
 
-SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false)
+SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false, int slots1 = DEFAULT_SLOTS)
 {
     SolvePlan p{};
+    p.slots1 = slots1;
     p.mixed = mixed;
     p.n = n;
     p.nk = nk;
@@ -175,6 +184,7 @@ HetrdWs<float> hetrd_ws32(const SolvePlan& p, void* w)
     HetrdWs<float> h{};
     h.n = (int)p.n;
     h.nb = p.nb;
+    h.slots1 = p.slots1;
     h.NBmax = p.NBmax;
     h.CHmax = p.CHmax;
     h.A = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_A); h.lda = p.n; h.sA = p.n * p.n;
@@ -201,6 +211,7 @@ HetrdWs<double> hetrd_ws(const SolvePlan& p, void* w, double2* A, int64_t lda, i
     HetrdWs<double> h{};
     h.n = (int)p.n;
     h.nb = p.nb;
+    h.slots1 = p.slots1;
     h.NBmax = p.NBmax;
     h.CHmax = p.CHmax;
     h.A = A; h.lda = lda; h.sA = sA;
@@ -247,6 +258,8 @@ kgev_opts resolve_opts(const kgev_opts* o)
     kgev_opts_default(&r);
     if (o) r = *o;
     if (r.panel_nb == 0) r.panel_nb = DEFAULT_NB;
+    if (r.hemv_slots == 0) r.hemv_slots = DEFAULT_SLOTS;
+    if (r.gemm_slots == 0) r.gemm_slots = GEMM_SMALL_SLOTS_DEFAULT;
     if (r.s_tol == 0.0) r.s_tol = 1e-12;
     if (r.refine_iters == 0) r.refine_iters = 3;
     if (r.streams == 0) r.streams = DEFAULT_STREAMS;
@@ -259,14 +272,35 @@ bool opts_valid(const kgev_opts& o)
     if (o.refine_iters < 1 || o.refine_iters > 10) return false;
     if (o.want_vectors != 0 && o.want_vectors != 1) return false;
     if (o.panel_nb < 1 || o.panel_nb > 64) return false;
+    if (o.hemv_slots < 1 || o.gemm_slots < 1) return false;
     if (!(o.s_tol > 0.0) || o.s_tol >= 1.0) return false;
     if (o.use_graph != 0 && o.use_graph != 1) return false;
     if (o.streams < 1 || o.streams > 8) return false;
     if (o.s_method != KGEV_S_EIG && o.s_method != KGEV_S_CHOLESKY && o.s_method != KGEV_S_PRUNE) return false;
-    for (int q = 0; q < 5; ++q)
+    for (int q = 0; q < 3; ++q)
         if (o.reserved[q] != 0) return false;
     return true;
 }
+
+// The tuner's values for the fields the caller left 0 (user: the caller's
+// options, null for all defaults).
+void apply_tuned(const kgev_ctx* ctx, int64_t n, const kgev_opts* user, kgev_opts& o)
+{
+    auto it = ctx->tuned.find({n, o.precision});
+    if (it == ctx->tuned.end()) return;
+    if (!user || user->panel_nb == 0) o.panel_nb = it->second.nb;
+    if (!user || user->hemv_slots == 0) o.hemv_slots = it->second.hemv_slots;
+    if (!user || user->gemm_slots == 0) o.gemm_slots = it->second.gemm_slots;
+}
+
+// the product tile policy of one call, installed for the calling thread
+struct TileScope {
+    int old;
+    explicit TileScope(int slots) : old(gemm_small_tile_slots(slots)) {}
+    ~TileScope() { gemm_small_tile_slots(old); }
+    TileScope(const TileScope&) = delete;
+    TileScope& operator=(const TileScope&) = delete;
+};
 
 // With KGEV_DEBUG set in the environment, a failing HIP call is reported on
 // stderr (call site and HIP error name) before KGEV_EDEVICE is returned.
@@ -395,6 +429,7 @@ kgev_status solve_device(const SolvePlan& p, const kgev_opts& o, void* w, hipStr
                          const double2* S, int64_t ld, double* dw, double2* dC, int64_t ldc, int32_t* d_status,
                          const double2* Xin = nullptr, double2* Xout = nullptr, const int* nreal = nullptr)
 {
+    const TileScope tiles(o.gemm_slots);
     const int64_t n = p.n, nk = p.nk, nn = n * n;
     int* status = at<int>(w, p.status);
     double2* Aw = at<double2>(w, p.Aw);
@@ -480,7 +515,7 @@ Groups make_groups(int64_t n, int64_t nk, const kgev_opts& o)
     g.G = (int)std::min<int64_t>(o.streams, nk);
     g.gsz = (nk + g.G - 1) / g.G;
     g.G = (int)((nk + g.gsz - 1) / g.gsz);
-    g.p = make_plan(n, g.gsz, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+    g.p = make_plan(n, g.gsz, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE, o.hemv_slots);
     g.region = (g.p.total + 255) & ~(size_t)255;
     return g;
 }
@@ -511,7 +546,7 @@ kgev_status solve_grouped(kgev_ctx* ctx, const Groups& g, const kgev_opts& o, vo
     KCHECK(hipEventRecord(ctx->ev[0], st));
     for (int q = 0; q < g.G; ++q) {
         const int64_t k0 = q * g.gsz, cnt = std::min<int64_t>(g.gsz, nk - k0);
-        const SolvePlan pq = (cnt == g.gsz) ? g.p : make_plan(n, cnt, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+        const SolvePlan pq = (cnt == g.gsz) ? g.p : make_plan(n, cnt, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE, o.hemv_slots);
         hipStream_t s = q == 0 ? st : ctx->aux[q - 1];
         if (q > 0) KCHECK(hipStreamWaitEvent(s, ctx->ev[0], 0));
         r = solve_device(pq, o, static_cast<char*>(w) + (size_t)q * g.region, s, H + k0 * ld * n, S + k0 * ld * n,
@@ -595,13 +630,10 @@ ClassLayout class_layout(const kgev_problem* probs, const BatchClass& c, const k
 }
 
 kgev_status solve_class(kgev_ctx* ctx, const kgev_problem* probs, const BatchClass& c, const kgev_opts& o0,
-                        void* w, hipStream_t st, bool tuned)
+                        void* w, hipStream_t st, const kgev_opts* user)
 {
     kgev_opts o = o0;
-    if (tuned) {
-        auto it = ctx->tuned_nb.find({c.N, o.precision});
-        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
-    }
+    apply_tuned(ctx, c.N, user, o);
     const ClassLayout L = class_layout(probs, c, o);
     char* base = static_cast<char*>(w);
     if (L.direct) {
@@ -776,13 +808,11 @@ kgev_status kgev_solve_k_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z* d
     if (ld < n) return -5;
     if (nk < 1) return -6;
     if (!dw) return -7;
-    if ((!opts || opts->panel_nb == 0)) {
+    if (!opts || opts->panel_nb == 0 || opts->hemv_slots == 0 || opts->gemm_slots == 0) {
         kgev_opts t = resolve_opts(opts);
-        auto it = ctx->tuned_nb.find({n, t.precision});
-        if (it != ctx->tuned_nb.end()) {
-            kgev_opts o2 = t;
-            o2.panel_nb = it->second;
-            return kgev_solve_k_device(ctx, dH, dS, n, ld, nk, dw, dC, ldc, dwork, work_bytes, d_status, &o2, stream);
+        if (ctx->tuned.count({n, t.precision})) {
+            apply_tuned(ctx, n, opts, t);     // every field now set: the call below does not come back here
+            return kgev_solve_k_device(ctx, dH, dS, n, ld, nk, dw, dC, ldc, dwork, work_bytes, d_status, &t, stream);
         }
     }
     kgev_opts o = resolve_opts(opts);
@@ -855,10 +885,7 @@ kgev_status kgev_solve_k_device_noalloc(kgev_ctx* ctx, const kgev_z* dH, const k
     if (nk < 1) return -6;
     if (!dw) return -7;
     kgev_opts o = resolve_opts(opts);
-    if ((!opts || opts->panel_nb == 0)) {
-        auto it = ctx->tuned_nb.find({n, o.precision});
-        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
-    }
+    apply_tuned(ctx, n, opts, o);
     if (!opts_valid(o)) return -10;
     if (o.want_vectors && (!dC || ldc < n)) return -8;
     if (o.use_graph || o.streams > 1) return KGEV_EUNSUPPORTED;
@@ -916,7 +943,7 @@ kgev_status kgev_solve_batch_device(kgev_ctx* ctx, const kgev_problem* probs, in
     const std::vector<BatchClass> classes = batch_classes(probs, count);
     auto run_all = [&](hipStream_t st) -> kgev_status {
         for (const BatchClass& c : classes) {
-            const kgev_status r = solve_class(ctx, probs, c, oe, w, st, !opts || opts->panel_nb == 0);
+            const kgev_status r = solve_class(ctx, probs, c, oe, w, st, opts);
             if (r != KGEV_OK) return r;
         }
         return KGEV_OK;
@@ -988,15 +1015,12 @@ kgev_status kgev_solve_k_x_device(kgev_ctx* ctx, const kgev_z* dH, const kgev_z*
     if (!dw) return -7;
     if (!dX) return -10;
     kgev_opts o = resolve_opts(opts);
-    if ((!opts || opts->panel_nb == 0)) {
-        auto it = ctx->tuned_nb.find({n, o.precision});
-        if (it != ctx->tuned_nb.end()) o.panel_nb = it->second;
-    }
+    apply_tuned(ctx, n, opts, o);
     if (!opts_valid(o)) return -15;
     if (o.want_vectors && (!dC || ldc < n)) return -8;
     if (x_mode == KGEV_X_REUSE && o.s_method == KGEV_S_PRUNE) return KGEV_EUNSUPPORTED;
     DevGuard g(ctx->device);
-    SolvePlan p = make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE);
+    SolvePlan p = make_plan(n, nk, o.panel_nb, o.precision == KGEV_PREC_FP32_REFINE, o.hemv_slots);
     void* w = dwork;
     if (w) {
         if (work_bytes < p.total) return -13;
@@ -1073,9 +1097,10 @@ kgev_status kgev_hetrd_device(kgev_ctx* ctx, kgev_z* dA, int64_t n, int64_t lda,
     if (!dtau) return -8;
     if (!dV) return -9;
     kgev_opts o = resolve_opts(opts);
-    if (o.panel_nb < 1 || o.panel_nb > 64) return -10;
+    if (o.panel_nb < 1 || o.panel_nb > 64 || o.hemv_slots < 1 || o.gemm_slots < 1) return -10;
     DevGuard g(ctx->device);
-    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    const TileScope tiles(o.gemm_slots);
+    SolvePlan p = make_plan(n, nk, o.panel_nb, false, o.hemv_slots);
     kgev_status r = ensure_work(ctx, p.total);
     if (r != KGEV_OK) return r;
     hipStream_t st = (hipStream_t)stream;
@@ -1154,9 +1179,10 @@ kgev_status kgev_eigh_device(kgev_ctx* ctx, const kgev_z* dA, int64_t n, int64_t
     if (nk < 1) return -5;
     if (!dw) return -6;
     kgev_opts o = resolve_opts(opts);
-    if (o.panel_nb < 1 || o.panel_nb > 64) return -9;
+    if (o.panel_nb < 1 || o.panel_nb > 64 || o.hemv_slots < 1 || o.gemm_slots < 1) return -9;
     DevGuard g(ctx->device);
-    SolvePlan p = make_plan(n, nk, o.panel_nb);
+    const TileScope tiles(o.gemm_slots);
+    SolvePlan p = make_plan(n, nk, o.panel_nb, false, o.hemv_slots);
     kgev_status r = ensure_work(ctx, p.total);
     if (r != KGEV_OK) return r;
     hipStream_t st = (hipStream_t)stream;
@@ -1370,44 +1396,121 @@ kgev_status kgev_autotune(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* 
     hipEvent_t e0, e1;
     KCHECK(hipEventCreate(&e0));
     KCHECK(hipEventCreate(&e1));
+    const int64_t nn = n * n;
+    // one timed reduction of the nk synthetic matrices
+    auto time_one = [&](int nb, int slots, float& ms) -> hipError_t {
+        SolvePlan p = make_plan(n, nk, nb, mixed, slots);
+        void* w = ctx->work;
+        hipError_t e;
+        if (mixed) {
+            HetrdWs<float> h = hetrd_ws32(p, w);
+            if ((e = fill_test_matrix<float>(st, n, h.A, nk, 17)) != hipSuccess) return e;
+            if ((e = fill_zero(st, h.V, sizeof(float2) * (size_t)nn * nk)) != hipSuccess) return e;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+            if ((e = hetrd<float>(st, h, nk)) != hipSuccess) return e;
+        } else {
+            double2* Aw = at<double2>(w, p.Aw);
+            double2* Vs = at<double2>(w, p.Vs);
+            if ((e = fill_test_matrix<double>(st, n, Aw, nk, 17)) != hipSuccess) return e;
+            if ((e = fill_zero(st, Vs, sizeof(double2) * (size_t)nn * nk)) != hipSuccess) return e;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+            if ((e = hetrd<double>(st, hetrd_ws(p, w, Aw, n, nn, Vs, at<double>(w, p.d), at<double>(w, p.e),
+                                                at<double2>(w, p.tau)),
+                                   nk)) != hipSuccess)
+                return e;
+        }
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        return hipEventElapsedTime(&ms, e0, e1);
+    };
+    // panel width (first pass warms up, second pass decides)
     const int cands[] = {16, 24, 32, 48, 64};
     int best = DEFAULT_NB;
     float best_ms = 1e30f;
-    const int64_t nn = n * n;
-    for (int rep = 0; rep < 2; ++rep) {          // first pass warms up, second pass decides
+    for (int rep = 0; rep < 2; ++rep) {
         for (int nb : cands) {
-            SolvePlan p = make_plan(n, nk, nb, mixed);
-            void* w = ctx->work;
-            if (mixed) {
-                HetrdWs<float> h = hetrd_ws32(p, w);
-                KCHECK(fill_test_matrix<float>(st, n, h.A, nk, 17));
-                KCHECK(fill_zero(st, h.V, sizeof(float2) * (size_t)nn * nk));
-                KCHECK(hipEventRecord(e0, st));
-                KCHECK(hetrd<float>(st, h, nk));
-            } else {
-                double2* Aw = at<double2>(w, p.Aw);
-                double2* Vs = at<double2>(w, p.Vs);
-                KCHECK(fill_test_matrix<double>(st, n, Aw, nk, 17));
-                KCHECK(fill_zero(st, Vs, sizeof(double2) * (size_t)nn * nk));
-                KCHECK(hipEventRecord(e0, st));
-                KCHECK(hetrd<double>(st, hetrd_ws(p, w, Aw, n, nn, Vs, at<double>(w, p.d), at<double>(w, p.e),
-                                                  at<double2>(w, p.tau)),
-                                     nk));
-            }
-            KCHECK(hipEventRecord(e1, st));
-            KCHECK(hipEventSynchronize(e1));
             float ms = 0;
-            KCHECK(hipEventElapsedTime(&ms, e0, e1));
+            KCHECK(time_one(nb, DEFAULT_SLOTS, ms));
             if (rep == 1 && ms < best_ms) {
                 best_ms = ms;
                 best = nb;
             }
         }
     }
+    // tile grouping of the Hermitian product at that width: the default
+    // unless another threshold is faster by more than 2% (best of two runs)
+    const int slots_c[] = {1, 256, DEFAULT_SLOTS, 2048, 1 << 30};
+    float t_def = 1e30f;
+    float t_c[5];
+    for (int q = 0; q < 5; ++q) {
+        t_c[q] = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            float ms = 0;
+            KCHECK(time_one(best, slots_c[q], ms));
+            t_c[q] = std::min(t_c[q], ms);
+        }
+        if (slots_c[q] == DEFAULT_SLOTS) t_def = t_c[q];
+    }
+    int best_slots = DEFAULT_SLOTS;
+    float best_t = t_def;
+    for (int q = 0; q < 5; ++q)
+        if (t_c[q] < 0.98f * t_def && t_c[q] < best_t) {
+            best_t = t_c[q];
+            best_slots = slots_c[q];
+        }
+    // product tiles: the n x n x n products of Parts 3 and 4 (G = H X, then
+    // the lower half of X^H G) on the reduction's matrices
+    const int gemm_c[] = {1, 64, GEMM_SMALL_SLOTS_DEFAULT, 1024, 1 << 30};
+    float g_c[5], g_def = 1e30f;
+    {
+        SolvePlan p = make_plan(n, nk, best, false);
+        double2* A = at<double2>(ctx->work, p.Aw);
+        double2* B = at<double2>(ctx->work, p.Vs);
+        double2* Cm = at<double2>(ctx->work, p.X);
+        KCHECK(fill_test_matrix<double>(st, n, A, nk, 19));
+        KCHECK(fill_test_matrix<double>(st, n, B, nk, 23));
+        const double2 one = mk<double>(1, 0), zero = mk<double>(0, 0);
+        for (int q = 0; q < 5; ++q) {
+            g_c[q] = 1e30f;
+            const TileScope tiles(gemm_c[q]);
+            for (int rep = 0; rep < 2; ++rep) {
+                KCHECK(hipEventRecord(e0, st));
+                KCHECK(cgemm<double>(st, 'N', 'N', n, n, n, one, A, n, nn, B, n, nn, zero, Cm, n, nn, nk, false));
+                KCHECK(cgemm<double>(st, 'C', 'N', n, n, n, one, B, n, nn, Cm, n, nn, zero, A, n, nn, nk, true));
+                KCHECK(hipEventRecord(e1, st));
+                KCHECK(hipEventSynchronize(e1));
+                float ms = 0;
+                KCHECK(hipEventElapsedTime(&ms, e0, e1));
+                g_c[q] = std::min(g_c[q], ms);
+            }
+            if (gemm_c[q] == GEMM_SMALL_SLOTS_DEFAULT) g_def = g_c[q];
+        }
+    }
+    int best_gemm = GEMM_SMALL_SLOTS_DEFAULT;
+    float best_g = g_def;
+    for (int q = 0; q < 5; ++q)
+        if (g_c[q] < 0.98f * g_def && g_c[q] < best_g) {
+            best_g = g_c[q];
+            best_gemm = gemm_c[q];
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ctx->tuned_nb[{n, precision}] = best;
+    ctx->tuned[{n, precision}] = {best, best_slots, best_gemm};
     if (best_nb) *best_nb = best;
+    return KGEV_OK;
+}
+
+kgev_status kgev_tuned_params(kgev_ctx* ctx, int64_t n, int32_t precision, int32_t* panel_nb, int32_t* hemv_slots,
+                              int32_t* gemm_slots, int32_t* tuned)
+{
+    if (!ctx) return -1;
+    if (precision != KGEV_PREC_FP64 && precision != KGEV_PREC_FP32_REFINE) return -3;
+    auto it = ctx->tuned.find({n, precision});
+    const bool t = it != ctx->tuned.end();
+    if (panel_nb) *panel_nb = t ? it->second.nb : DEFAULT_NB;
+    if (hemv_slots) *hemv_slots = t ? it->second.hemv_slots : DEFAULT_SLOTS;
+    if (gemm_slots) *gemm_slots = t ? it->second.gemm_slots : GEMM_SMALL_SLOTS_DEFAULT;
+    if (tuned) *tuned = t ? 1 : 0;
     return KGEV_OK;
 }
 

@@ -318,18 +318,23 @@ hipError_t launch_tiles(CGemmArgs<R> p, hipStream_t st, const ProfLaunch& pl)
 }
 
 // the operand forms are compile-time so that the tile loads are straight-line
-template <typename R, bool G3>
+template <typename R, bool G3, int T>
 hipError_t launch_forms(const CGemmArgs<R>& p, hipStream_t st, const ProfLaunch& pl)
 {
-    if (p.tb[0] == 2) return launch_tiles<R, 64, 64, false, 0, 2>(p, st, pl);
+    if (p.tb[0] == 2) return launch_tiles<R, T, T, false, 0, 2>(p, st, pl);
     const int f = p.ta[0] * 2 + p.tb[0];
     switch (f) {
-    case 0: return launch_tiles<R, 64, 64, G3, 0, 0>(p, st, pl);
-    case 1: return launch_tiles<R, 64, 64, G3, 0, 1>(p, st, pl);
-    case 2: return launch_tiles<R, 64, 64, G3, 1, 0>(p, st, pl);
-    default: return launch_tiles<R, 64, 64, G3, 1, 1>(p, st, pl);
+    case 0: return launch_tiles<R, T, T, G3, 0, 0>(p, st, pl);
+    case 1: return launch_tiles<R, T, T, G3, 0, 1>(p, st, pl);
+    case 2: return launch_tiles<R, T, T, G3, 1, 0>(p, st, pl);
+    default: return launch_tiles<R, T, T, G3, 1, 1>(p, st, pl);
     }
 }
+
+// Products whose 64 x 64 grid would launch fewer workgroups than this take
+// 32 x 32 tiles (four times the workgroups, each a quarter of the work): set
+// per calling thread by the solve entry points from their options.
+thread_local int tl_small_tile_slots = GEMM_SMALL_SLOTS_DEFAULT;
 
 template <typename R>
 hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
@@ -346,13 +351,23 @@ hipError_t launch_cgemm(const CGemmArgs<R>& a, int64_t batch, hipStream_t st)
     // products in the 3M form (1.22x the four-product form on gfx950 on the
     // path's products, with unchanged residuals).
     p.remap = 1;
+    const int64_t tm = (p.m + 63) / 64, tn = (p.n + 63) / 64;
+    const int64_t grid64 = (p.lower && tm == tn ? tm * (tm + 1) / 2 : tm * tn) * p.batch;
     const ProfLaunch pl = prof_launch_begin(PH_GEMM, st);
-    const hipError_t e = launch_forms<R, true>(p, st, pl);
+    const hipError_t e = grid64 < tl_small_tile_slots ? launch_forms<R, true, 32>(p, st, pl)
+                                                      : launch_forms<R, true, 64>(p, st, pl);
     prof_launch_end(PH_GEMM, st, pl, 0.0, flops);
     return e;
 }
 
 }  // namespace
+
+int gemm_small_tile_slots(int slots)
+{
+    const int old = tl_small_tile_slots;
+    tl_small_tile_slots = slots;
+    return old;
+}
 
 template <typename R>
 hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,

@@ -46,6 +46,28 @@ constexpr int RB = 64;          // rows per workgroup in the column kernels
 __device__ __host__ inline int nchunks(int NB, int C) { return (NB - C + ZCH - 1) / ZCH; }
 __device__ __host__ inline int nchunks_z(int NB, int C, int zch) { return zch == 1 ? NB - C : (NB - C + 3) >> 2; }
 
+// Procedure 2's reflector for the sub-column x = (alpha, x_2, ...) with
+// sig2 = |x_2|^2 + ...: beta = -sign(Re alpha) ||x||, tau = (beta - alpha) /
+// beta and the scale 1 / (alpha - beta) applied to x_2, ...; two reciprocals
+// (the latency of a division chain dominates this single-lane step).
+template <typename R>
+__device__ inline void reflector_core(cx<R> alpha, R sig2, cx<R>& tau, cx<R>& scale, R& beta)
+{
+    if (sig2 == (R)0 && alpha.y == (R)0) {
+        tau = czero<cx<R>>();
+        scale = czero<cx<R>>();
+        beta = alpha.x;
+        return;
+    }
+    const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+    beta = (alpha.x >= (R)0) ? -nrm : nrm;
+    const R ib = (R)1 / beta;
+    tau = mk<R>((beta - alpha.x) * ib, -alpha.y * ib);
+    const R dr = alpha.x - beta, di = alpha.y;
+    const R iden = (R)1 / (dr * dr + di * di);
+    scale = mk<R>(dr * iden, -di * iden);
+}
+
 // Reflector from the partial norms: returns tau and the scale applied to x.
 // Called by whole waves: the partial norms are summed across the lanes (the
 // same tree in every wave, so every wave holds the same bits).
@@ -59,19 +81,7 @@ __device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& 
     for (int q = (int)(threadIdx.x & 63); q < np; q += 64) part += pn[q];
     const R sig2 = dpp_wave_sum(part);
     const cx<R> alpha = ws.A[b * ws.sA + (int64_t)(i + 1) + (int64_t)i * ws.lda];
-    if (sig2 == (R)0 && alpha.y == (R)0) {
-        tau = czero<cx<R>>();
-        scale = czero<cx<R>>();
-        beta = alpha.x;
-        return;
-    }
-    const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
-    beta = (alpha.x >= (R)0) ? -nrm : nrm;
-    tau = mk<R>((beta - alpha.x) / beta, -alpha.y / beta);
-    // scale = 1 / (alpha - beta)
-    const R dr = alpha.x - beta, di = alpha.y;
-    const R den = dr * dr + di * di;
-    scale = mk<R>(dr / den, -di / den);
+    reflector_core(alpha, sig2, tau, scale, beta);
 }
 
 // One halving step of the transposing reduction: lanes with the MASK bit set
@@ -686,7 +696,7 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
 // ---------------------------------------------------------------------------
 // The last columns, once the trailing matrix has at most TAIL_M rows: one
 // workgroup per problem holds its lower triangle in LDS (packed by rows,
-// element (r, s), r >= s, at r (r + 1) / 2 + s) and reduces it column by
+// element (r, s), r >= s, at tail_row(r) + s) and reduces it column by
 // column, unblocked: Procedure 2's reflector from the column's norm,
 // y = tau A22 v (Procedure 4), w = y - (tau / 2)(y^H v) v (Procedure 5) and
 // A22 -= v w^H + w v^H (Procedure 6), with the same reflector convention as
@@ -705,10 +715,13 @@ constexpr int TAIL_T = 1024;
 constexpr int TAIL_W = TAIL_T / 64;
 static_assert(TAIL_T / 8 >= TAIL_M, "eight threads per row of the tail's trailing matrix");
 
+// start of row r of the packed lower triangle
+__host__ __device__ constexpr int tail_row(int r) { return r * (r + 1) / 2; }
+
 template <typename R>
 __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
 {
-    __shared__ cx<R> P[TAIL_M * (TAIL_M + 1) / 2];
+    __shared__ cx<R> P[tail_row(TAIL_M)];
     __shared__ cx<R> sv[TAIL_M], sy[TAIL_M], sw[TAIL_M];
     __shared__ R red[TAIL_W];
     __shared__ cx<R> sred[TAIL_W];
@@ -721,14 +734,14 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
     const cx<R> zero = czero<cx<R>>();
     for (int e = tid; e < M * M; e += TAIL_T) {
         const int rr = e % M, c = e / M;
-        if (rr >= c) P[rr * (rr + 1) / 2 + c] = A[(int64_t)(i0 + rr) + (int64_t)(i0 + c) * ws.lda];
+        if (rr >= c) P[tail_row(rr) + c] = A[(int64_t)(i0 + rr) + (int64_t)(i0 + c) * ws.lda];
     }
     __syncthreads();
     {
         // squared norm of rows 2.. of column 0
         R part = 0;
         if (tid >= 2 && tid < M) {
-            const cx<R> x = P[tid * (tid + 1) / 2];
+            const cx<R> x = P[tail_row(tid)];
             part = x.x * x.x + x.y * x.y;
         }
         part = dpp_wave_sum(part);
@@ -737,37 +750,27 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
     __syncthreads();
     for (int c = 0; c + 1 < M; ++c) {
         const int i = i0 + c, mm = M - c - 1;     // trailing order below column c
-        // (A) Procedure 2
-        if (tid == 0) {
-            R sig2 = 0;
-#pragma unroll
-            for (int t = 0; t < TAIL_W; ++t) sig2 += red[t];
-            const cx<R> alpha = P[(c + 1) * (c + 2) / 2 + c];
-            cx<R> tau, scale;
-            R beta;
-            if (sig2 == (R)0 && alpha.y == (R)0) {
-                tau = zero;
-                scale = zero;
-                beta = alpha.x;
-            } else {
-                const R nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
-                beta = (alpha.x >= (R)0) ? -nrm : nrm;
-                tau = mk<R>((beta - alpha.x) / beta, -alpha.y / beta);
-                const R dr = alpha.x - beta, di = alpha.y;
-                const R den = dr * dr + di * di;
-                scale = mk<R>(dr / den, -di / den);
+        // (A) Procedure 2 (wave 0: the sixteen partial norms summed across
+        // lanes, then lane 0)
+        if (wv == 0) {
+            const R sig2 = dpp_sum<TAIL_W>(red[lane & (TAIL_W - 1)]);
+            if (lane == 0) {
+                const cx<R> alpha = P[tail_row(c + 1) + c];
+                cx<R> tau, scale;
+                R beta;
+                reflector_core(alpha, sig2, tau, scale, beta);
+                sref[0] = tau;
+                sref[1] = scale;
+                ws.d[b * n + i] = P[tail_row(c) + c].x;
+                ws.e[b * n + i] = beta;
+                ws.tau[b * n + i] = tau;
             }
-            sref[0] = tau;
-            sref[1] = scale;
-            ws.d[b * n + i] = P[c * (c + 1) / 2 + c].x;
-            ws.e[b * n + i] = beta;
-            ws.tau[b * n + i] = tau;
         }
         __syncthreads();
         const cx<R> tau = sref[0];
         // (B) Procedure 3: v = (1, scale x_1, ...), stored for the back-transformation
         if (tid < mm) {
-            const cx<R> v = tid == 0 ? mk<R>(1, 0) : cmul(sref[1], P[(c + 1 + tid) * (c + 2 + tid) / 2 + c]);
+            const cx<R> v = tid == 0 ? mk<R>(1, 0) : cmul(sref[1], P[tail_row(c + 1 + tid) + c]);
             sv[tid] = v;
             V[(int64_t)(i + 1 + tid) + (int64_t)i * ws.n] = v;
         }
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
             cx<R> acc = zero;
             if (r < mm) {
                 const int gr = c + 1 + r;
-                const cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                const cx<R>* Prow = P + tail_row(gr) + (c + 1);
                 int s2 = q;
                 for (; s2 + 24 <= r; s2 += 32) {
                     cx<R> a4[4], v4[4];
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int gs = c + 1 + s2 + 8 * u;
-                        a4[u] = P[gs * (gs + 1) / 2 + gr];
+                        a4[u] = P[tail_row(gs) + gr];
                         v4[u] = sv[s2 + 8 * u];
                     }
 #pragma unroll
@@ -806,7 +809,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
                 }
                 for (; s2 < mm; s2 += 8) {
                     const int gs = c + 1 + s2;
-                    acc = cfma(cconj(P[gs * (gs + 1) / 2 + gr]), sv[s2], acc);
+                    acc = cfma(cconj(P[tail_row(gs) + gr]), sv[s2], acc);
                 }
             }
             acc.x = dpp_sum<8>(acc.x);
@@ -823,10 +826,10 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
         }
         __syncthreads();
         // (D) Procedure 5: w = y - (tau / 2) (y^H v) v
+        cx<R> dot = sred[lane & (TAIL_W - 1)];
+        dot.x = dpp_sum<TAIL_W>(dot.x);
+        dot.y = dpp_sum<TAIL_W>(dot.y);
         if (tid < mm) {
-            cx<R> dot = zero;
-#pragma unroll
-            for (int t = 0; t < TAIL_W; ++t) dot = cadd(dot, sred[t]);
             const cx<R> k = cscale(cmul(tau, dot), (R)0.5);
             sw[tid] = csub(sy[tid], cmul(k, sv[tid]));
         }
@@ -838,7 +841,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
             if (r < mm) {
                 const int gr = c + 1 + r;
                 const cx<R> vr = sv[r], wr = sw[r];
-                cx<R>* Prow = P + gr * (gr + 1) / 2 + (c + 1);
+                cx<R>* Prow = P + tail_row(gr) + (c + 1);
                 int s2 = q;
                 for (; s2 + 24 <= r; s2 += 32) {
                     cx<R> a4[4], w4[4], v4[4];
@@ -866,7 +869,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
         }
         __syncthreads();
     }
-    if (tid == 0) ws.d[b * n + n - 1] = P[(M - 1) * M / 2 + (M - 1)].x;
+    if (tid == 0) ws.d[b * n + n - 1] = P[tail_row(M - 1) + (M - 1)].x;
 }
 
 }  // namespace
@@ -894,13 +897,14 @@ hipError_t hetrd(hipStream_t st, const HetrdWs<R>& ws0, int64_t nk)
             const int o = i + 1, m = n - o;
             const int NB = (m + ZT - 1) / ZT;
             // The one-tile form when the four-tile form would launch fewer
-            // workgroups than three per CU (its chains of loads are a quarter
-            // as long); the product and the update of a column agree on the
+            // workgroups than ws.slots1 (default three per CU: its chains of
+            // loads are a quarter as long); the product and the update of a column agree on the
             // chunk layout of the partial sums through ws.zch and ws.CHmax
             // (the buffers hold the one-tile form's NBmax chunks per column).
             int nch4 = 0;
             for (int C = 0; C < NB; ++C) nch4 += nchunks(NB, C);
-            ws.zch = (int64_t)nch4 * nk < 3 * 256 ? 1 : ZCH;
+            const int64_t slots1 = ws0.slots1 > 0 ? ws0.slots1 : 3 * 256;
+            ws.zch = (int64_t)nch4 * nk < slots1 ? 1 : ZCH;
             ws.CHmax = ws.zch == 1 ? ws0.NBmax : (ws0.NBmax + ZCH - 1) / ZCH;
             const int nch = ws.zch == 1 ? NB * (NB + 1) / 2 : nch4;
             // Consecutive columns traverse their tiles in opposite orders (odd

@@ -33,6 +33,10 @@ inline void launch_timed(const ProfLaunch& pl, F kernel, dim3 grid, dim3 block, 
 
 // ---------------------------------------------------------------------------
 // matrix products (gemm.hip)
+// Tile policy of the calling thread: products whose 64 x 64 grid has fewer
+// workgroups than `slots` use 32 x 32 tiles; returns the previous value.
+constexpr int GEMM_SMALL_SLOTS_DEFAULT = 256;
+int gemm_small_tile_slots(int slots);
 template <typename R>
 hipError_t cgemm(hipStream_t st, char ta, char tb, int64_t m, int64_t n, int64_t k, cx<R> alpha,
                  const cx<R>* A, int64_t lda, int64_t sA, const cx<R>* B, int64_t ldb, int64_t sB,
@@ -63,6 +67,8 @@ struct HetrdWs {
     int n, nb;
     int NBmax, CHmax;          // 64-row blocks of the largest trailing matrix; chunks per block column
     int zch;                   // tiles per chunk of the Hermitian product (set by hetrd: 4, or 1)
+    int slots1;                // a column takes one-tile chunks when four-tile chunks would launch
+                               // fewer workgroups than this over all problems (0: 768)
     cx<R>* A; int64_t lda, sA; // matrix (lower), reduced in place
     cx<R>* V; int64_t sV;      // reflectors, n x n, ld n (zero outside the reflector rows)
     cx<R>* W; int64_t sW;      // panel W, n x nb, ld n

@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_vectors", ctypes.c_int32),
                 ("panel_nb", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("s_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("streams", ctypes.c_int32),
-                ("s_method", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("s_method", ctypes.c_int32), ("hemv_slots", ctypes.c_int32), ("gemm_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Problem(ctypes.Structure):
@@ -65,7 +66,7 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
            "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device",
            "kgev_solve_k_x_device", "kgev_batch_workspace_bytes", "kgev_solve_batch_device",
-           "kgev_solve_k_device_noalloc", "kgev_stebz_device"]
+           "kgev_solve_k_device_noalloc", "kgev_stebz_device", "kgev_tuned_params"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 PHASE_HEMV, PHASE_GEMM = 1, 2
 S_EIG, S_CHOLESKY, S_PRUNE = 0, 1, 2
@@ -144,6 +145,9 @@ def _load():
     lib.kgev_server_destroy.argtypes = [P]
     lib.kgev_autotune.argtypes = [P, I64, I32, ctypes.POINTER(I32)]
     lib.kgev_autotune.restype = I32
+    lib.kgev_tuned_params.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                      ctypes.POINTER(I32)]
+    lib.kgev_tuned_params.restype = I32
     return lib
 
 
@@ -160,9 +164,11 @@ def _check(fn, st):
 
 
 def make_opts(precision=PREC_FP64, want_vectors=True, panel_nb=0, refine_iters=0, s_tol=0.0,
-              use_graph=False, streams=0, s_method=0) -> Opts:
+              use_graph=False, streams=0, s_method=0, hemv_slots=0, gemm_slots=0) -> Opts:
     o = Opts()
     lib.kgev_opts_default(ctypes.byref(o))
+    o.hemv_slots = hemv_slots
+    o.gemm_slots = gemm_slots
     o.use_graph = 1 if use_graph else 0
     o.streams = streams
     o.s_method = s_method
@@ -420,3 +426,12 @@ def autotune(ctx, n, precision=PREC_FP64) -> int:
     best = ctypes.c_int32()
     _check("kgev_autotune", lib.kgev_autotune(ctx.handle, int(n), int(precision), ctypes.byref(best)))
     return best.value
+
+
+def tuned_params(ctx, n, precision=PREC_FP64):
+    """(panel_nb, hemv_slots, gemm_slots, tuned) that solves of order n use
+    through ctx when the options leave them 0."""
+    nb, hs, gs, tuned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("kgev_tuned_params", lib.kgev_tuned_params(ctx.handle, int(n), int(precision), ctypes.byref(nb),
+                                                       ctypes.byref(hs), ctypes.byref(gs), ctypes.byref(tuned)))
+    return nb.value, hs.value, gs.value, bool(tuned.value)

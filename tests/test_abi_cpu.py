@@ -36,7 +36,8 @@ def test_status_strings_and_defaults():
     assert "converge" in K.status_str(2)
     assert "non-finite" in K.status_str(3)
     o = K.make_opts()
-    assert o.precision == 0 and o.want_vectors == 1 and all(r == 0 for r in o.reserved)
+    assert o.precision == 0 and o.want_vectors == 1 and o.hemv_slots == 0 and o.gemm_slots == 0
+    assert all(r == 0 for r in o.reserved)
 
 
 def test_workspace_bytes_scales_with_problem():
@@ -87,3 +88,9 @@ def test_noalloc_entry_rejects_null_context():
     st = K.lib.kgev_solve_k_device_noalloc(None, ctypes.c_void_p(1), ctypes.c_void_p(1), 4, 4, 1,
                                            ctypes.c_void_p(1), ctypes.c_void_p(1), 4, None, None, None)
     assert st == -1
+
+
+def test_tuned_params_rejects_null_context_and_bad_precision():
+    nb, hs, gs, tuned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert K.lib.kgev_tuned_params(None, 100, 0, ctypes.byref(nb), ctypes.byref(hs), ctypes.byref(gs),
+                                   ctypes.byref(tuned)) == -1
