@@ -180,7 +180,7 @@ def serve_stream(args, K, G, torch, dev):
     max_inflight, max_bytes = 48, 64 << 30
     budget = 140 << 30          # the server's workspace budget; inputs and outputs live beside it
 
-    def run(arrivals, what):
+    def run(arrivals, what, reqs=reqs):
         from collections import deque
         res = [None] * len(reqs)
         with K.Server(0, budget, args.serve_slots) as srv:
@@ -216,10 +216,12 @@ def serve_stream(args, K, G, torch, dev):
             t1 = time.perf_counter()
         return res, t1 - t0
 
-    # closed loop (everything queued at t = 0) gives the saturation rate
-    log(f"[serve] closed loop, {len(reqs)} requests")
-    res, span = run([0.0] * len(reqs), "closed loop")
-    sat = len(reqs) / span
+    # closed loop (everything queued at t = 0) gives the saturation rate, on
+    # the first --serve-sat requests of the stream (all of them by default)
+    nsat = min(len(reqs), args.serve_sat) if args.serve_sat > 0 else len(reqs)
+    log(f"[serve] closed loop, {nsat} requests")
+    res, span = run([0.0] * nsat, "closed loop", reqs[:nsat])
+    sat = nsat / span
     lam = 0.8 * sat
     gaps = rng.exponential(1.0 / lam, len(reqs))
     arrivals = np.cumsum(gaps) - gaps[0]
@@ -228,7 +230,7 @@ def serve_stream(args, K, G, torch, dev):
     lat = np.array([1e3 * (r.t_done - r.t_submit) for r in res])
     solves = sum(nk for _, nk in reqs)
     return {"requests": len(reqs), "slots": args.serve_slots, "orders": sizes,
-            "saturation_requests_per_s": sat, "arrival_rate_requests_per_s": lam,
+            "saturation_requests": nsat, "saturation_requests_per_s": sat, "arrival_rate_requests_per_s": lam,
             "solves_per_s": solves / span, "latency_ms_p50": float(np.percentile(lat, 50)),
             "latency_ms_p99": float(np.percentile(lat, 99)),
             "status_all_ok": all(r.status == 0 for r in res)}
@@ -273,6 +275,8 @@ def main():
     ap.add_argument("--serve", type=int, default=64,
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-sat", type=int, default=0,
+                    help="requests of the closed-loop run that measures the saturation rate (0: all)")
     ap.add_argument("--serve-nmax", type=int, default=2000)
     ap.add_argument("--panel-nb", type=int, default=0,
                     help="Householder panel width (0: the library default, or the tuned width with --autotune)")
