@@ -156,14 +156,17 @@ def roofline_object(prof, phase, elapsed, note, traffic, K):
 
 
 def serve_stream(args, K, G, torch, dev):
-    """Serving workload: requests with n log-uniform in [256, nmax] (drawn from
-    a pool of 6 log-spaced orders) and 1..16 k-points, arriving as a Poisson
-    process at 80% of the closed-loop saturation rate of the same mix.  Each
-    pool order has one seeded LCAO pencil, replicated over the request's
-    k-points (the cost of a k-point does not depend on which k it is)."""
+    """Serving workload: requests with n log-uniform in [256, nmax] (the order
+    taken at the centre of one of --serve-bins equal bins of log n, so the
+    pool's mean cost matches the continuous distribution's) and 1..16
+    k-points, arriving as a Poisson process at 80% of the closed-loop
+    saturation rate of the same mix.  Each pool order has one seeded LCAO
+    pencil, replicated over the request's k-points (the cost of a k-point
+    does not depend on which k it is)."""
     import math
     rng = np.random.default_rng(5005)
-    sizes = sorted({int(round(math.exp(x))) for x in np.linspace(math.log(256), math.log(args.serve_nmax), 6)})
+    lo, hi, nb = math.log(256), math.log(args.serve_nmax), args.serve_bins
+    sizes = sorted({int(round(math.exp(lo + (i + 0.5) * (hi - lo) / nb))) for i in range(nb)})
     log(f"[serve] pool orders {sizes}")
     pool = {}
     for n in sizes:
@@ -275,6 +278,8 @@ def main():
     ap.add_argument("--serve", type=int, default=64,
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-bins", type=int, default=6,
+                    help="pool orders: the centres of this many equal bins of log n in [256, --serve-nmax]")
     ap.add_argument("--serve-sat", type=int, default=0,
                     help="requests of the closed-loop run that measures the saturation rate (0: all)")
     ap.add_argument("--serve-nmax", type=int, default=2000)

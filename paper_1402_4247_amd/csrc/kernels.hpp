@@ -111,7 +111,6 @@ struct DcWs {
     int* status;         // per problem (may be null)
 };
 
-int dc_levels(int64_t n);
 hipError_t stedc(hipStream_t st, const DcWs& ws, double* w, double* Z, double* Qscratch, int64_t nk);
 
 // eigenvalues only of nk tridiagonals (d, e with stride sde; e[i] couples

@@ -46,6 +46,13 @@ template <int M> __device__ inline double lane_xor(double v)
 {
     return __hiloint2double(lane_xor<M>(__double2hiint(v)), lane_xor<M>(__double2loint(v)));
 }
+// the value of lane l (wave-uniform l) in every lane
+__device__ inline int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline double lane_read(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
 // broadcast of lane Q of each quad
 template <int Q, typename T> __device__ inline T quad_bcast(T v)
 {

@@ -2,9 +2,12 @@
 // Eigen_HH (Section III of arXiv:1402.4247 calls a LAPACK routine there; the
 // paper does not fix which).  Divide and conquer, batched over k-points:
 //
-//  * Cuppen's rank-one tearing down to 1x1 leaves: at a split between rows
-//    mid-1 and mid, T = diag(T1', T2') + |beta| u u^T with u = e_{mid-1} +
-//    sign(beta) e_mid and the two corner diagonal entries lowered by |beta|;
+//  * Cuppen's rank-one tearing down to leaves of at most LEAF rows: at a split
+//    between rows mid-1 and mid, T = diag(T1', T2') + |beta| u u^T with
+//    u = e_{mid-1} + sign(beta) e_mid and the two corner diagonal entries
+//    lowered by |beta|;
+//  * each leaf solved by implicit QL with Wilkinson shifts (Bowdler, Martin,
+//    Reinsch & Wilkinson 1968), one wave per leaf;
 //  * per merge: z = Q^T u / sqrt(2), rho = 2 |beta|, deflation of negligible
 //    z components and of close pole pairs by Givens rotations (Dongarra &
 //    Sorensen 1987);
@@ -43,10 +46,27 @@ __device__ inline Seg seg_of(int64_t j, int64_t n, int t)
     return g;
 }
 
+constexpr int LEAF = 16;   // largest leaf of the tree
+
+// depth of the leaves: the smallest depth whose segments have at most LEAF rows
+__host__ __device__ inline int dc_leaf_depth(int64_t n)
+{
+    int t = 0;
+    while (((int64_t)LEAF << t) < n) ++t;
+    return t;
+}
+
+// row i starts a segment at depth t (i > 0: the boundary before it is torn)
+__device__ inline bool starts_segment(int64_t i, int64_t n, int t)
+{
+    const int64_t j = ((i << t) + n - 1) / n;      // smallest j with j n / 2^t >= i
+    return seg_bound(j, n, t) == i;
+}
+
 // ---------------------------------------------------------------------------
-// Scale T to max |entry| = 1, lower the diagonal by the rank-one tears of every
-// 1x1 leaf boundary, set Q = I and D = the leaf eigenvalues.
-__global__ __launch_bounds__(256) void dc_init(DcWs ws)
+// Scale T to max |entry| = 1 and lower the diagonal by the rank-one tears of
+// the leaf boundaries (depth tl); D = the torn diagonal.
+__global__ __launch_bounds__(256) void dc_init(DcWs ws, int tl)
 {
     __shared__ double sh[4];
     const int64_t b = blockIdx.x;
@@ -69,10 +89,119 @@ __global__ __launch_bounds__(256) void dc_init(DcWs ws)
     double* es = ws.es + b * ws.n;
     for (int i = threadIdx.x; i < n; i += 256) {
         double v = d[i] * inv;
-        if (i > 0) v -= fabs(e[i - 1] * inv);
-        if (i + 1 < n) v -= fabs(e[i] * inv);
+        if (i > 0 && starts_segment(i, n, tl)) v -= fabs(e[i - 1] * inv);
+        if (i + 1 < n && starts_segment(i + 1, n, tl)) v -= fabs(e[i] * inv);
         D[i] = v;
         es[i] = (i + 1 < n) ? e[i] * inv : 0.0;
+    }
+}
+
+// d (double) of lane i: a wave-uniform read of a lane-distributed array
+__device__ inline double rdl(double v, int i) { return lane_read(v, i); }
+
+// ---------------------------------------------------------------------------
+// Leaf eigensolver: one wave per leaf segment (at most LEAF rows) of the torn
+// tridiagonal, implicit QL with Wilkinson shifts.  Lane i holds d_i and e_i
+// (e_i couples leaf rows i and i + 1); the recurrences of a QL sweep run on
+// wave-uniform values read with readlane and written back by lane select,
+// and the sweep's rotations are kept one per lane and applied afterwards to
+// the rows of the eigenvector matrix (row k in LDS, lane k): the column
+// carried from one rotation to the next stays in a register.  A sub-diagonal
+// entry is negligible when adding it to the running norm tst1 = max(|d_l| +
+// |e_l|) leaves tst1 unchanged.  Eigenvalues go to D[0] ascending, the
+// eigenvectors to the leaf's diagonal block of Q[0] (the rest of Q[0] is the
+// identity's zeros).
+__global__ __launch_bounds__(64) void dc_leaf(DcWs ws, int tl)
+{
+    __shared__ double Zs[LEAF][LEAF + 1];
+    const int64_t b = blockIdx.y;
+    const int64_t n = ws.n;
+    const Seg g = seg_of(blockIdx.x, n, tl);
+    const int s = (int)g.s, ns = (int)(g.e - g.s);
+    if (ns < 1) return;
+    const int lane = threadIdx.x;
+    double* D = ws.D[0] + b * n;
+    const double* es = ws.es + b * n;
+    double dr = lane < ns ? D[s + lane] : 0.0;
+    double er = lane + 1 < ns ? es[s + lane] : 0.0;
+    if (lane < ns)
+        for (int j = 0; j < ns; ++j) Zs[lane][j] = (lane == j) ? 1.0 : 0.0;
+    double cr = 0.0, sr = 0.0;     // lane i: rotation i of the current sweep
+    bool conv = true;
+    double f = 0.0, tst1 = 0.0;
+    for (int l = 0; l < ns; ++l) {
+        tst1 = fmax(tst1, fabs(rdl(dr, l)) + fabs(rdl(er, l)));
+        for (int it = 0;; ++it) {
+            int m = l;
+            while (m < ns - 1 && tst1 + fabs(rdl(er, m)) != tst1) ++m;
+            if (m == l) break;
+            if (it == 30) {
+                conv = false;
+                break;
+            }
+            // shift: the eigenvalue of the leading 2 x 2 nearer d_l
+            const double gl = rdl(dr, l), el = rdl(er, l);
+            double p = (rdl(dr, l + 1) - gl) / (2.0 * el);
+            double r = hypot(p, 1.0);
+            const double pr = p + copysign(r, p);
+            const double dl = el / pr, dl1 = el * pr;
+            const double h = gl - dl;
+            dr = (lane == l) ? dl : (lane == l + 1) ? dl1 : (lane > l + 1) ? dr - h : dr;
+            f += h;
+            // the sweep from row m up to row l
+            p = rdl(dr, m);
+            double c = 1.0, c2 = 1.0, c3 = 1.0, sn = 0.0, s2 = 0.0;
+            const double el1 = rdl(er, l + 1);
+            for (int i = m - 1; i >= l; --i) {
+                c3 = c2;
+                c2 = c;
+                s2 = sn;
+                const double ei = rdl(er, i), di = rdl(dr, i);
+                const double gg = c * ei, hh = c * p;
+                // |p| and |e_i| are O(1) on the scaled matrix: the squares
+                // cannot overflow; hypot where they could underflow
+                const double t2 = fma(p, p, ei * ei);
+                r = t2 > 1e-280 ? sqrt(t2) : hypot(p, ei);
+                const double ir = 1.0 / r;
+                const double ei1 = sn * r;
+                sn = ei * ir;
+                c = p * ir;
+                p = c * di - sn * gg;
+                const double di1 = hh + sn * (c * gg + sn * di);
+                er = (lane == i + 1) ? ei1 : er;
+                dr = (lane == i + 1) ? di1 : dr;
+                cr = (lane == i) ? c : cr;
+                sr = (lane == i) ? sn : sr;
+            }
+            p = -sn * s2 * c3 * el1 * rdl(er, l) / dl1;
+            er = (lane == l) ? sn * p : er;
+            dr = (lane == l) ? c * p : dr;
+            if (lane < ns) {
+                double carry = Zs[lane][m];
+                for (int i = m - 1; i >= l; --i) {
+                    const double zi = Zs[lane][i];
+                    const double ci = rdl(cr, i), si = rdl(sr, i);
+                    Zs[lane][i + 1] = si * zi + ci * carry;
+                    carry = ci * zi - si * carry;
+                }
+                Zs[lane][l] = carry;
+            }
+        }
+        dr = (lane == l) ? dr + f : dr;
+        er = (lane == l) ? 0.0 : er;
+    }
+    if (!conv && lane == 0 && ws.status) atomicOr(ws.status + b, ST_NOCONV);
+    // ascending order: the rank of lane j's value (ties by index)
+    int rank = 0;
+    for (int k = 0; k < ns; ++k) {
+        const double dk = rdl(dr, k);
+        rank += (dk < dr || (dk == dr && k < lane)) ? 1 : 0;
+    }
+    if (lane < ns) D[s + rank] = dr;
+    double* Q = ws.Q[0] + b * ws.sQ;
+    for (int j = 0; j < ns; ++j) {
+        const int rj = __builtin_amdgcn_readlane(rank, j);
+        if (lane < ns) Q[(int64_t)(s + lane) + (int64_t)(s + rj) * n] = Zs[lane][j];
     }
 }
 
@@ -592,24 +721,19 @@ __global__ __launch_bounds__(256) void dc_finish(DcWs ws, int fb, double* w)
 
 }  // namespace
 
-int dc_levels(int64_t n)
-{
-    int L = 0;
-    while (((int64_t)1 << L) < n) ++L;
-    return L;
-}
-
 hipError_t stedc(hipStream_t st, const DcWs& ws0, double* w, double* Z, double* Qscratch, int64_t nk)
 {
     DcWs ws = ws0;
     const int64_t n = ws.n;
     if (n < 1 || nk < 1) return hipSuccess;
-    const int L = dc_levels(n);
-    // the last level writes buffer L & 1: make that the caller's Z
+    const int L = dc_leaf_depth(n);
+    // the leaves write buffer 0 and the last merge level buffer L & 1: make
+    // that the caller's Z
     ws.Q[L & 1] = Z;
     ws.Q[(L & 1) ^ 1] = Qscratch;
-    hipLaunchKernelGGL(dc_init, dim3((unsigned)nk), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(dc_init, dim3((unsigned)nk), dim3(256), 0, st, ws, L);
     hipLaunchKernelGGL(dc_eye, dim3((unsigned)((n * n + 255) / 256), (unsigned)nk), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(dc_leaf, dim3(1u << L, (unsigned)nk), dim3(64), 0, st, ws, L);
     for (int t = L - 1; t >= 0; --t) {
         const int rb = (L - t - 1) & 1, wb = (L - t) & 1;
         const unsigned segs = 1u << t;
