@@ -1,5 +1,6 @@
 // Shared device helpers of the HIP library: complex arithmetic on interleaved
-// (re, im) pairs, wave-level reductions and the MFMA wrappers.  gfx950 only.
+// (re, im) pairs, buffer loads and the MFMA wrappers (cross-lane reductions:
+// lanes.hpp).  gfx950 only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,27 +86,6 @@ template <typename C> __device__ inline C csel(bool c, C a, C b)
     r.x = c ? a.x : b.x;
     r.y = c ? a.y : b.y;
     return r;
-}
-
-// ---------------------------------------------------------------------------
-// wave reductions (64 lanes)
-__device__ inline double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
-}
-__device__ inline float wave_sum(float v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
-}
-__device__ inline double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
-    return v;
 }
 
 // ---------------------------------------------------------------------------

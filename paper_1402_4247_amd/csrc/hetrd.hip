@@ -101,15 +101,7 @@ __device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV],
     }
 }
 
-// r + r(lane ^ MASK): through the LDS unit (the Hermitian-product kernel's
-// column sums), and as vector-ALU lane exchanges (everywhere else)
-template <int MASK, typename R>
-__device__ __attribute__((always_inline)) inline cx<R> xor_add(cx<R> r)
-{
-    r.x += __shfl_xor(r.x, MASK, WAVE);
-    r.y += __shfl_xor(r.y, MASK, WAVE);
-    return r;
-}
+// r + r(lane ^ MASK), as vector-ALU lane exchanges
 template <int MASK, typename R>
 __device__ __attribute__((always_inline)) inline cx<R> xor_add_v(cx<R> r)
 {
@@ -265,9 +257,9 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
             cx<R> cs = czero<cx<R>>();
 #pragma unroll
             for (int r = 0; r < 8; ++r) cs = cadd(cs, sP[w][c][r0 + r]);
-            cs = xor_add<8, R>(cs);
-            cs = xor_add<16, R>(cs);
-            cs = xor_add<32, R>(cs);
+            cs = xor_add_v<8, R>(cs);
+            cs = xor_add_v<16, R>(cs);
+            cs = xor_add_v<32, R>(cs);
             if (lane < 8) sT[w][g * 8 + lane] = cs;
             __builtin_amdgcn_wave_barrier();
         }
@@ -276,14 +268,14 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
     } else {
         sT[w][lane] = czero<cx<R>>();
     }
-    qd = wave_sum(qd);
+    qd = dpp_wave_sum(qd);
     if (lane == 0) sq[w] = qd;
     __syncthreads();
     if (tid < ZT) {
         const cx<R> s = cadd(cadd(sT[0][tid], sT[1][tid]), cadd(sT[2][tid], sT[3][tid]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
         R qt = svC[tid].x * s.x + svC[tid].y * s.y;
-        qt = wave_sum(qt);
+        qt = dpp_wave_sum(qt);
         if (tid == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
 }
