@@ -59,6 +59,7 @@ METRIC = "k-point eigensolves/s at n=2000 (FP64 vs FP32+refine); p50/p99 latency
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hetrd_zhemv_n2000_nk16_traffic.md")
+MFMA_FILE = os.path.join(HERE, "profiles", "cgemm_n2000_nk16_mfma_counters.md")
 CSRC = os.path.join(HERE, "paper_1402_4247_amd", "csrc")
 
 
@@ -86,6 +87,41 @@ def zhemv_source_sha256():
     with open(os.path.join(CSRC, "common.hpp"), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()
+
+
+def gemm_source_sha256():
+    """SHA-256 of gemm.hip followed by common.hpp (the complex-product kernel
+    and the helpers it uses)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "common.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def summary_fields(path):
+    """The `key: value` lines of a committed counter summary."""
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    return fields
+
+
+def counter_mfma(n, nk):
+    """FP64 MFMA work rate of the complex products from the committed
+    rocprofv3 counter summary, or None when the workload differs or the
+    product kernel's source has changed since the counters were taken."""
+    if (n, nk) != (2000, 16) or not os.path.exists(MFMA_FILE):
+        return None
+    fields = summary_fields(MFMA_FILE)
+    if fields.get("source_sha256") != gemm_source_sha256():
+        return None
+    return {"tflops": float(fields["mfma_tflops"]), "frac": float(fields["mfma_frac"]),
+            "counters": fields.get("counters"), "source": os.path.relpath(MFMA_FILE, HERE)}
 
 
 def counter_traffic(n, nk):
@@ -385,6 +421,9 @@ def main():
         prof2 = K.profile_end(ctx)
         roof2 = roofline_object(prof2, ph2, el2, f"every {args.time_stride}-th launch of {args.gemm_steps} "
                                 "untimed step(s) after the timed region", None, K)
+        mc = counter_mfma(n, nk)
+        if mc is not None:
+            roof2["mfma_counters"] = mc
         log(f"[bench] second roofline: {roof2['kernel']} {roof2['achieved']} {roof2['unit']}")
 
     # latency of single-k-point calls

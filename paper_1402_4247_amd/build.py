@@ -1,8 +1,10 @@
 """Build the HIP library libkgev.so (gfx950) in-tree.
 
 ``python -m paper_1402_4247_amd.build`` compiles every ``csrc/*.hip`` with
-hipcc into ``_build/`` and links ``paper_1402_4247_amd/libkgev.so``.  Packed
-FP32 instructions are disabled for all device code.
+hipcc into ``_build/`` and links ``paper_1402_4247_amd/libkgev.so``, then
+the native command-line driver ``paper_1402_4247_amd/kgev_driver`` (host
+code only, linked to the library).  Packed FP32 instructions are disabled for
+all device code.
 """
 from __future__ import annotations
 
@@ -15,6 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libkgev.so")
+DRIVER = os.path.join(PKG, "kgev_driver")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -54,8 +57,17 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    # the driver: plain C++ against the C ABI and the HIP runtime API
+    dtmp = DRIVER + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", os.path.join(PKG, "driver.cpp"), "-o", dtmp, "-L", PKG, "-lkgev",
+           "-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(dtmp, DRIVER)
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} and {DRIVER}")
     return OUT
 
 

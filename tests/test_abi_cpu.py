@@ -94,3 +94,11 @@ def test_tuned_params_rejects_null_context_and_bad_precision():
     nb, hs, gs, tuned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert K.lib.kgev_tuned_params(None, 100, 0, ctypes.byref(nb), ctypes.byref(hs), ctypes.byref(gs),
                                    ctypes.byref(tuned)) == -1
+
+
+def test_driver_is_built_and_rejects_unknown_options():
+    import subprocess
+    drv = os.path.join(ROOT, "paper_1402_4247_amd", "kgev_driver")
+    assert os.path.exists(drv)
+    r = subprocess.run([drv, "--bogus", "1"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage" in r.stderr

@@ -15,10 +15,15 @@ plain PyTorch products on the device (independent of the library's
 kernels): r_res = ||H C - S C diag(w)||_F / ||H||_F <= 1e-12 and
 max |C^H S C - I| <= 1e-12, eigenvalues ascending.  Sampled k-points are
 compared with the oracle's eigenvalues (1e-10 relative), where the oracle
-finishes in seconds (n <= 2000); at the benchmark size one k-point's
+finishes in seconds (n <= 2000), and with stored oracle eigenvalues at
+n = 3000 and n = 4096 (k-point 0; tests/golden/oracle_eig_lcao_*.txt, written
+by tests/golden/make_oracle_fixtures.py, which calls only the oracle); at
+the benchmark size one k-point's
 eigenvectors are compared with the oracle's as well (phase-invariant
 S-overlap of every column whose eigenvalue is separated from its
 neighbours)."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -72,6 +77,18 @@ def check_all(dH, dS, dw, dC, st, what):
     return w
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_eigs(name, w, what):
+    """Eigenvalues of k-point 0 against the stored oracle values."""
+    w0 = np.loadtxt(os.path.join(GOLDEN, name))
+    assert w0.shape == w.shape
+    err = np.abs(w - w0).max() / np.abs(w0).max()
+    print(f"{what}: k=0 eigenvalues vs stored oracle {err:.2e}", flush=True)
+    assert err <= TOL_EIG
+
+
 def oracle_eigs(Hs, Ss, w, ks, what):
     for k in ks:
         s0, w0, _ = O.solve_k(Hs[k], Ss[k], vectors=False)
@@ -109,7 +126,8 @@ def test_lcao_n3000_one_k():
     dH, dS = to_dev(Hs), to_dev(Ss)
     with kg.Context(0) as ctx:
         dw, dC, st = solve(ctx, dH, dS, n, nk, kg.make_opts())
-    check_all(dH, dS, dw, dC, st, "n=3000 x1")
+    w = check_all(dH, dS, dw, dC, st, "n=3000 x1")
+    golden_eigs("oracle_eig_lcao_n3000_k0.txt", w[0], "n=3000 x1")
 
 
 @pytest.mark.timeout(600)
@@ -180,3 +198,5 @@ def test_mixed_n4096_8k_against_fp64_path():
     diff = np.abs(wmh - w64h).max() / np.abs(w64h).max()
     print(f"n=4096 x8: mixed vs fp64 eigenvalues {diff:.2e}", flush=True)
     assert diff <= TOL_EIG
+    golden_eigs("oracle_eig_lcao_n4096_k0.txt", w64h[0], "n=4096 x8 fp64")
+    golden_eigs("oracle_eig_lcao_n4096_k0.txt", wmh[0], "n=4096 x8 fp32+refine")
