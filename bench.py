@@ -33,6 +33,10 @@ Extra fields:
   eigenvalues_only
                 the same batch without eigenvectors (Band_DFT_Col's first
                 pass: Part 4's tridiagonal step by bisection);
+  other_workloads
+                the batched-k workload (n = 1024, the 64 k-points of the 4x4x4
+                grid in one call, autotuned) and the mixed-precision workload
+                (n = 4096, 8 k-points, FP64 and FP32+refine), a few calls each;
   x_reuse       the batch with Part 2's X(k) exported by an earlier call and
                 reused (an SCF iteration after the first: S(k) unchanged);
   host_path     the host-pointer entry point (kgev_solve_k) on the same batch
@@ -275,6 +279,90 @@ def serve_stream(args, K, G, torch, dev):
             "status_all_ok": all(r.status == 0 for r in res)}
 
 
+def device_residuals(torch, dH, dS, dw, dC, k):
+    """r_res and max |C^H S C - I| of k-point k with torch products on the
+    device (column-major buffers)."""
+    H = dH[k].transpose(0, 1).contiguous()
+    S = dS[k].transpose(0, 1).contiguous()
+    C = dC[k].transpose(0, 1).contiguous()
+    SC = S @ C
+    R = H @ C - SC * dw[k].to(torch.complex128)[None, :]
+    r_res = float(torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(H))
+    CSC = C.conj().transpose(0, 1).contiguous() @ SC
+    r_orth = float((CSC - torch.eye(C.shape[0], dtype=torch.complex128, device=C.device)).abs().max())
+    return r_res, r_orth
+
+
+def other_configs(args, K, G, torch, dev, ctx):
+    """The batched-k workload (n = 1024, the 64 k-points of the 4x4x4 grid,
+    autotuned) and the mixed-precision workload (n = 4096, the 8 k-points of
+    the 2x2x2 grid, FP64 and complex64 reduction + FP64 refinement), a few
+    timed calls each after one untimed call."""
+    out = {}
+
+    def timed(n, nk, dH, dS, opts, steps):
+        dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
+        dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
+        st = torch.zeros(nk, dtype=torch.int32, device=dev)
+        ms = []
+        for r in range(steps + 1):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            rc = K.solve_k_device(ctx, dH, dS, n, n, nk, dw, dC, n, d_status=st, opts=opts)
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError(f"solve n={n} nk={nk} returned {rc}")
+            if r >= 1:
+                ms.append(1e3 * (time.perf_counter() - a))
+        return dw, dC, st, float(np.mean(ms))
+
+    if args.config3_steps > 0:
+        n, nk = 1024, 64
+        log(f"[bench] batched-k workload n={n} nk={nk}: generating, autotuning")
+        Hs, Ss = G.config3(n, nk, 3003)
+        dH = torch.from_numpy(G.colmajor(Hs)).to(dev)
+        dS = torch.from_numpy(G.colmajor(Ss)).to(dev)
+        del Hs, Ss
+        nb = K.autotune(ctx, n)
+        _, hs, gs, _ = K.tuned_params(ctx, n)
+        dw, dC, st, ms = timed(n, nk, dH, dS, K.make_opts(), args.config3_steps)
+        r_res, r_orth = device_residuals(torch, dH, dS, dw, dC, 0)
+        out["batched_n1024_nk64"] = {
+            "value": nk * 1e3 / ms, "unit": "solves/s", "ms_per_call": ms, "calls": args.config3_steps,
+            "workload": "LCAO pencil n=1024, the 64 k-points of the 4x4x4 grid in one call, seed 3003",
+            "tuned": {"panel_nb": nb, "hemv_slots": hs, "gemm_slots": gs},
+            "status_all_ok": bool(np.all(st.cpu().numpy() == 0)), "r_res_k0": r_res, "r_orth_k0": r_orth}
+        log(f"[bench] batched-k workload {out['batched_n1024_nk64']['value']:.1f} solves/s")
+        del dH, dS, dw, dC
+    if args.config4_steps > 0:
+        n, nk = 4096, 8
+        log(f"[bench] mixed-precision workload n={n} nk={nk}: generating")
+        Hs, Ss = G.config4(n, nk, 4004)
+        dH = torch.from_numpy(G.colmajor(Hs)).to(dev)
+        dS = torch.from_numpy(G.colmajor(Ss)).to(dev)
+        del Hs, Ss
+        dw, dC, st, ms = timed(n, nk, dH, dS, K.make_opts(), args.config4_steps)
+        r_res, r_orth = device_residuals(torch, dH, dS, dw, dC, 0)
+        w64 = dw.cpu().numpy()
+        ok64 = bool(np.all(st.cpu().numpy() == 0))
+        del dC
+        dwm, dCm, stm, msm = timed(n, nk, dH, dS, K.make_opts(precision=K.PREC_FP32_REFINE), args.config4_steps)
+        rm_res, rm_orth = device_residuals(torch, dH, dS, dwm, dCm, 0)
+        wm = dwm.cpu().numpy()
+        out["mixed_n4096_nk8"] = {
+            "workload": "LCAO pencil n=4096, the 8 k-points of the 2x2x2 grid in one call, seed 4004",
+            "fp64": {"value": nk * 1e3 / ms, "unit": "solves/s", "ms_per_call": ms, "calls": args.config4_steps,
+                     "status_all_ok": ok64, "r_res_k0": r_res, "r_orth_k0": r_orth},
+            "fp32_refine": {"value": nk * 1e3 / msm, "unit": "solves/s", "ms_per_call": msm,
+                            "calls": args.config4_steps, "status_all_ok": bool(np.all(stm.cpu().numpy() == 0)),
+                            "r_res_k0": rm_res, "r_orth_k0": rm_orth,
+                            "eig_diff_vs_fp64_rel": float(np.abs(wm - w64).max() / np.abs(w64).max())}}
+        log(f"[bench] mixed-precision workload: fp64 {nk * 1e3 / ms:.2f}, fp32+refine {nk * 1e3 / msm:.2f} solves/s")
+        del dH, dS, dwm, dCm
+    torch.cuda.empty_cache()
+    return out or None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +402,11 @@ def main():
     ap.add_argument("--serve", type=int, default=64,
                     help="also run the serving stream with this many requests (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--config3-steps", type=int, default=3,
+                    help="timed calls of the batched-k workload (n=1024, 64 k-points, autotuned; 0 skips it)")
+    ap.add_argument("--config4-steps", type=int, default=2,
+                    help="timed calls of the mixed-precision workload (n=4096, 8 k-points, FP64 and "
+                         "FP32+refine; 0 skips it)")
     ap.add_argument("--serve-bins", type=int, default=6,
                     help="pool orders: the centres of this many equal bins of log n in [256, --serve-nmax]")
     ap.add_argument("--serve-sat", type=int, default=0,
@@ -654,6 +747,7 @@ def main():
         log(f"[bench] host-pointer path {host['value']:.2f} solves/s")
 
     serving = serve_stream(args, K, G, torch, dev) if args.serve > 0 else None
+    others = other_configs(args, K, G, torch, dev, ctx)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -700,6 +794,7 @@ def main():
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "reps": int(lat.size), "nk": 1} if args.latency_reps > 0 else None),
         "latency_n128_ms": lat128,
+        "other_workloads": others,
         "check": check,
     }
     ctx.close()
