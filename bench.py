@@ -414,6 +414,10 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=2000)
     ap.add_argument("--panel-nb", type=int, default=0,
                     help="Householder panel width (0: the library default, or the tuned width with --autotune)")
+    ap.add_argument("--hemv-slots", type=int, default=0,
+                    help="Hermitian-product tile grouping threshold (opts.hemv_slots; 0: tuned or default)")
+    ap.add_argument("--gemm-slots", type=int, default=0,
+                    help="product tile threshold (opts.gemm_slots; 0: tuned or default)")
     ap.add_argument("--graph-steps", type=int, default=3,
                     help="steps of graph replay (the solve captured once as a HIP graph) reported beside the "
                          "kernel-by-kernel headline; 0 skips it")
@@ -455,7 +459,7 @@ def main():
     dw = torch.zeros((nk, n), dtype=torch.float64, device=dev)
     dC = torch.zeros((nk, n, n), dtype=torch.complex128, device=dev)
     dst = torch.zeros(nk, dtype=torch.int32, device=dev)
-    opts = K.make_opts(panel_nb=args.panel_nb)
+    opts = K.make_opts(panel_nb=args.panel_nb, hemv_slots=args.hemv_slots, gemm_slots=args.gemm_slots)
     ctx = K.Context(0)
     tuned_nb = None
     if args.autotune:
@@ -663,7 +667,8 @@ def main():
     # the same batch in graph mode: captured once (untimed), then replayed
     graph = None
     if args.graph_steps > 0:
-        og = K.make_opts(panel_nb=args.panel_nb, use_graph=True)
+        og = K.make_opts(panel_nb=args.panel_nb, hemv_slots=args.hemv_slots, gemm_slots=args.gemm_slots,
+                         use_graph=True)
         gs = torch.cuda.Stream()
         wg = torch.zeros_like(dw)
         Cg = torch.zeros_like(dC)
@@ -787,7 +792,8 @@ def main():
                                 f"eigenvalues uniform in [-1, 1]), n={n}, {nk} independent pencils, complex128, all "
                                 "eigenpairs"),
                    "n": n, "nk": nk, "precision": "fp64", "seed": args.seed,
-                   "panel_nb": args.panel_nb or tuned_nb or 32, "hemv_slots": hemv_slots, "gemm_slots": gemm_slots,
+                   "panel_nb": args.panel_nb or tuned_nb or 32, "hemv_slots": args.hemv_slots or hemv_slots,
+                   "gemm_slots": args.gemm_slots or gemm_slots,
                    "autotuned": bool(args.autotune)},
         "roofline": roof, "roofline_gemm": roof2, "cpu_baseline": cpu, "graph_replay": graph, "fp32_refine": mixed, "eigenvalues_only": values, "cholesky_s": chol,
         "host_path": host, "x_reuse": xreuse, "serving": serving,
