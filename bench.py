@@ -72,24 +72,26 @@ def log(*a):
 
 
 def zhemv_source_sha256():
-    """SHA-256 of the Hermitian-product kernel's own source text (the
-    hetrd_zhemv template in hetrd.hip, from its template line to its closing
-    brace) followed by common.hpp, whose helpers it uses; None if the kernel
-    is not found."""
+    """SHA-256 of the Hermitian-product kernels' own source text (the
+    hetrd_zhemv and hetrd_zhemv_tile templates in hetrd.hip, each from its
+    template line to its closing brace) followed by common.hpp and lanes.hpp,
+    whose helpers they use; None if a kernel is not found."""
     import hashlib
     with open(os.path.join(CSRC, "hetrd.hip")) as fh:
         text = fh.read()
-    k = text.find(" void hetrd_zhemv(")
-    if k < 0:
-        return None
-    i0 = text.rfind("template <", 0, k)
-    i1 = text.find("\n}\n", k)
-    if i0 < 0 or i1 < 0:
-        return None
-    i1 += 3
-    h = hashlib.sha256(text[i0:i1].encode())
-    with open(os.path.join(CSRC, "common.hpp"), "rb") as fh:
-        h.update(fh.read())
+    h = hashlib.sha256()
+    for name in (" void hetrd_zhemv(", " void hetrd_zhemv_tile("):
+        k = text.find(name)
+        if k < 0:
+            return None
+        i0 = text.rfind("template <", 0, k)
+        i1 = text.find("\n}\n", k)
+        if i0 < 0 or i1 < 0:
+            return None
+        h.update(text[i0:i1 + 3].encode())
+    for hdr in ("common.hpp", "lanes.hpp"):
+        with open(os.path.join(CSRC, hdr), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 

@@ -86,7 +86,7 @@ struct SolvePlan {
     int slots1;                // Hermitian-product tile grouping threshold (HetrdWs::slots1)
     int NBmax, CHmax, PN;
     // complex128 arrays
-    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, pvv, qpart, uwork, cwork, ppart, ndrop;
+    size_t Aw, Vs, X, G, Wp, tau, ypart, ypartT, pvw, qpart, uwork, cwork, ppart, ndrop;
     // real / int arrays
     size_t d, e, sS, wA, pnorm, Zr, Qs, Vsec;
     size_t dc_es, dc_onrm, dc_D0, dc_D1, dc_sd, dc_sz, dc_ndd, dc_ndz, dc_dfd, dc_rotc, dc_rots, dc_rho, dc_tauv,
@@ -96,7 +96,7 @@ struct SolvePlan {
     // mixed precision: complex64 tridiagonalisation / back-transformation
     // buffers and the FP64 refinement scratch (size 0 in the FP64 form)
     bool mixed;
-    size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_pvv, f_qpart, f_uwork, f_d, f_e, f_pnorm;
+    size_t f_A, f_V, f_Y, f_W, f_tau, f_ypart, f_ypartT, f_pvw, f_qpart, f_uwork, f_d, f_e, f_pnorm;
     size_t r_Ynext, r_G, r_S, r_F, r_pS, r_pR, r_delta, r_cid;
     size_t total;
 };
@@ -127,8 +127,7 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false, int slots
     p.tau = L.add(z * n * nk);
     p.ypart = L.add(z * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.ypartT = L.add(z * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.pvw = L.add(z * 2 * (size_t)p.NBmax * nbA * nk);
-    p.pvv = L.add(z * 2 * (size_t)p.NBmax * nbA * nk);
+    p.pvw = L.add(z * 4 * (size_t)p.NBmax * nbA * nk);      // W and V parts interleaved by block
     p.qpart = L.add(r * (size_t)p.NBmax * p.CHmax * nk);
     p.uwork = L.add(z * (size_t)unmtr_work_elems(n, p.kb) * nk);
     p.cwork = L.add(z * (size_t)chol_work_elems(n) * nk);
@@ -160,8 +159,7 @@ SolvePlan make_plan(int64_t n, int64_t nk, int nb, bool mixed = false, int slots
     p.f_tau = L.add(m * c * n * nk);
     p.f_ypart = L.add(m * c * (size_t)p.NBmax * p.NBmax * 64 * nk);
     p.f_ypartT = L.add(m * c * (size_t)p.NBmax * p.CHmax * 64 * nk);
-    p.f_pvw = L.add(m * c * 2 * (size_t)p.NBmax * nbA * nk);
-    p.f_pvv = L.add(m * c * 2 * (size_t)p.NBmax * nbA * nk);
+    p.f_pvw = L.add(m * c * 4 * (size_t)p.NBmax * nbA * nk);
     p.f_qpart = L.add(m * f * (size_t)p.NBmax * p.CHmax * nk);
     p.f_uwork = L.add(m * c * (size_t)unmtr_work_elems(n, p.kb) * nk);
     p.f_d = L.add(m * f * n * nk);
@@ -197,8 +195,8 @@ HetrdWs<float> hetrd_ws32(const SolvePlan& p, void* w)
     h.ypart = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
     h.ypartT = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
     h.pvw = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvw);
-    h.pvv = reinterpret_cast<float2*>(static_cast<char*>(w) + p.f_pvv);
-    h.s_pdot = 2 * (int64_t)p.NBmax * p.nb;
+    h.pvv = h.pvw + p.nb;
+    h.s_pdot = 4 * (int64_t)p.NBmax * p.nb;
     h.qpart = reinterpret_cast<float*>(static_cast<char*>(w) + p.f_qpart); h.s_qpart = (int64_t)p.NBmax * p.CHmax;
     return h;
 }
@@ -221,7 +219,7 @@ HetrdWs<double> hetrd_ws(const SolvePlan& p, void* w, double2* A, int64_t lda, i
     h.pnorm = at<double>(w, p.pnorm); h.s_pnorm = 2 * p.PN;
     h.ypart = at<double2>(w, p.ypart); h.s_ypart = (int64_t)p.NBmax * p.NBmax * 64;
     h.ypartT = at<double2>(w, p.ypartT); h.s_ypartT = (int64_t)p.NBmax * p.CHmax * 64;
-    h.pvw = at<double2>(w, p.pvw); h.pvv = at<double2>(w, p.pvv); h.s_pdot = 2 * (int64_t)p.NBmax * p.nb;
+    h.pvw = at<double2>(w, p.pvw); h.pvv = h.pvw + p.nb; h.s_pdot = 4 * (int64_t)p.NBmax * p.nb;
     h.qpart = at<double>(w, p.qpart); h.s_qpart = (int64_t)p.NBmax * p.CHmax;
     return h;
 }

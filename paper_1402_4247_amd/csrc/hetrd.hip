@@ -68,36 +68,54 @@ __device__ inline void reflector_core(cx<R> alpha, R sig2, cx<R>& tau, cx<R>& sc
     scale = mk<R>(dr * iden, -di * iden);
 }
 
-// Reflector from the partial norms: returns tau and the scale applied to x.
-// Called by whole waves: the partial norms are summed across the lanes (the
-// same tree in every wave, so every wave holds the same bits).
+// Partial norms of column i: lane q takes the per-block partials q, q + 64,
+// ... (pn_first: the first of them, requested with the kernel's first batch
+// of loads; pn_rest: the sum, in that order).
 template <typename R>
-__device__ inline void reflector(const HetrdWs<R>& ws, int64_t b, int i, cx<R>& tau, cx<R>& scale, R& beta)
+__device__ inline const R* pnorm_base(const HetrdWs<R>& ws, int64_t b, int i)
 {
-    const int n = ws.n;
-    const int np = (n - i + RB - 1) / RB;
-    const R* pn = ws.pnorm + b * ws.s_pnorm + (i & 1) * ((n + RB - 1) / RB);
-    R part = 0;
-    for (int q = (int)(threadIdx.x & 63); q < np; q += 64) part += pn[q];
-    const R sig2 = dpp_wave_sum(part);
-    const cx<R> alpha = ws.A[b * ws.sA + (int64_t)(i + 1) + (int64_t)i * ws.lda];
-    reflector_core(alpha, sig2, tau, scale, beta);
+    return ws.pnorm + b * ws.s_pnorm + (i & 1) * ((ws.n + RB - 1) / RB);
+}
+template <typename R>
+__device__ inline R pn_first(const HetrdWs<R>& ws, int64_t b, int i, int lane)
+{
+    const int np = (ws.n - i + RB - 1) / RB;
+    return pnorm_base(ws, b, i)[lane < np ? lane : 0];
+}
+template <typename R>
+__device__ inline R pn_rest(const HetrdWs<R>& ws, int64_t b, int i, int lane, R first)
+{
+    const int np = (ws.n - i + RB - 1) / RB;
+    const R* pn = pnorm_base(ws, b, i);
+    R part = lane < np ? first : (R)0;
+    for (int q = lane + 64; q < np; q += 64) part += pn[q];
+    return part;
 }
 
 // One halving step of the transposing reduction: lanes with the MASK bit set
 // keep values HALF..2HALF-1 (moved down to 0..HALF-1), the others keep
-// 0..HALF-1; each adds its partner's copy of the values it keeps.
+// 0..HALF-1; each adds its partner's copy of the values it keeps.  Across
+// rows (MASK 16, 32) a permlane swap of the pair (t[q], t[q + HALF]) leaves
+// both addends in place; within a row the sent value is selected and moved
+// by DPP.
 template <int MASK, int HALF, int NV, typename R>
 __device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV], bool up)
 {
 #pragma unroll
     for (int q = 0; q < HALF; ++q) {
-        const cx<R> send = csel(up, t[q], t[q + HALF]);
-        const cx<R> keep = csel(up, t[q + HALF], t[q]);
-        cx<R> rcv;
-        rcv.x = lane_xor<MASK>(send.x);
-        rcv.y = lane_xor<MASK>(send.y);
-        t[q] = cadd(keep, rcv);
+        if constexpr (MASK >= 16) {
+            cx<R> a = t[q], c = t[q + HALF];
+            swap_across<MASK>(a.x, c.x);
+            swap_across<MASK>(a.y, c.y);
+            t[q] = cadd(a, c);
+        } else {
+            const cx<R> send = csel(up, t[q], t[q + HALF]);
+            const cx<R> keep = csel(up, t[q + HALF], t[q]);
+            cx<R> rcv;
+            rcv.x = lane_xor<MASK>(send.x);
+            rcv.y = lane_xor<MASK>(send.y);
+            t[q] = cadd(keep, rcv);
+        }
     }
 }
 
@@ -105,8 +123,8 @@ __device__ __attribute__((always_inline)) inline void halve_step(cx<R> (&t)[NV],
 template <int MASK, typename R>
 __device__ __attribute__((always_inline)) inline cx<R> xor_add_v(cx<R> r)
 {
-    r.x += lane_xor<MASK>(r.x);
-    r.y += lane_xor<MASK>(r.y);
+    r.x = xor_sum<MASK>(r.x);
+    r.y = xor_sum<MASK>(r.y);
     return r;
 }
 
@@ -399,33 +417,134 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
 }
 
 // ---------------------------------------------------------------------------
+// Partial sums read as buffer loads: an offset at or beyond the buffer's size
+// returns 0, so a term that does not exist is read at OOB and added as 0, and
+// every batch is loaded and added whole, without selects.
+constexpr int OOB = 0x20000000;
+
+// A descriptor built from workgroup-uniform values, pinned to scalar
+// registers (64-bit offset arithmetic can leave it in vector registers, and a
+// buffer load from those would loop over the lanes' distinct descriptors).
+__device__ inline i4_t uniform_rsrc(const void* base, uint32_t bytes)
+{
+    i4_t r = buffer_rsrc(base, bytes);
+    r.x = __builtin_amdgcn_readfirstlane(r.x);
+    r.y = __builtin_amdgcn_readfirstlane(r.y);
+    r.z = __builtin_amdgcn_readfirstlane(r.z);
+    r.w = __builtin_amdgcn_readfirstlane(r.w);
+    return r;
+}
+
+template <typename R>
+__device__ inline cx<R> bload(i4_t rsrc, int voff)
+{
+    if constexpr (sizeof(R) == 8)
+        return __builtin_bit_cast(cx<R>, raw_buffer_load_v4i32(rsrc, voff, 0, 0));
+    else
+        return __builtin_bit_cast(cx<R>, raw_buffer_load_v2i32(rsrc, voff, 0, 0));
+}
+
 // z at one row: the partial sums over the block columns and chunks that
 // touch it, split over the four waves (wave w takes the terms with index =
-// w mod 4) and combined as (w0 + w1) + (w2 + w3).  Every workgroup that
-// needs row o's value uses this same sequence, so it is bitwise equal to the
-// value the owner of row o computes.
+// w mod 4) and combined as (w0 + w1) + (w2 + w3).  A wave's terms are the
+// block columns C = w, w + 4, ... <= Rb (per-block partials) and the chunks
+// ch = w, w + 4, ... < nc (per-chunk partials); term t of each list goes to
+// the first of two running sums if t is even, to the second if odd.  The
+// first ZB terms of both lists are requested together (one memory round trip
+// at n = 2000), longer lists load the rest as they are summed.
+constexpr int ZB = 8;
+
 template <typename R>
-__device__ inline cx<R> zpart(const HetrdWs<R>& ws, int64_t b, int Rb, int NB, int r, int w)
+struct ZTerms {
+    i4_t rp, rq;          // block row Rb's per-block and per-chunk partials
+    int w, tp, tq, roff;  // wave (uniform), term counts, row offset in bytes
+    __device__ ZTerms(const HetrdWs<R>& ws, int64_t b, int Rb, int NB, int r, int w_) : w(w_)
+    {
+        rp = uniform_rsrc(ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT,
+                         (uint32_t)((int64_t)ws.NBmax * ZT * (int64_t)sizeof(cx<R>)));
+        rq = uniform_rsrc(ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT,
+                         (uint32_t)((int64_t)ws.CHmax * ZT * (int64_t)sizeof(cx<R>)));
+        const int nc = nchunks_z(NB, Rb, ws.zch);
+        tp = Rb >= w ? (Rb - w) / 4 + 1 : 0;
+        tq = nc > w ? (nc - 1 - w) / 4 + 1 : 0;
+        roff = r * (int)sizeof(cx<R>);
+    }
+    __device__ int off(int t, int tn) const
+    {
+        return (t < tn ? (w + 4 * t) * ZT * (int)sizeof(cx<R>) : OOB) + roff;
+    }
+    __device__ void load(int t0, cx<R> (&vp)[ZB], cx<R> (&vq)[ZB]) const
+    {
+#pragma unroll
+        for (int t = 0; t < ZB; ++t) {
+            vp[t] = bload<R>(rp, off(t0 + t, tp));
+            vq[t] = bload<R>(rq, off(t0 + t, tq));
+        }
+    }
+    // the whole sum, given the first batches (overwritten)
+    __device__ cx<R> sum(cx<R> (&vp)[ZB], cx<R> (&vq)[ZB]) const
+    {
+        cx<R> y0 = czero<cx<R>>(), y1 = czero<cx<R>>();
+#pragma unroll
+        for (int t = 0; t < ZB; t += 2) {
+            y0 = cadd(y0, vp[t]);
+            y1 = cadd(y1, vp[t + 1]);
+        }
+        for (int t0 = ZB; t0 < tp; t0 += ZB) {
+#pragma unroll
+            for (int t = 0; t < ZB; ++t) vp[t] = bload<R>(rp, off(t0 + t, tp));
+#pragma unroll
+            for (int t = 0; t < ZB; t += 2) {
+                y0 = cadd(y0, vp[t]);
+                y1 = cadd(y1, vp[t + 1]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < ZB; t += 2) {
+            y0 = cadd(y0, vq[t]);
+            y1 = cadd(y1, vq[t + 1]);
+        }
+        for (int t0 = ZB; t0 < tq; t0 += ZB) {
+#pragma unroll
+            for (int t = 0; t < ZB; ++t) vq[t] = bload<R>(rq, off(t0 + t, tq));
+#pragma unroll
+            for (int t = 0; t < ZB; t += 2) {
+                y0 = cadd(y0, vq[t]);
+                y1 = cadd(y1, vq[t + 1]);
+            }
+        }
+        return cadd(y0, y1);
+    }
+};
+
+// z at row o (row 0 of block 0), needed by every workgroup: the 1 + nc terms
+// (block column 0, then the chunks of block row 0) spread over the lanes of
+// one wave and summed by a fixed lane tree, so every workgroup holds the same
+// bits.  z0_first is the lane's first term, requested with the kernel's first
+// batch of loads; z0_rest adds the others (lane + 64, ...).
+template <typename R>
+__device__ inline cx<R> z0_first(const HetrdWs<R>& ws, int64_t b, int NB, int lane)
 {
-    // two running sums (terms w, w + 8, ... and w + 4, w + 12, ...) so that
-    // consecutive loads do not wait on each other
-    cx<R> y0 = czero<cx<R>>(), y1 = czero<cx<R>>();
-    const cx<R>* yp = ws.ypart + b * ws.s_ypart + (int64_t)Rb * ws.NBmax * ZT + r;
-    int C = w;
-    for (; C + 4 <= Rb; C += 8) {
-        y0 = cadd(y0, yp[(int64_t)C * ZT]);
-        y1 = cadd(y1, yp[(int64_t)(C + 4) * ZT]);
-    }
-    if (C <= Rb) y0 = cadd(y0, yp[(int64_t)C * ZT]);
-    const int nc = nchunks_z(NB, Rb, ws.zch);
-    const cx<R>* yq = ws.ypartT + b * ws.s_ypartT + (int64_t)Rb * ws.CHmax * ZT + r;
-    int ch = w;
-    for (; ch + 4 < nc; ch += 8) {
-        y0 = cadd(y0, yq[(int64_t)ch * ZT]);
-        y1 = cadd(y1, yq[(int64_t)(ch + 4) * ZT]);
-    }
-    if (ch < nc) y0 = cadd(y0, yq[(int64_t)ch * ZT]);
-    return cadd(y0, y1);
+    const int T = 1 + nchunks_z(NB, 0, ws.zch);
+    return lane == 0 ? ws.ypart[b * ws.s_ypart] : ws.ypartT[b * ws.s_ypartT + (int64_t)(lane < T ? lane - 1 : 0) * ZT];
+}
+template <typename R>
+__device__ inline cx<R> z0_rest(const HetrdWs<R>& ws, int64_t b, int NB, int lane, cx<R> first)
+{
+    const cx<R>* yq = ws.ypartT + b * ws.s_ypartT;
+    const int T = 1 + nchunks_z(NB, 0, ws.zch);
+    cx<R> acc = csel(lane < T, first, czero<cx<R>>());
+    for (int s = lane + 64; s < T; s += 64) acc = cadd(acc, yq[(int64_t)(s - 1) * ZT]);
+    return acc;
+}
+
+// LDS written by a wave and then read by other lanes of the same wave: a
+// wave-scope fence and a scheduling barrier, no workgroup barrier
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename C>
@@ -444,19 +563,17 @@ __device__ inline C sum4(const C (&s)[4][64], int l)
 template <typename R>
 __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p, int update_next, int nch)
 {
-    __shared__ cx<R> s1[4][64], s2[4][64], sy[4][64];
-    __shared__ cx<R> swv[64], svv[64];        // W^H v, V^H v (zero beyond j)
+    __shared__ cx<R> s1[4][64], s2[4][64], sy[4][64], sco[4][64];
+    __shared__ cx<R> swv[4][64], svv[4][64];  // W^H v, V^H v (zero beyond j), one copy per wave
     __shared__ cx<R> sWo[64], sVo[64];        // row o of W(:, 0:j) and V(:, p:p+j) (zero beyond j)
-    __shared__ cx<R> szo[4];
     __shared__ R sqq[4];
-    __shared__ cx<R> sv[64], sw[64];          // this block's v and w
-    __shared__ cx<R> sc[4];                   // w_o, (alpha2, 0)
     const int64_t b = blockIdx.y;
     const int n = ws.n, o = i + 1, m = n - o;
     const int NB = (m + ZT - 1) / ZT;
     const int Rb = blockIdx.x;
     const int j = i - p;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar) wave index
     const int64_t gr = (int64_t)o + (int64_t)Rb * ZT + lane;
     const int64_t grc = gr < n ? gr : (int64_t)n - 1;     // clamped row for unconditional loads
     const cx<R>* A = ws.A + b * ws.sA;
@@ -465,7 +582,9 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     const int npn = (n + RB - 1) / RB;
     const cx<R> zero = czero<cx<R>>();
 
-    // ---- phase 1: every load that depends on nothing computed here
+    // ---- phase 1: every load that depends on nothing computed here, issued
+    // whole before any of it is waited for (lists longer than their first
+    // batch load the rest as they are summed)
     cx<R> pv[8], pw[8];       // V(gr, p + jj), W(gr, jj) for jj = w + 4q < j, else 0
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -476,41 +595,88 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     }
     const cx<R> ai = A[grc + (int64_t)i * ws.lda];
     cx<R> h = A[grc + (int64_t)o * ws.lda];
-    if (w == 1) {
-        const int lc = lane < j ? lane : 0;
-        const cx<R> wv = W[(int64_t)o + (int64_t)lc * n];
-        const cx<R> vv = V[(int64_t)o + (int64_t)(p + lc) * n];
-        sWo[lane] = csel(lane < j, wv, zero);
-        sVo[lane] = csel(lane < j, vv, zero);
+    const cx<R> alpha = A[(int64_t)(i + 1) + (int64_t)i * ws.lda];
+    const R hoo = A[(int64_t)o + (int64_t)o * ws.lda].x;
+    const R npf = pn_first(ws, b, i, lane);
+    const cx<R> z0f = z0_first(ws, b, NB, lane);
+    // row o of the panel (stored to LDS by wave 1 once every load is issued)
+    const int lc = lane < j ? lane : 0;
+    const cx<R> wo_l = W[(int64_t)o + (int64_t)lc * n];
+    const cx<R> vo_l = V[(int64_t)o + (int64_t)(p + lc) * n];
+    // this row's z partials and the chunk shares of q = Re(u^H A22 u)
+    const ZTerms<R> zt(ws, b, Rb, NB, lane, w);
+    cx<R> zp[ZB], zq[ZB];
+    zt.load(0, zp, zq);
+    constexpr int QL = 4;
+    R qt[QL];
+#pragma unroll
+    for (int u = 0; u < QL; ++u) {
+        const int c = tid + 256 * u;
+        qt[u] = ws.qpart[b * ws.s_qpart + (c < nch ? c : 0)];
     }
+
+    // the unscaled panel-dot partials of column i, blocks q = w, w + 4, ...
+    // (added in that order); lanes 0-31 take the W parts of panel columns
+    // 0-31, lanes 32-63 their V parts (columns 32 and up, for panels wider
+    // than 32, in a second pass)
+    constexpr int PL = 8;
+    const int npd = (n - i + RB - 1) / RB;
+    const int nb2 = 2 * ws.nb;
+    const i4_t rpd = uniform_rsrc(ws.pvw + b * ws.s_pdot + (int64_t)(i & 1) * ws.NBmax * nb2,
+                                 (uint32_t)((int64_t)ws.NBmax * nb2 * (int64_t)sizeof(cx<R>)));
+    const int pd_half = lane >> 5, pd_c = lane & 31;
+    auto pd_off = [&](int c0, int q) {
+        const int loff = c0 + pd_c < j ? (pd_half * ws.nb + c0 + pd_c) * (int)sizeof(cx<R>) : OOB;
+        return (q < npd ? q * nb2 * (int)sizeof(cx<R>) : OOB) + loff;
+    };
+    cx<R> pt[PL];
+#pragma unroll
+    for (int u = 0; u < PL; ++u) pt[u] = bload<R>(rpd, pd_off(0, w + 4 * u));
+
+    // ---- sums of the partials (the remainders of long lists load here)
+    if (w == 1) {
+        sWo[lane] = csel(lane < j, wo_l, zero);
+        sVo[lane] = csel(lane < j, vo_l, zero);
+    }
+    sy[w][lane] = zt.sum(zp, zq);
     {
-        // unscaled panel-dot partials of column i (lane = panel column)
-        cx<R> a1 = zero, a2 = zero;
-        if (lane < j) {
-            const int np = (n - i + RB - 1) / RB;
-            const int64_t base = b * ws.s_pdot + (int64_t)(i & 1) * ws.NBmax * ws.nb + lane;
-#pragma unroll 4
-            for (int q = w; q < np; q += 4) {
-                a1 = cadd(a1, ws.pvw[base + (int64_t)q * ws.nb]);
-                a2 = cadd(a2, ws.pvv[base + (int64_t)q * ws.nb]);
+        R qa = 0;
+        for (int c0 = tid;; c0 += 256 * QL) {
+#pragma unroll
+            for (int u = 0; u < QL; ++u) qa = c0 + 256 * u < nch ? qa + qt[u] : qa;
+            if (c0 + 256 * QL >= nch) break;
+#pragma unroll
+            for (int u = 0; u < QL; ++u) {
+                const int c = c0 + 256 * QL + 256 * u;
+                qt[u] = ws.qpart[b * ws.s_qpart + (c < nch ? c : 0)];
             }
         }
-        s1[w][lane] = a1;
-        s2[w][lane] = a2;
-    }
-    sy[w][lane] = zpart(ws, b, Rb, NB, lane, w);
-    if (lane == 0) szo[w] = zpart(ws, b, 0, NB, 0, w);
-    {
-        // q = Re(u^H A22 u) from the shares of the nch chunks of the product
-        R qa = 0;
-        for (int c = tid; c < nch; c += 256) qa += ws.qpart[b * ws.s_qpart + c];
         qa = dpp_wave_sum(qa);
         if (lane == 0) sqq[w] = qa;
     }
+    cx<R> z0 = z0_rest(ws, b, NB, lane, z0f);
+    // panel-dot sums (the first pass's loads were issued with the others)
+    for (int c0 = 0; c0 < j; c0 += 32) {
+        if (c0 > 0) {
+#pragma unroll
+            for (int u = 0; u < PL; ++u) pt[u] = bload<R>(rpd, pd_off(c0, w + 4 * u));
+        }
+        cx<R> a = zero;
+        for (int q0 = w;; q0 += 4 * PL) {
+#pragma unroll
+            for (int u = 0; u < PL; ++u) a = cadd(a, pt[u]);
+            if (q0 + 4 * PL >= npd) break;
+#pragma unroll
+            for (int u = 0; u < PL; ++u) pt[u] = bload<R>(rpd, pd_off(c0, q0 + 4 * PL + 4 * u));
+        }
+        if (pd_half == 0)
+            s1[w][c0 + pd_c] = a;
+        else
+            s2[w][c0 + pd_c] = a;
+    }
     cx<R> tau, scale;
     R beta;
-    reflector(ws, b, i, tau, scale, beta);
-    const R hoo = A[(int64_t)o + (int64_t)o * ws.lda].x;
+    reflector_core(alpha, dpp_wave_sum(pn_rest(ws, b, i, lane, npf)), tau, scale, beta);
 #pragma unroll
     for (int q = 0; q < 8; ++q)
         if (!(w + 4 * q < j)) {
@@ -520,94 +686,90 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     if (gr == o) h.y = 0;
     __syncthreads();
 
-    // ---- panel dots W^H v = conj(W(o, :)) + scale * partials (likewise V)
-    if (tid < 64) {
-        if (tid < j) {
-            swv[tid] = cfma(scale, sum4(s1, tid), cconj(sWo[tid]));
-            svv[tid] = cfma(scale, sum4(s2, tid), cconj(sVo[tid]));
-        } else {
-            swv[tid] = zero;
-            svv[tid] = zero;
-        }
+    // ---- panel dots W^H v = conj(W(o, :)) + scale * partials (likewise V),
+    // lane = panel column.  Every wave forms them (the same bits in each) and
+    // keeps them in its own LDS row for the corrections, so no barrier is
+    // needed before those.
+    cx<R> wvl = zero, vvl = zero;
+    if (lane < j) {
+        wvl = cfma(scale, sum4(s1, lane), cconj(sWo[lane]));
+        vvl = cfma(scale, sum4(s2, lane), cconj(sVo[lane]));
     }
-    __syncthreads();
+    swv[w][lane] = wvl;
+    svv[w][lane] = vvl;
 
-    // ---- row o: y_o, alpha2 and w_o, identical in every workgroup (wave 0,
-    // lane = panel column, fixed-order wave sums)
-    if (w == 0) {
-        cx<R> co = cfma(sVo[lane], swv[lane], cmul(sWo[lane], svv[lane]));
-        R cross = svv[lane].x * swv[lane].x + svv[lane].y * swv[lane].y;   // Re(conj(V^H v) W^H v)
-        co.x = dpp_wave_sum(co.x);
-        co.y = dpp_wave_sum(co.y);
-        cross = dpp_wave_sum(cross);
-        if (lane == 0) {
-            const cx<R> zo = cadd(cadd(szo[0], szo[1]), cadd(szo[2], szo[3]));
-            const R q = (sqq[0] + sqq[1]) + (sqq[2] + sqq[3]);
-            const cx<R> sz = cmul(scale, zo);
-            const R vav = hoo + (R)2 * sz.x + (scale.x * scale.x + scale.y * scale.y) * q;
-            const R a2 = (R)-0.5 * (tau.x * tau.x + tau.y * tau.y) * (vav - (R)2 * cross);
-            const cx<R> yo = cmul(tau, csub(cadd(mk<R>(hoo, 0), sz), co));
-            sc[0] = cadd(yo, mk<R>(a2, 0));
-            sc[1] = mk<R>(a2, 0);
-        }
-    }
-    // ---- this block's corrections V (W^H v) + W (V^H v)
+    // ---- row o: y_o, alpha2 and w_o from fixed-order wave sums over the
+    // panel columns, identical in every wave and every workgroup
+    cx<R> co = cfma(sVo[lane], wvl, cmul(sWo[lane], vvl));
+    R cross = vvl.x * wvl.x + vvl.y * wvl.y;   // Re(conj(V^H v) W^H v)
+    co.x = dpp_wave_sum(co.x);
+    co.y = dpp_wave_sum(co.y);
+    cross = dpp_wave_sum(cross);
+    z0.x = dpp_wave_sum(z0.x);
+    z0.y = dpp_wave_sum(z0.y);
+    const R qq = (sqq[0] + sqq[1]) + (sqq[2] + sqq[3]);
+    const cx<R> sz = cmul(scale, z0);
+    const R vav = hoo + (R)2 * sz.x + (scale.x * scale.x + scale.y * scale.y) * qq;
+    const R a2 = (R)-0.5 * (tau.x * tau.x + tau.y * tau.y) * (vav - (R)2 * cross);
+    const cx<R> wo = cadd(cmul(tau, csub(cadd(mk<R>(hoo, 0), sz), co)), mk<R>(a2, 0));
+    wave_sync();
+
+    // ---- this block's corrections V (W^H v) + W (V^H v), partial per wave
     cx<R> corr = zero;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int jj = w + 4 * q;
-        corr = cfma(pv[q], swv[jj], corr);
-        corr = cfma(pw[q], svv[jj], corr);
+        corr = cfma(pv[q], swv[w][jj], corr);
+        corr = cfma(pw[q], svv[w][jj], corr);
     }
     for (int jj = w + 32; jj < j; jj += 4) {
-        corr = cfma(V[grc + (int64_t)(p + jj) * n], swv[jj], corr);
-        corr = cfma(W[grc + (int64_t)jj * n], svv[jj], corr);
+        corr = cfma(V[grc + (int64_t)(p + jj) * n], swv[w][jj], corr);
+        corr = cfma(W[grc + (int64_t)jj * n], svv[w][jj], corr);
     }
-    s1[w][lane] = corr;
-    __syncthreads();
-    const cx<R> wo = sc[0];
-    const R a2 = sc[1].x;
-    if (w == 0) {
-        cx<R> v = zero, wv = zero;
-        if (gr < n) {
-            v = csel(gr == o, mk<R>(1, 0), cmul(ai, scale));
-            if (gr == o) {
-                wv = wo;
-            } else {
-                const cx<R> z = sum4(sy, lane);
-                const cx<R> y = cmul(tau, csub(cfma(scale, z, h), sum4(s1, lane)));
-                wv = cfma(mk<R>(a2, 0), v, y);
-            }
-            V[gr + (int64_t)i * n] = v;
-            W[gr + (int64_t)j * n] = wv;
-        }
-        sv[lane] = v;
-        sw[lane] = wv;
-        if (Rb == 0 && lane == 0) {
-            ws.e[b * n + i] = beta;
-            ws.tau[b * n + i] = tau;
-        }
-    }
-    if (!update_next) return;
+    sco[w][lane] = corr;
     __syncthreads();
 
-    // ---- column o -= V(:, 0:j) conj(W(o, 0:j))^T + W(:, 0:j) conj(V(o, 0:j))^T
-    // (column j of the panel is this block's v, w, with row o = (1, w_o))
-    const cx<R> myv = sv[lane], myw = sw[lane];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        if (w + 4 * q == j) {
-            pv[q] = myv;
-            pw[q] = myw;
+    // ---- v and w of this block's rows (every wave forms them, wave 0 stores)
+    cx<R> myv = zero, myw = zero;
+    if (gr < n) {
+        myv = csel(gr == o, mk<R>(1, 0), cmul(ai, scale));
+        if (gr == o) {
+            myw = wo;
+        } else {
+            const cx<R> z = sum4(sy, lane);
+            const cx<R> y = cmul(tau, csub(cfma(scale, z, h), sum4(sco, lane)));
+            myw = cfma(mk<R>(a2, 0), myv, y);
         }
+        if (w == 0) {
+            V[gr + (int64_t)i * n] = myv;
+            W[gr + (int64_t)j * n] = myw;
+        }
+    }
+    if (w == 0 && Rb == 0 && lane == 0) {
+        ws.e[b * n + i] = beta;
+        ws.tau[b * n + i] = tau;
+    }
+    if (!update_next) return;
+
+    // ---- column o -= V(:, 0:j) conj(W(o, 0:j))^T + W(:, 0:j) conj(V(o, 0:j))^T
+    // (sWo, sVo hold row o of columns 0..j-1 and zero beyond; column j is
+    // this block's v, w with row o = (1, w_o), added last by its wave)
     cx<R> acc = zero;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int jj = w + 4 * q;
-        const cx<R> wo_j = csel(jj < j, sWo[jj], csel(jj == j, wo, zero));
-        const cx<R> vo_j = csel(jj < j, sVo[jj], csel(jj == j, mk<R>(1, 0), zero));
-        acc = cfma(pv[q], cconj(wo_j), acc);
-        acc = cfma(pw[q], cconj(vo_j), acc);
+        acc = cfma(pv[q], cconj(sWo[jj]), acc);
+        acc = cfma(pw[q], cconj(sVo[jj]), acc);
+    }
+    if (j < 32 && ((j - w) & 3) == 0) {
+        acc = cfma(myv, cconj(wo), acc);
+        acc = cfma(myw, cconj(mk<R>(1, 0)), acc);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (w + 4 * q == j) {
+                pv[q] = myv;
+                pw[q] = myw;
+            }
     }
     for (int jj = w + 32; jj <= j; jj += 4) {
         const bool old = jj < j;
@@ -619,33 +781,36 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     }
     s2[w][lane] = acc;
     __syncthreads();
-    if (w == 0) {
+    // the updated column (every wave; wave 0 stores it, its diagonal and the
+    // partial norm of rows o + 2 and below)
+    cx<R> an = zero;
+    {
         R nrm = 0;
-        cx<R> an = zero;
         if (gr < n) {
             const cx<R> a = csub(h, sum4(s2, lane));
-            if (gr == o) {
-                // the diagonal goes to d only: A(o, o) is read as it stood by
-                // every workgroup of this launch and is not needed afterwards
-                ws.d[b * n + o] = a.x;
-            } else {
-                ws.A[b * ws.sA + gr + (int64_t)o * ws.lda] = a;
+            if (w == 0) {
+                if (gr == o) {
+                    // the diagonal goes to d only: A(o, o) is read as it stood by
+                    // every workgroup of this launch and is not needed afterwards
+                    ws.d[b * n + o] = a.x;
+                } else {
+                    ws.A[b * ws.sA + gr + (int64_t)o * ws.lda] = a;
+                }
             }
             if (gr >= o + 2) {
                 nrm = a.x * a.x + a.y * a.y;
                 an = a;
             }
         }
-        nrm = dpp_wave_sum(nrm);
-        if (lane == 0) ws.pnorm[b * ws.s_pnorm + (o & 1) * npn + Rb] = nrm;
-        s1[0][lane] = an;
+        if (w == 0) {
+            nrm = dpp_wave_sum(nrm);
+            if (lane == 0) ws.pnorm[b * ws.s_pnorm + (o & 1) * npn + Rb] = nrm;
+        }
     }
-    __syncthreads();
     // products of the panel columns 0..j with the updated column below its
     // sub-diagonal: this block's share of the next reflector's panel dots,
     // eight columns per wave per transposing reduction
-    const cx<R> an = s1[0][lane];
-    const int64_t base = b * ws.s_pdot + (int64_t)(o & 1) * ws.NBmax * ws.nb + (int64_t)Rb * ws.nb;
+    const int64_t base = b * ws.s_pdot + ((int64_t)(o & 1) * ws.NBmax + Rb) * 2 * ws.nb;
     {
         cx<R> t1[8], t2[8];
 #pragma unroll

@@ -79,7 +79,9 @@ struct HetrdWs {
     R* pnorm; int64_t s_pnorm; // partial squared norms, 2 x hetrd_pn(n)
     cx<R>* ypart; int64_t s_ypart;   // NBmax x NBmax x 64
     cx<R>* ypartT; int64_t s_ypartT; // NBmax x CHmax x 64
-    cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;  // 2 x NBmax x nb
+    // panel-dot partials W^H u and V^H u: per problem 2 x NBmax blocks of
+    // [W part (nb), V part (nb)], so pvv = pvw + nb and the block stride is 2 nb
+    cx<R>* pvw; cx<R>* pvv; int64_t s_pdot;
     R* qpart; int64_t s_qpart;       // NBmax x CHmax: per-chunk shares of Re(u^H A22 u)
 };
 

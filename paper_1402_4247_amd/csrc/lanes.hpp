@@ -18,9 +18,11 @@ namespace kgev {
 // v_permlane16_swap / v_permlane32_swap of a register with itself return, in
 // one of their two results, the values of the other row of a row pair / the
 // other half of the wave.  All lanes taking part must be active.
+// (every pattern used here reads a lane of the same row, so no lane keeps an
+// old value and none needs initialising)
 template <int CTRL> __device__ inline int dpp(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 template <int M> __device__ inline int lane_xor(int v)
 {
@@ -45,6 +47,52 @@ template <int M> __device__ inline float lane_xor(float v) { return __int_as_flo
 template <int M> __device__ inline double lane_xor(double v)
 {
     return __hiloint2double(lane_xor<M>(__double2hiint(v)), lane_xor<M>(__double2loint(v)));
+}
+// Transposing exchange of a pair (a, b) across lane bit M (16 or 32): lanes
+// with the bit clear end with (own a, the partner's a), lanes with it set
+// with (the partner's b, own b), so a + b is each lane's kept value (a below
+// the bit, b above it) plus the partner's copy of it.  One permlane swap per
+// 32-bit word and no selects.
+template <int M> __device__ inline void swap_across(int& a, int& b)
+{
+    static_assert(M == 16 || M == 32, "row pair or wave half");
+    if constexpr (M == 32) {
+        const auto s = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+        a = (int)s[0];
+        b = (int)s[1];
+    } else {
+        const auto s = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+        a = (int)s[0];
+        b = (int)s[1];
+    }
+}
+template <int M> __device__ inline void swap_across(double& a, double& b)
+{
+    int ah = __double2hiint(a), al = __double2loint(a), bh = __double2hiint(b), bl = __double2loint(b);
+    swap_across<M>(ah, bh);
+    swap_across<M>(al, bl);
+    a = __hiloint2double(ah, al);
+    b = __hiloint2double(bh, bl);
+}
+template <int M> __device__ inline void swap_across(float& a, float& b)
+{
+    int ai = __float_as_int(a), bi = __float_as_int(b);
+    swap_across<M>(ai, bi);
+    a = __int_as_float(ai);
+    b = __int_as_float(bi);
+}
+// v + v(lane ^ M), the same bits in both lanes of a pair (the two addends
+// are the same, and addition commutes); across rows by one permlane swap of
+// v with a copy of itself, with no select
+template <int M, typename T> __device__ inline T xor_sum(T v)
+{
+    if constexpr (M >= 16) {
+        T a = v, b = v;
+        swap_across<M>(a, b);
+        return a + b;
+    } else {
+        return v + lane_xor<M>(v);
+    }
 }
 // the value of lane l (wave-uniform l) in every lane
 __device__ inline int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -92,12 +140,12 @@ template <int G, typename T> __device__ inline T dpp_prod(T v)
 // bits as a __shfl_xor butterfly in that order, in every lane
 template <typename T> __device__ inline T dpp_wave_sum(T v)
 {
-    v += lane_xor<32>(v);
-    v += lane_xor<16>(v);
-    v += lane_xor<8>(v);
-    v += lane_xor<4>(v);
-    v += lane_xor<2>(v);
-    v += lane_xor<1>(v);
+    v = xor_sum<32>(v);
+    v = xor_sum<16>(v);
+    v = xor_sum<8>(v);
+    v = xor_sum<4>(v);
+    v = xor_sum<2>(v);
+    v = xor_sum<1>(v);
     return v;
 }
 __device__ inline double dpp_wave_max(double v)
