@@ -92,6 +92,15 @@ __device__ inline R pn_rest(const HetrdWs<R>& ws, int64_t b, int i, int lane, R 
     return part;
 }
 
+// LDS written by a wave and then read by other lanes of the same wave: a
+// wave-scope fence and a scheduling barrier, no workgroup barrier
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One halving step of the transposing reduction: lanes with the MASK bit set
 // keep values HALF..2HALF-1 (moved down to 0..HALF-1), the others keep
 // 0..HALF-1; each adds its partner's copy of the values it keeps.  Across
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
 template <typename R, bool BUF>
 __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i, int rev)
 {
-    __shared__ cx<R> svC[ZT];
+    __shared__ cx<R> svC[ZCH][ZT];
     __shared__ cx<R> sT[ZCH][ZT];
     __shared__ cx<R> sP[ZCH][8][ZT + 1];
     const int64_t b = rev ? (int64_t)(gridDim.y - 1 - blockIdx.y) : (int64_t)blockIdx.y;
@@ -355,18 +364,21 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
             }
         }
     };
+    // u first, then the wave's first column group (the second is requested
+    // while the first is reduced).  Each wave keeps its own copy of u in LDS,
+    // so the waves do not wait for each other before the products.
+    const int64_t gcu = gcb + lane;
+    const cx<R> uC = Ai[gcu < n ? gcu : (int64_t)n - 1];
+    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
     const int g0 = 2 * w, g1 = 2 * w + 2;
     cx<R> a[8];
     load_group(g0, a);
     sT[w][lane] = czero<cx<R>>();      // the other waves' columns add zero
-    if (tid < ZT) {
-        const int64_t gc = gcb + tid;
-        const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
-        svC[tid] = csel(gc > o && gc < n, u, czero<cx<R>>());
-    }
-    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
+    // (every wave stores its own copy: a store in one wave only would let the
+    // compiler move the load of u behind the tile's)
+    svC[w][lane] = csel(gcu > o && gcu < n, uC, czero<cx<R>>());
     if (!(row_ok && gr > o)) uR = czero<cx<R>>();
-    __syncthreads();
+    wave_sync();
 
     __shared__ R sq[ZCH];
     const bool diag_tile = (Rb == C);
@@ -382,7 +394,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
             cx<R> x;
             x.x = ok ? a[cc].x : (R)0;
             x.y = (ok && !diag) ? a[cc].y : (R)0;
-            yd = cfma(x, svC[g * 8 + cc], yd);
+            yd = cfma(x, svC[w][g * 8 + cc], yd);
             a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
         }
 #pragma unroll
@@ -410,7 +422,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = ys;
         const cx<R> s = cadd(cadd(sT[0][lane], sT[1][lane]), cadd(sT[2][lane], sT[3][lane]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + lane] = s;
-        R qt = svC[lane].x * s.x + svC[lane].y * s.y;
+        R qt = svC[0][lane].x * s.x + svC[0][lane].y * s.y;
         qt = dpp_wave_sum(qt);
         if (lane == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
@@ -536,15 +548,6 @@ __device__ inline cx<R> z0_rest(const HetrdWs<R>& ws, int64_t b, int NB, int lan
     cx<R> acc = csel(lane < T, first, czero<cx<R>>());
     for (int s = lane + 64; s < T; s += 64) acc = cadd(acc, yq[(int64_t)(s - 1) * ZT]);
     return acc;
-}
-
-// LDS written by a wave and then read by other lanes of the same wave: a
-// wave-scope fence and a scheduling barrier, no workgroup barrier
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename C>
