@@ -182,7 +182,7 @@ __global__ __launch_bounds__(RB) void hetrd_colstart(HetrdWs<R> ws, int c)
 template <typename R, bool BUF>
 __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int rev)
 {
-    __shared__ cx<R> svC[ZT];
+    __shared__ cx<R> svC[ZCH][ZT];
     __shared__ cx<R> sT[ZCH][ZT];
     __shared__ cx<R> sP[ZCH][8][ZT + 1];      // per-wave staging of one group's products
     // rev: the workgroups take the chunks in reverse order (last k-point's
@@ -241,16 +241,16 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
             }
         }
     };
+    // u first, then the first column group; each wave keeps its own copy of
+    // u_C in LDS, so the waves do not wait for each other before the products
+    const int64_t gcu = gcb + lane;
+    const cx<R> uC = Ai[gcu < n ? gcu : (int64_t)n - 1];
+    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
     cx<R> a[8];
     load_group(0, a);
-    if (tid < ZT) {
-        const int64_t gc = gcb + tid;
-        const cx<R> u = Ai[gc < n ? gc : (int64_t)n - 1];
-        svC[tid] = csel(gc > o && gc < n, u, czero<cx<R>>());
-    }
-    cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
+    svC[w][lane] = csel(gcu > o && gcu < n, uC, czero<cx<R>>());
     if (!(row_ok && gr > o)) uR = czero<cx<R>>();
-    __syncthreads();
+    wave_sync();
 
     __shared__ R sq[ZCH];
     R qd = 0;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
                 cx<R> x;
                 x.x = ok ? a[cc].x : (R)0;
                 x.y = (ok && !diag) ? a[cc].y : (R)0;
-                yd = cfma(x, svC[g * 8 + cc], yd);
+                yd = cfma(x, svC[w][g * 8 + cc], yd);
                 // the diagonal entry is counted once (direct part only)
                 a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
             }
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
     if (tid < ZT) {
         const cx<R> s = cadd(cadd(sT[0][tid], sT[1][tid]), cadd(sT[2][tid], sT[3][tid]));
         ws.ypartT[b * ws.s_ypartT + ((int64_t)C * ws.CHmax + ch) * ZT + tid] = s;
-        R qt = svC[tid].x * s.x + svC[tid].y * s.y;
+        R qt = svC[0][tid].x * s.x + svC[0][tid].y * s.y;
         qt = dpp_wave_sum(qt);
         if (tid == 0) ws.qpart[b * ws.s_qpart + lid] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + qt;
     }
