@@ -447,6 +447,17 @@ __device__ inline i4_t uniform_rsrc(const void* base, uint32_t bytes)
     return r;
 }
 
+__device__ int raw_buffer_load_i32(i4_t rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.i32");
+
+template <typename R>
+__device__ inline R bload_r(i4_t rsrc, int voff)
+{
+    if constexpr (sizeof(R) == 8)
+        return __builtin_bit_cast(R, raw_buffer_load_v2i32(rsrc, voff, 0, 0));
+    else
+        return __builtin_bit_cast(R, raw_buffer_load_i32(rsrc, voff, 0, 0));
+}
+
 template <typename R>
 __device__ inline cx<R> bload(i4_t rsrc, int voff)
 {
@@ -588,13 +599,18 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     // ---- phase 1: every load that depends on nothing computed here, issued
     // whole before any of it is waited for (lists longer than their first
     // batch load the rest as they are summed)
-    cx<R> pv[8], pw[8];       // V(gr, p + jj), W(gr, jj) for jj = w + 4q < j, else 0
+    // V(gr, p + jj), W(gr, jj) for jj = w + 4q < j, else 0 (read past the
+    // panel's buffers)
+    const uint32_t panel_bytes = (uint32_t)((int64_t)n * ws.nb * (int64_t)sizeof(cx<R>));
+    const i4_t rV = uniform_rsrc(V + (int64_t)p * n, panel_bytes), rW = uniform_rsrc(W, panel_bytes);
+    const int roff = (int)grc * (int)sizeof(cx<R>);
+    cx<R> pv[8], pw[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int jj = w + 4 * q;
-        const int jc = jj < j ? jj : 0;
-        pv[q] = V[grc + (int64_t)(p + jc) * n];
-        pw[q] = W[grc + (int64_t)jc * n];
+        const int off = (jj < j ? jj * n * (int)sizeof(cx<R>) : OOB) + roff;
+        pv[q] = bload<R>(rV, off);
+        pw[q] = bload<R>(rW, off);
     }
     const cx<R> ai = A[grc + (int64_t)i * ws.lda];
     cx<R> h = A[grc + (int64_t)o * ws.lda];
@@ -611,12 +627,10 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     cx<R> zp[ZB], zq[ZB];
     zt.load(0, zp, zq);
     constexpr int QL = 4;
+    const i4_t rq = uniform_rsrc(ws.qpart + b * ws.s_qpart, (uint32_t)((int64_t)nch * (int64_t)sizeof(R)));
     R qt[QL];
 #pragma unroll
-    for (int u = 0; u < QL; ++u) {
-        const int c = tid + 256 * u;
-        qt[u] = ws.qpart[b * ws.s_qpart + (c < nch ? c : 0)];
-    }
+    for (int u = 0; u < QL; ++u) qt[u] = bload_r<R>(rq, (tid + 256 * u) * (int)sizeof(R));
 
     // the unscaled panel-dot partials of column i, blocks q = w, w + 4, ...
     // (added in that order); lanes 0-31 take the W parts of panel columns
@@ -646,13 +660,10 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
         R qa = 0;
         for (int c0 = tid;; c0 += 256 * QL) {
 #pragma unroll
-            for (int u = 0; u < QL; ++u) qa = c0 + 256 * u < nch ? qa + qt[u] : qa;
+            for (int u = 0; u < QL; ++u) qa += qt[u];
             if (c0 + 256 * QL >= nch) break;
 #pragma unroll
-            for (int u = 0; u < QL; ++u) {
-                const int c = c0 + 256 * QL + 256 * u;
-                qt[u] = ws.qpart[b * ws.s_qpart + (c < nch ? c : 0)];
-            }
+            for (int u = 0; u < QL; ++u) qt[u] = bload_r<R>(rq, (c0 + 256 * QL + 256 * u) * (int)sizeof(R));
         }
         qa = dpp_wave_sum(qa);
         if (lane == 0) sqq[w] = qa;
@@ -680,12 +691,6 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
     cx<R> tau, scale;
     R beta;
     reflector_core(alpha, dpp_wave_sum(pn_rest(ws, b, i, lane, npf)), tau, scale, beta);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        if (!(w + 4 * q < j)) {
-            pv[q] = zero;
-            pw[q] = zero;
-        }
     if (gr == o) h.y = 0;
     __syncthreads();
 
