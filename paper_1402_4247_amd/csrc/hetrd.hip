@@ -29,6 +29,8 @@
 // reduction runs in one launch, unblocked, with the matrix in LDS (tail).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible run to run.
+#include <type_traits>
+
 #include "common.hpp"
 #include "lanes.hpp"
 #include "kernels.hpp"
@@ -222,24 +224,22 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
     const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
+    auto load_one = [&](int g, int cc) -> cx<R> {
+        const int64_t gc = gcb + g * 8 + cc;
+        const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
+        if constexpr (BUF) {
+            const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
+            if constexpr (sizeof(R) == 8)
+                return __builtin_bit_cast(cx<R>, raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0));
+            else
+                return __builtin_bit_cast(cx<R>, raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0));
+        } else {
+            return A[gcc * lda + rowc];
+        }
+    };
     auto load_group = [&](int g, cx<R> (&a)[8]) {
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            const int64_t gc = gcb + g * 8 + cc;
-            const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
-            if constexpr (BUF) {
-                const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
-                if constexpr (sizeof(R) == 8) {
-                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
-                    a[cc] = __builtin_bit_cast(cx<R>, v);
-                } else {
-                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
-                    a[cc] = __builtin_bit_cast(cx<R>, v);
-                }
-            } else {
-                a[cc] = A[gcc * lda + rowc];
-            }
-        }
+        for (int cc = 0; cc < 8; ++cc) a[cc] = load_one(g, cc);
     };
     // u first, then the first column group; each wave keeps its own copy of
     // u_C in LDS, so the waves do not wait for each other before the products
@@ -257,8 +257,10 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
     if (have_tile) {
         const bool diag_tile = (Rb == C);
         cx<R> yd = czero<cx<R>>();
-#pragma unroll 1
-        for (int g = 0; g < 8; ++g) {
+        // one group of 8 columns; NEXT: the next group's columns are requested
+        // as this group's registers free up (the last group has none to fetch)
+        auto group = [&](int g, auto next) {
+            constexpr bool NEXT = decltype(next)::value;
             const int64_t gc0 = gcb + g * 8;
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc) {
@@ -270,15 +272,16 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
                 x.y = (ok && !diag) ? a[cc].y : (R)0;
                 yd = cfma(x, svC[w][g * 8 + cc], yd);
                 // the diagonal entry is counted once (direct part only)
-                a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
+                sP[w][cc][lane] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
+                // the column's register is free: request the next group's
+                // column at once, so that group streams in while this one is
+                // still being multiplied out
+                if constexpr (NEXT) a[cc] = load_one(g + 1, cc);
             }
-            // the products go to this wave's LDS block, the next group is
-            // requested, and the column sums are taken from LDS while it is in
-            // flight: lane l adds rows 8 (l / 8) .. +7 of column l mod 8, then
-            // the eight lanes of a column combine
-#pragma unroll
-            for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
-            if (g + 1 < 8) load_group(g + 1, a);
+            // the products are in this wave's LDS block; the column sums are
+            // taken from LDS while the next group is in flight: lane l adds
+            // rows 8 (l / 8) .. +7 of column l mod 8, then the eight lanes of
+            // a column combine
             __builtin_amdgcn_wave_barrier();
             const int c = lane & 7, r0 = (lane >> 3) * 8;
             cx<R> cs = czero<cx<R>>();
@@ -289,7 +292,10 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv(HetrdWs<R> ws, int i, int 
             cs = xor_add_v<32, R>(cs);
             if (lane < 8) sT[w][g * 8 + lane] = cs;
             __builtin_amdgcn_wave_barrier();
-        }
+        };
+#pragma unroll 1
+        for (int g = 0; g < 7; ++g) group(g, std::true_type{});
+        group(7, std::false_type{});
         ws.ypart[b * ws.s_ypart + ((int64_t)Rb * ws.NBmax + C) * ZT + lane] = yd;
         qd = uR.x * yd.x + uR.y * yd.y;
     } else {
@@ -345,34 +351,30 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
     const int rowc = row_ok ? (int)gr : n - 1;
     const int64_t gcb = (int64_t)o + (int64_t)C * ZT;
     const i4_t rsrc = buffer_rsrc(A, (uint32_t)(BUF ? (int64_t)sizeof(cx<R>) * lda * n : 0));
-    auto load_group = [&](int g, cx<R> (&a)[8]) {
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            const int64_t gc = gcb + g * 8 + cc;
-            const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
-            if constexpr (BUF) {
-                const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
-                if constexpr (sizeof(R) == 8) {
-                    const i4_t v = raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
-                    a[cc] = __builtin_bit_cast(cx<R>, v);
-                } else {
-                    const i2_t v = raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0);
-                    a[cc] = __builtin_bit_cast(cx<R>, v);
-                }
-            } else {
-                a[cc] = A[gcc * lda + rowc];
-            }
+    auto load_one = [&](int g, int cc) -> cx<R> {
+        const int64_t gc = gcb + g * 8 + cc;
+        const int64_t gcc = gc < n ? gc : (int64_t)n - 1;
+        if constexpr (BUF) {
+            const int soff = (int)(gcc * lda * (int64_t)sizeof(cx<R>));
+            if constexpr (sizeof(R) == 8)
+                return __builtin_bit_cast(cx<R>, raw_buffer_load_v4i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0));
+            else
+                return __builtin_bit_cast(cx<R>, raw_buffer_load_v2i32(rsrc, rowc * (int)sizeof(cx<R>), soff, 0));
+        } else {
+            return A[gcc * lda + rowc];
         }
     };
-    // u first, then the wave's first column group (the second is requested
-    // while the first is reduced).  Each wave keeps its own copy of u in LDS,
-    // so the waves do not wait for each other before the products.
+    // u first, then the wave's first column group (the second group's columns
+    // are requested as the first group's registers free up).  Each wave keeps
+    // its own copy of u in LDS, so the waves do not wait for each other before
+    // the products.
     const int64_t gcu = gcb + lane;
     const cx<R> uC = Ai[gcu < n ? gcu : (int64_t)n - 1];
     cx<R> uR = Ai[row_ok ? gr : (int64_t)n - 1];
-    const int g0 = 2 * w, g1 = 2 * w + 2;
+    const int g0 = 2 * w;
     cx<R> a[8];
-    load_group(g0, a);
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) a[cc] = load_one(g0, cc);
     sT[w][lane] = czero<cx<R>>();      // the other waves' columns add zero
     // (every wave stores its own copy: a store in one wave only would let the
     // compiler move the load of u behind the tile's)
@@ -383,8 +385,8 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
     __shared__ R sq[ZCH];
     const bool diag_tile = (Rb == C);
     cx<R> yd = czero<cx<R>>();
-#pragma unroll 1
-    for (int g = g0; g < g1; ++g) {
+    auto group = [&](int g, auto next) {
+        constexpr bool NEXT = decltype(next)::value;
         const int64_t gc0 = gcb + g * 8;
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
@@ -395,11 +397,9 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
             x.x = ok ? a[cc].x : (R)0;
             x.y = (ok && !diag) ? a[cc].y : (R)0;
             yd = cfma(x, svC[w][g * 8 + cc], yd);
-            a[cc] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
+            sP[w][cc][lane] = csel(diag, czero<cx<R>>(), cmulc(x, uR));
+            if constexpr (NEXT) a[cc] = load_one(g + 1, cc);
         }
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) sP[w][cc][lane] = a[cc];
-        if (g + 1 < g1) load_group(g + 1, a);
         __builtin_amdgcn_wave_barrier();
         const int c = lane & 7, r0 = (lane >> 3) * 8;
         cx<R> cs = czero<cx<R>>();
@@ -410,7 +410,9 @@ __global__ __launch_bounds__(256, 3) void hetrd_zhemv_tile(HetrdWs<R> ws, int i,
         cs = xor_add_v<32, R>(cs);
         if (lane < 8) sT[w][g * 8 + lane] = cs;
         __builtin_amdgcn_wave_barrier();
-    }
+    };
+    group(g0, std::true_type{});
+    group(g0 + 1, std::false_type{});
     // the four waves' shares of the tile's direct part
     sP[w][0][lane] = yd;
     R qd = uR.x * yd.x + uR.y * yd.y;
