@@ -877,6 +877,16 @@ __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p,
 // of the next column (rows two and more below its diagonal).  Eight threads
 // share a row in (C) and (E) and take its entries in groups of four, so one
 // LDS round trip serves four of them.
+// over the lanes that agree in lane mod 8: the first three steps of
+// dpp_wave_sum only, so where only the lanes 0 mod 8 hold nonzero values
+// lane 0 ends with the wave's sum
+template <typename T> __device__ inline T dpp_sum_mod8(T v)
+{
+    v = xor_sum<32>(v);
+    v = xor_sum<16>(v);
+    return xor_sum<8>(v);
+}
+
 constexpr int TAIL_M = 128;
 constexpr int TAIL_T = 1024;
 constexpr int TAIL_W = TAIL_T / 64;
@@ -987,8 +997,9 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
                 sy[r] = y;
                 yv = cmulc(y, sv[r]);
             }
-            yv.x = dpp_wave_sum(yv.x);
-            yv.y = dpp_wave_sum(yv.y);
+            // nonzero only in the lanes with q = 0 (0 mod 8)
+            yv.x = dpp_sum_mod8(yv.x);
+            yv.y = dpp_sum_mod8(yv.y);
             if (lane == 0) sred[wv] = yv;
         }
         __syncthreads();
@@ -1031,7 +1042,7 @@ __global__ __launch_bounds__(TAIL_T) void hetrd_tail(HetrdWs<R> ws, int i0)
                     Prow[s2] = a;
                 }
             }
-            part = dpp_wave_sum(part);
+            part = dpp_sum_mod8(part);     // nonzero only where q = 0
             if (lane == 0) red[wv] = part;
         }
         __syncthreads();
