@@ -575,7 +575,10 @@ __device__ inline C sum4(const C (&s)[4][64], int l)
 // is requested in one first phase, including this thread's rows of the panel
 // columns V(:, p + jj), W(:, jj) (the four waves take jj = w, w+4, ...; panels
 // up to 32 wide are held in registers, wider ones reload the rest), which
-// then serve the corrections, the column update and the panel dots.
+// then serve the corrections, the column update and the panel dots.  Every
+// wave forms the panel dots, the row-o scalars and v, w of the block itself,
+// so the launch has three workgroup barriers: after the loads, after the
+// corrections and after the column update.
 template <typename R>
 __global__ __launch_bounds__(256) void hetrd_update(HetrdWs<R> ws, int i, int p, int update_next, int nch)
 {
