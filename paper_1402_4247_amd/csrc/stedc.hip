@@ -99,21 +99,57 @@ __global__ __launch_bounds__(256) void dc_init(DcWs ws, int tl)
 // d (double) of lane i: a wave-uniform read of a lane-distributed array
 __device__ inline double rdl(double v, int i) { return lane_read(v, i); }
 
+// LDS written by a wave and then read by other lanes of the same wave: a
+// wave-scope fence and a scheduling barrier, no workgroup barrier
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // Leaf eigensolver: one wave per leaf segment (at most LEAF rows) of the torn
-// tridiagonal, implicit QL with Wilkinson shifts.  Lane i holds d_i and e_i
-// (e_i couples leaf rows i and i + 1); the recurrences of a QL sweep run on
-// wave-uniform values read with readlane and written back by lane select,
-// and the sweep's rotations are kept one per lane and applied afterwards to
-// the rows of the eigenvector matrix (row k in LDS, lane k): the column
-// carried from one rotation to the next stays in a register.  A sub-diagonal
-// entry is negligible when adding it to the running norm tst1 = max(|d_l| +
-// |e_l|) leaves tst1 unchanged.  Eigenvalues go to D[0] ascending, the
-// eigenvectors to the leaf's diagonal block of Q[0] (the rest of Q[0] is the
-// identity's zeros).
+// tridiagonal, by the parallel cyclic Jacobi method (Golub & Van Loan §8.5):
+// the leaf is held as a dense symmetric LEAF x LEAF matrix in LDS (rows past
+// the leaf are zero and never rotated), and each sweep takes LEAF - 1 rounds of
+// LEAF / 2 disjoint rotations (round-robin pairing with the last index fixed).
+// A rotation of the (p, q) plane with c = 1 / sqrt(1 + t^2), s = t c,
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), tau = (a_qq - a_pp) / (2 a_pq),
+// zeroes a_pq; each lane forms the rotation of pair lane mod 8 and applies it
+// to two rows (then two columns): the columns of A and of the accumulated V
+// together, then the rows of A.  An off-diagonal entry
+// at most eps * max_i(|d_i| + |e_i|) is left alone (the deflation threshold of
+// the QL form it replaces); a sweep that rotates nothing ends the iteration.
+// Eigenvalues go to D[0] ascending, the eigenvectors (columns of V) to the
+// leaf's diagonal block of Q[0] (the rest of Q[0] is the identity's zeros).
+// The rounds are short dependent chains of LDS traffic instead of the QL
+// sweep's chain of rotations, each with a square root and a reciprocal.
+constexpr int LEAF_SWEEPS = 30;
+
+__device__ inline void leaf_pair(int r, int k, int& p, int& q)
+{
+    // round r of the circle method on LEAF indices: index LEAF - 1 is fixed,
+    // the others rotate; pair k of the round
+    constexpr int M = LEAF - 1;
+    if (k == 0) {
+        p = r;
+        q = M;
+    } else {
+        p = (r + k) % M;
+        q = (r + M - k) % M;
+    }
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
 __global__ __launch_bounds__(64) void dc_leaf(DcWs ws, int tl)
 {
-    __shared__ double Zs[LEAF][LEAF + 1];
+    __shared__ double As[LEAF][LEAF + 1];
+    __shared__ double Vs[LEAF][LEAF + 1];
     const int64_t b = blockIdx.y;
     const int64_t n = ws.n;
     const Seg g = seg_of(blockIdx.x, n, tl);
@@ -122,86 +158,82 @@ __global__ __launch_bounds__(64) void dc_leaf(DcWs ws, int tl)
     const int lane = threadIdx.x;
     double* D = ws.D[0] + b * n;
     const double* es = ws.es + b * n;
-    double dr = lane < ns ? D[s + lane] : 0.0;
-    double er = lane + 1 < ns ? es[s + lane] : 0.0;
-    if (lane < ns)
-        for (int j = 0; j < ns; ++j) Zs[lane][j] = (lane == j) ? 1.0 : 0.0;
-    double cr = 0.0, sr = 0.0;     // lane i: rotation i of the current sweep
-    bool conv = true;
-    double f = 0.0, tst1 = 0.0;
-    for (int l = 0; l < ns; ++l) {
-        tst1 = fmax(tst1, fabs(rdl(dr, l)) + fabs(rdl(er, l)));
-        for (int it = 0;; ++it) {
-            int m = l;
-            while (m < ns - 1 && tst1 + fabs(rdl(er, m)) != tst1) ++m;
-            if (m == l) break;
-            if (it == 30) {
-                conv = false;
-                break;
-            }
-            // shift: the eigenvalue of the leading 2 x 2 nearer d_l
-            const double gl = rdl(dr, l), el = rdl(er, l);
-            double p = (rdl(dr, l + 1) - gl) / (2.0 * el);
-            double r = hypot(p, 1.0);
-            const double pr = p + copysign(r, p);
-            const double dl = el / pr, dl1 = el * pr;
-            const double h = gl - dl;
-            dr = (lane == l) ? dl : (lane == l + 1) ? dl1 : (lane > l + 1) ? dr - h : dr;
-            f += h;
-            // the sweep from row m up to row l
-            p = rdl(dr, m);
-            double c = 1.0, c2 = 1.0, c3 = 1.0, sn = 0.0, s2 = 0.0;
-            const double el1 = rdl(er, l + 1);
-            for (int i = m - 1; i >= l; --i) {
-                c3 = c2;
-                c2 = c;
-                s2 = sn;
-                const double ei = rdl(er, i), di = rdl(dr, i);
-                const double gg = c * ei, hh = c * p;
-                // |p| and |e_i| are O(1) on the scaled matrix: the squares
-                // cannot overflow; hypot where they could underflow
-                const double t2 = fma(p, p, ei * ei);
-                r = t2 > 1e-280 ? sqrt(t2) : hypot(p, ei);
-                const double ir = 1.0 / r;
-                const double ei1 = sn * r;
-                sn = ei * ir;
-                c = p * ir;
-                p = c * di - sn * gg;
-                const double di1 = hh + sn * (c * gg + sn * di);
-                er = (lane == i + 1) ? ei1 : er;
-                dr = (lane == i + 1) ? di1 : dr;
-                cr = (lane == i) ? c : cr;
-                sr = (lane == i) ? sn : sr;
-            }
-            p = -sn * s2 * c3 * el1 * rdl(er, l) / dl1;
-            er = (lane == l) ? sn * p : er;
-            dr = (lane == l) ? c * p : dr;
-            if (lane < ns) {
-                double carry = Zs[lane][m];
-                for (int i = m - 1; i >= l; --i) {
-                    const double zi = Zs[lane][i];
-                    const double ci = rdl(cr, i), si = rdl(sr, i);
-                    Zs[lane][i + 1] = si * zi + ci * carry;
-                    carry = ci * zi - si * carry;
-                }
-                Zs[lane][l] = carry;
-            }
+    const double dr = lane < ns ? D[s + lane] : 0.0;
+    const double er = lane + 1 < ns ? es[s + lane] : 0.0;
+    // the deflation threshold from the leaf's norm (max over rows of |d| + |e|)
+    const double tol = 2.220446049250313e-16 * dpp_wave_max(fabs(dr) + fabs(er));
+    for (int e = lane; e < LEAF * LEAF; e += 64) {
+        const int i = e / LEAF, j = e % LEAF;
+        double a = 0.0;
+        if (i < ns && j < ns) {
+            if (i == j) a = D[s + i];
+            else if (j == i + 1) a = es[s + i];
+            else if (i == j + 1) a = es[s + j];
         }
-        dr = (lane == l) ? dr + f : dr;
-        er = (lane == l) ? 0.0 : er;
+        As[i][j] = a;
+        Vs[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    wave_sync();
+    bool conv = false;
+    for (int sweep = 0; sweep < LEAF_SWEEPS; ++sweep) {
+        bool rotated = false;
+        for (int r = 0; r < LEAF - 1; ++r) {
+            // every lane forms the rotation of pair k = lane mod 8, the pair
+            // of both its items below, so no LDS round trip shares it
+            int p, q;
+            leaf_pair(r, lane % (LEAF / 2), p, q);
+            const double apq = As[p][q];
+            double c = 1.0, sn = 0.0;
+            if (fabs(apq) > tol) {
+                const double tau = (As[q][q] - As[p][p]) / (2.0 * apq);
+                const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
+                c = 1.0 / sqrt(fma(t, t, 1.0));
+                sn = t * c;
+                rotated = true;
+            }
+            wave_sync();
+            // columns p, q of A and of V: rows i = lane / 8 and lane / 8 + 8
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane / (LEAF / 2) + 8 * h;
+                const double aip = As[i][p], aiq = As[i][q];
+                const double vip = Vs[i][p], viq = Vs[i][q];
+                As[i][p] = c * aip - sn * aiq;
+                As[i][q] = sn * aip + c * aiq;
+                Vs[i][p] = c * vip - sn * viq;
+                Vs[i][q] = sn * vip + c * viq;
+            }
+            wave_sync();
+            // rows p, q of A: columns j = lane / 8 and lane / 8 + 8; the
+            // rotated entry is set to its exact value 0
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = lane / (LEAF / 2) + 8 * h;
+                const double apj = As[p][j], aqj = As[q][j];
+                const bool rot = sn != 0.0;
+                As[p][j] = (rot && j == q) ? 0.0 : c * apj - sn * aqj;
+                As[q][j] = (rot && j == p) ? 0.0 : sn * apj + c * aqj;
+            }
+            wave_sync();
+        }
+        if (!__builtin_amdgcn_ballot_w64(rotated)) {
+            conv = true;
+            break;
+        }
     }
     if (!conv && lane == 0 && ws.status) atomicOr(ws.status + b, ST_NOCONV);
     // ascending order: the rank of lane j's value (ties by index)
+    const double lam = lane < ns ? As[lane][lane] : 0.0;
     int rank = 0;
     for (int k = 0; k < ns; ++k) {
-        const double dk = rdl(dr, k);
-        rank += (dk < dr || (dk == dr && k < lane)) ? 1 : 0;
+        const double dk = rdl(lam, k);
+        rank += (dk < lam || (dk == lam && k < lane)) ? 1 : 0;
     }
-    if (lane < ns) D[s + rank] = dr;
+    if (lane < ns) D[s + rank] = lam;
     double* Q = ws.Q[0] + b * ws.sQ;
     for (int j = 0; j < ns; ++j) {
         const int rj = __builtin_amdgcn_readlane(rank, j);
-        if (lane < ns) Q[(int64_t)(s + lane) + (int64_t)(s + rj) * n] = Zs[lane][j];
+        if (lane < ns) Q[(int64_t)(s + lane) + (int64_t)(s + rj) * n] = Vs[lane][j];
     }
 }
 
