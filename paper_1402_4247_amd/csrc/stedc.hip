@@ -6,8 +6,8 @@
 //    between rows mid-1 and mid, T = diag(T1', T2') + |beta| u u^T with
 //    u = e_{mid-1} + sign(beta) e_mid and the two corner diagonal entries
 //    lowered by |beta|;
-//  * each leaf solved by implicit QL with Wilkinson shifts (Bowdler, Martin,
-//    Reinsch & Wilkinson 1968), one wave per leaf;
+//  * each leaf solved by the parallel cyclic Jacobi method (Golub & Van Loan
+//    §8.5), one wave per leaf;
 //  * per merge: z = Q^T u / sqrt(2), rho = 2 |beta|, deflation of negligible
 //    z components and of close pole pairs by Givens rotations (Dongarra &
 //    Sorensen 1987);
@@ -119,12 +119,12 @@ __device__ inline void wave_sync()
 // zeroes a_pq; each lane forms the rotation of pair lane mod 8 and applies it
 // to two rows (then two columns): the columns of A and of the accumulated V
 // together, then the rows of A.  An off-diagonal entry
-// at most eps * max_i(|d_i| + |e_i|) is left alone (the deflation threshold of
-// the QL form it replaces); a sweep that rotates nothing ends the iteration.
+// at most eps * max_i(|d_i| + |e_i|) is left alone (the normwise deflation
+// threshold of implicit QL); a sweep that rotates nothing ends the iteration.
 // Eigenvalues go to D[0] ascending, the eigenvectors (columns of V) to the
 // leaf's diagonal block of Q[0] (the rest of Q[0] is the identity's zeros).
-// The rounds are short dependent chains of LDS traffic instead of the QL
-// sweep's chain of rotations, each with a square root and a reciprocal.
+// The rounds are short dependent chains of LDS traffic, where a QL sweep is a
+// chain of rotations, each with a square root and a reciprocal.
 constexpr int LEAF_SWEEPS = 30;
 
 __device__ inline void leaf_pair(int r, int k, int& p, int& q)
