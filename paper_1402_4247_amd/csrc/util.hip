@@ -135,7 +135,7 @@ constexpr int KBMAX = 64;
 // T factors of every reflector block at once, one workgroup per (block,
 // k-point): T_b (kk x kk, ld kb) from G_b = V_b^H V_b (ld kb).  The 256
 // threads take row r = tid / 4 of the recurrence and split its sum four
-// ways (fixed-order shuffle combine).
+// ways (fixed-order lane-exchange combine).
 template <typename R>
 __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>* G, int64_t sG,
                                                    const cx<R>* tau, int64_t stau, cx<R>* T, int64_t strT)
@@ -157,8 +157,20 @@ __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>
     __syncthreads();
     for (int j = 0; j < kk; ++j) {
         cx<R> acc = czero<cx<R>>();
-        if (r < j)
-            for (int q = r + part; q < j; q += 4) acc = cfma(sT[q][r], gl[j][q], acc);
+        // the terms q = r + part, +4, ... < j in order, their LDS reads four
+        // at a time (one round trip per four terms instead of per term)
+        for (int q0 = r + part; q0 < j; q0 += 16) {
+            cx<R> tv[4], gv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + 4 * u, qc = q < j ? q : q0;
+                tv[u] = sT[qc][r];
+                gv[u] = gl[j][qc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q0 + 4 * u < j) acc = cfma(tv[u], gv[u], acc);
+        }
         acc.x = dpp_sum<4>(acc.x);
         acc.y = dpp_sum<4>(acc.y);
         if (part == 0 && r < kk) {
