@@ -381,7 +381,8 @@ kgev_status kgev_zgemm_device(kgev_ctx* ctx, char transa, char transb, int64_t m
  * request granularity).  Each admitted request runs the batched per-k solve
  * (Band_DFT_Col Parts 2-4, Section III) on its own HIP stream, so requests
  * admitted while others run overlap with them on the device.  Admission is in
- * arrival order; a request is admitted when a slot is free and its workspace
+ * arrival order (optionally with bounded bypass, kgev_server_set_bypass); a
+ * request is admitted when a slot is free and its workspace
  * footprint (kgev_workspace_bytes + status words) fits the remaining budget;
  * the caller's own dH, dS, dw and dC are not counted, since they are allocated
  * before the request is submitted.  Inputs and outputs stay device-resident: the caller keeps dH, dS, dw and dC
@@ -415,6 +416,17 @@ typedef struct {
  * reserve).  Returns -1 (out NULL), -2 (device), -4 (slots) or KGEV_EDEVICE.
  */
 kgev_status kgev_server_create(kgev_server** out, int device, size_t hbm_budget, int32_t max_slots);
+
+/*
+ * Bounded bypass of the arrival order: when the request at the head of the
+ * queue does not fit the remaining budget, a later request that fits may
+ * start first, at most max_bypass times for the same head (0, the default:
+ * strict arrival order).  The head therefore waits at most for max_bypass
+ * later requests beyond the running ones, and never starves.  Takes effect
+ * at the server's next scheduling pass; results do not depend on it.
+ * Returns -1 (srv NULL) or -2 (max_bypass < 0).
+ */
+kgev_status kgev_server_set_bypass(kgev_server* srv, int32_t max_bypass);
 
 /* Queue a request; *ticket identifies it.  -2: invalid request fields. */
 kgev_status kgev_server_submit(kgev_server* srv, const kgev_request* req, uint64_t* ticket);

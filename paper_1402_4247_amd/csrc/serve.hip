@@ -114,6 +114,7 @@ struct kgev_server {
     std::unordered_map<uint64_t, ServeReq*> reqs;
     uint64_t next = 1;
     bool stop = false;
+    std::atomic<int> bypass{0};     // applied to the core by the worker
     std::thread worker;
 };
 
@@ -142,6 +143,7 @@ void worker_main(kgev_server* s)
                 changed = true;
             }
         }
+        s->core->set_max_bypass(s->bypass.load());
         if (s->core->step(s->ex) > 0) changed = true;
         if (changed) {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -190,6 +192,15 @@ kgev_status kgev_server_create(kgev_server** out, int device, size_t hbm_budget,
     s->core = new kgev::ServeCore<ServeReq, Exec>(hbm_budget, max_slots);
     s->worker = std::thread(worker_main, s);
     *out = s;
+    return KGEV_OK;
+}
+
+kgev_status kgev_server_set_bypass(kgev_server* s, int32_t max_bypass)
+{
+    if (!s) return -1;
+    if (max_bypass < 0) return -2;
+    s->bypass.store(max_bypass);
+    s->cv.notify_all();
     return KGEV_OK;
 }
 

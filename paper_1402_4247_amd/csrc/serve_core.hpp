@@ -1,6 +1,10 @@
 // Scheduling core of the serving loop: admission of eigensolve requests by
 // device-memory footprint and by free execution slots, in arrival order, as
 // earlier requests complete (continuous batching at request granularity).
+// Optionally (max_bypass > 0) a request behind a head that does not fit the
+// remaining budget may start first if it fits, at most max_bypass times per
+// head, so that small requests fill memory a large one is waiting for without
+// the large one ever starving.
 // Plain C++ with no HIP dependency: the executor that actually runs a request
 // is a template parameter, so the policy can be exercised on the host with a
 // stand-in executor.
@@ -37,6 +41,10 @@ public:
     }
     size_t queued() const { return queue_.size(); }
 
+    // Bypass limit (0: strict arrival order); takes effect at the next step.
+    void set_max_bypass(int k) { max_bypass_ = k > 0 ? k : 0; }
+    int max_bypass() const { return max_bypass_; }
+
     // Queue a request.  One whose footprint can never fit the budget is
     // rejected at once (returns false and leaves it untouched).
     bool submit(Req* r, Exec& ex)
@@ -50,7 +58,10 @@ public:
 
     // One scheduling pass: retire finished requests, then admit queued ones
     // in arrival order while a slot is free and the head request fits the
-    // remaining budget.  Returns the number of requests that changed state.
+    // remaining budget; when the head does not fit, the earliest later
+    // request that does is admitted instead, while the head has been passed
+    // fewer than max_bypass times.  Returns the number of requests that
+    // changed state.
     int step(Exec& ex)
     {
         int changed = 0;
@@ -65,13 +76,23 @@ public:
             }
         }
         while (!queue_.empty()) {
-            Req* r = queue_.front();
-            if (used_ + r->footprint > budget_) break;     // head-of-line: keep arrival order
+            size_t pick = 0;
+            if (used_ + queue_.front()->footprint > budget_) {
+                if (passed_ >= max_bypass_) break;          // keep arrival order
+                for (size_t q = 1; q < queue_.size(); ++q)
+                    if (used_ + queue_[q]->footprint <= budget_) { pick = q; break; }
+                if (pick == 0) break;
+            }
             int slot = -1;
             for (size_t s = 0; s < slot_busy_.size(); ++s)
                 if (!slot_busy_[s]) { slot = (int)s; break; }
             if (slot < 0) break;
-            queue_.pop_front();
+            Req* r = queue_[pick];
+            queue_.erase(queue_.begin() + (ptrdiff_t)pick);
+            if (pick == 0)
+                passed_ = 0;        // a new head
+            else
+                ++passed_;
             used_ += r->footprint;
             r->state = RQ_RUNNING;
             slot_busy_[slot] = r;
@@ -91,6 +112,8 @@ public:
 private:
     size_t budget_;
     size_t used_ = 0;
+    int max_bypass_ = 0;
+    int passed_ = 0;                // times the current head has been passed
     std::vector<Req*> slot_busy_;
     std::deque<Req*> queue_;
 };

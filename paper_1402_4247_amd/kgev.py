@@ -63,7 +63,7 @@ EXPORTS = ["kgev_opts_default", "kgev_status_str", "kgev_create", "kgev_destroy"
            "kgev_workspace_bytes", "kgev_solve_k", "kgev_solve_k_device", "kgev_hetrd_device",
            "kgev_stedc_device", "kgev_unmtr_device", "kgev_eigh_device", "kgev_zgemm_device",
            "kgev_profile_begin", "kgev_profile_end", "kgev_server_create", "kgev_server_submit",
-           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_autotune",
+           "kgev_server_poll", "kgev_server_wait", "kgev_server_destroy", "kgev_server_set_bypass", "kgev_autotune",
            "kgev_fermi_device", "kgev_density_workspace_bytes", "kgev_density_device", "kgev_bloch_device",
            "kgev_solve_k_x_device", "kgev_batch_workspace_bytes", "kgev_solve_batch_device",
            "kgev_solve_k_device_noalloc", "kgev_stebz_device", "kgev_tuned_params"]
@@ -143,6 +143,8 @@ def _load():
     lib.kgev_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     lib.kgev_server_wait.restype = I32
     lib.kgev_server_destroy.argtypes = [P]
+    lib.kgev_server_set_bypass.argtypes = [P, I32]
+    lib.kgev_server_set_bypass.restype = I32
     lib.kgev_autotune.argtypes = [P, I64, I32, ctypes.POINTER(I32)]
     lib.kgev_autotune.restype = I32
     lib.kgev_tuned_params.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -393,6 +395,9 @@ class Server:
         t = ctypes.c_uint64()
         _check("kgev_server_submit", lib.kgev_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(t)))
         return t.value
+
+    def set_bypass(self, max_bypass: int):
+        _check("kgev_server_set_bypass", lib.kgev_server_set_bypass(self.handle, int(max_bypass)))
 
     def poll(self, ticket) -> bool:
         d = ctypes.c_int32()

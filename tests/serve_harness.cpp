@@ -72,6 +72,7 @@ int sh_submit(void* hp, uint64_t footprint, int steps, int fail_start)
     return h->core.submit(r, h->ex) ? r->id : -1;
 }
 
+void sh_set_bypass(void* hp, int k) { static_cast<Harness*>(hp)->core.set_max_bypass(k); }
 int sh_step(void* hp) { Harness* h = static_cast<Harness*>(hp); return h->core.step(h->ex); }
 int sh_state(void* hp, int id) { return static_cast<Harness*>(hp)->reqs[id]->state; }
 int sh_start_seq(void* hp, int id) { return static_cast<Harness*>(hp)->reqs[id]->start_seq; }

@@ -125,6 +125,31 @@ def test_budget_limits_and_rejection():
     assert r3.t_admit >= r1.t_done - 1e-3      # serialised by the budget
 
 
+def test_bypass_admits_small_requests_past_a_waiting_head():
+    # the budget holds one large request and the three small ones, not two
+    # large ones: with bypass the small requests start beside the first large
+    # one while the second waits; every result equals the request alone
+    kg = K()
+    sizes = [(300, 2), (300, 2), (64, 1), (80, 1), (64, 2)]
+    reqs = [make_req(n, nk, 7100 + q) for q, (n, nk) in enumerate(sizes)]
+    fp = [((kg.workspace_bytes(n, nk) + 255) // 256) * 256 + 4 * nk for n, nk in sizes]
+    budget = fp[0] + fp[2] + fp[3] + fp[4] + 4096
+    assert budget < fp[0] + fp[1]
+    torch.cuda.synchronize()
+    with kg.Server(0, budget, 4) as srv:
+        srv.set_bypass(3)
+        tickets = [srv.submit(r["dH"], r["dS"], r["n"], r["nk"], r["dw"], r["dC"]) for r in reqs]
+        results = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    assert all(res.status == 0 for res in results)
+    # the small requests were admitted before the second large one
+    assert all(results[q].t_admit < results[1].t_admit for q in (2, 3, 4))
+    for r in reqs:
+        w_alone, C_alone = solve_alone(r)
+        assert np.array_equal(r["dw"].cpu().numpy(), w_alone)
+        assert np.array_equal(r["dC"].cpu().numpy(), C_alone)
+
+
 def test_failures_are_isolated():
     kg = K()
     good = make_req(70, 2, 21)

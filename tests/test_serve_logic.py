@@ -2,7 +2,8 @@
 on the host with a stand-in executor: arrival order, HBM budget and slot
 limits are never exceeded, queued work starts as soon as resources free up,
 requests that can never fit are rejected, a request that fails to start does
-not block the others."""
+not block the others; with bounded bypass, later requests that fit start ahead
+of a head that does not, never more often than the bound."""
 import ctypes
 import os
 import subprocess
@@ -29,6 +30,7 @@ def H():
     for f in ["sh_destroy"]:
         getattr(lib, f).argtypes = [ctypes.c_void_p]
     lib.sh_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+    lib.sh_set_bypass.argtypes = [ctypes.c_void_p, ctypes.c_int]
     for f in ["sh_step", "sh_max_running", "sh_running"]:
         getattr(lib, f).argtypes = [ctypes.c_void_p]
     for f in ["sh_state", "sh_start_seq", "sh_failed"]:
@@ -105,3 +107,40 @@ def test_failed_start_is_isolated(H):
     assert [H.sh_failed(h, i) for i in ids] == [0, 0, 1, 0, 0, 0]
     assert H.sh_in_use(h) == 0
     H.sh_destroy(h)
+
+
+def test_bypass_fills_memory_but_bounds_the_head(H):
+    # budget 100, 4 slots: A (70) runs long; the head B (50) does not fit
+    # beside it, C, D, E (10 each) do.  Strict order keeps them behind B;
+    # bypass 2 lets exactly two of them pass B, and B then starts before E.
+    for k, passed in [(0, 0), (2, 2), (8, 3)]:
+        h = H.sh_create(100, 4)
+        H.sh_set_bypass(h, k)
+        ids = [H.sh_submit(h, 70, 6, 0), H.sh_submit(h, 50, 2, 0)]
+        ids += [H.sh_submit(h, 10, 2, 0) for _ in range(3)]
+        run_to_completion(H, h, ids)
+        seq = [H.sh_start_seq(h, i) for i in ids]
+        a, b, c, d, e = seq
+        assert a == 0
+        ahead_of_b = sum(1 for x in (c, d, e) if x < b)
+        assert ahead_of_b == passed, (k, seq)
+        assert c < d < e                      # the small ones keep their order
+        assert H.sh_peak_bytes(h) <= 100 and H.sh_max_running(h) <= 4
+        H.sh_destroy(h)
+
+
+def test_bypass_never_starves_and_respects_limits(H):
+    rng = np.random.default_rng(3)
+    for k in (1, 3):
+        h = H.sh_create(120, 3)
+        H.sh_set_bypass(h, k)
+        sizes = [int(rng.integers(1, 100)) for _ in range(60)]
+        ids = [H.sh_submit(h, sz, int(rng.integers(1, 6)), 0) for sz in sizes]
+        run_to_completion(H, h, ids)
+        seq = [H.sh_start_seq(h, i) for i in ids]
+        # request q starts after at most k requests that arrived after it
+        for q in range(len(ids)):
+            later_first = sum(1 for p in range(q + 1, len(ids)) if seq[p] < seq[q])
+            assert later_first <= k * (q + 1), (k, q)
+        assert H.sh_peak_bytes(h) <= 120 and H.sh_max_running(h) <= 3
+        H.sh_destroy(h)
