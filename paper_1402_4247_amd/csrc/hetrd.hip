@@ -37,6 +37,9 @@
 
 namespace kgev {
 
+// 32-bit raw buffer load (the 64- and 128-bit forms are in common.hpp)
+__device__ int raw_buffer_load_i32(i4_t rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.i32");
+
 namespace {
 
 constexpr int ZT = 64;          // ZHEMV tile edge
@@ -448,8 +451,6 @@ __device__ inline i4_t uniform_rsrc(const void* base, uint32_t bytes)
     r.w = __builtin_amdgcn_readfirstlane(r.w);
     return r;
 }
-
-__device__ int raw_buffer_load_i32(i4_t rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.i32");
 
 template <typename R>
 __device__ inline R bload_r(i4_t rsrc, int voff)
