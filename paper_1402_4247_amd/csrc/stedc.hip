@@ -343,25 +343,46 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb, int ld
             bool have = false;
             double zp = 0.0, dpv = 0.0;
             int cp = 0;
-            for (int q = 0; q < ns; ++q) {
-                const double zq = sz[q], dq = sd[q];
-                const int cq = perm[q];
-                if (rho * fabs(zq) <= tol) { dfx[nd] = cq; dfd[nd] = dq; ++nd; continue; }
-                if (!have) { have = true; zp = zq; dpv = dq; cp = cq; continue; }
-                // |gap c s| <= tol with c = z_q / tau, s = -z_p / tau, tau^2 = z_q^2 + z_p^2,
-                // tested without the square root and the divisions
-                const double gap = dq - dpv;
-                if (fabs(gap * zq * zp) <= tol * (zq * zq + zp * zp)) {
-                    const double tau = hypot(zq, zp);
-                    const double c = zq / tau, sn = -zp / tau;
-                    rota[nr] = cp; rotb[nr] = cq; rotc[nr] = c; rots[nr] = sn; ++nr;
-                    dfx[nd] = cp; dfd[nd] = dpv * c * c + dq * sn * sn; ++nd;
-                    zp = tau;
-                    dpv = dpv * sn * sn + dq * c * c;
-                    cp = cq;
-                } else {
-                    ndx[K] = cp; ndd[K] = dpv; ndz[K] = zp; ++K;
-                    zp = zq; dpv = dq; cp = cq;
+            // the candidates are read from LDS four at a time, ahead of the
+            // serial decisions that use them
+            constexpr int DQ = 4;
+            for (int q0 = 0; q0 < ns; q0 += DQ) {
+                double zq4[DQ], dq4[DQ];
+                int cq4[DQ];
+#pragma unroll
+                for (int u = 0; u < DQ; ++u) {
+                    const int q = q0 + u < ns ? q0 + u : q0;
+                    zq4[u] = sz[q];
+                    dq4[u] = sd[q];
+                    cq4[u] = perm[q];
+                }
+#pragma unroll
+                for (int u = 0; u < DQ; ++u) {
+                    if (q0 + u >= ns) break;
+                    const double zq = zq4[u], dq = dq4[u];
+                    const int cq = cq4[u];
+                    if (rho * fabs(zq) <= tol) {
+                        dfx[nd] = cq; dfd[nd] = dq; ++nd;
+                    } else if (!have) {
+                        have = true; zp = zq; dpv = dq; cp = cq;
+                    } else {
+                        // |gap c s| <= tol with c = z_q / tau, s = -z_p / tau,
+                        // tau^2 = z_q^2 + z_p^2, tested without the square
+                        // root and the divisions
+                        const double gap = dq - dpv;
+                        if (fabs(gap * zq * zp) <= tol * (zq * zq + zp * zp)) {
+                            const double tau = hypot(zq, zp);
+                            const double c = zq / tau, sn = -zp / tau;
+                            rota[nr] = cp; rotb[nr] = cq; rotc[nr] = c; rots[nr] = sn; ++nr;
+                            dfx[nd] = cp; dfd[nd] = dpv * c * c + dq * sn * sn; ++nd;
+                            zp = tau;
+                            dpv = dpv * sn * sn + dq * c * c;
+                            cp = cq;
+                        } else {
+                            ndx[K] = cp; ndd[K] = dpv; ndz[K] = zp; ++K;
+                            zp = zq; dpv = dq; cp = cq;
+                        }
+                    }
                 }
             }
             if (have) { ndx[K] = cp; ndd[K] = dpv; ndz[K] = zp; ++K; }
@@ -374,15 +395,24 @@ __global__ __launch_bounds__(256) void dc_deflate(DcWs ws, int t, int rb, int ld
     }
     __syncthreads();
     const int nr = s_nrot;
-    // apply the deflation rotations, in order, to the columns of Q (rows s..e)
+    // apply the deflation rotations, in order, to the columns of Q (rows s..e).
+    // Consecutive rotations chain through their second column (the pending
+    // candidate), so that column is carried in a register: no rotation waits
+    // for the store of the one before it to come back from memory.
     for (int r = tid; r < ns; r += 256) {
         const int64_t row = s + r;
+        int cur = -1;            // column held in cv (not yet stored), or -1
+        double cv = 0.0;
         for (int q = 0; q < nr; ++q) {
-            const int64_t ca = s + rota[q], cb = s + rotb[q];
-            const double x = Qr[row + ca * n], y = Qr[row + cb * n];
-            Qr[row + ca * n] = rotc[q] * x + rots[q] * y;
-            Qr[row + cb * n] = rotc[q] * y - rots[q] * x;
+            const int ca = rota[q], cb = rotb[q];
+            const double x = ca == cur ? cv : Qr[row + (s + ca) * n];
+            const double y = cb == cur ? cv : Qr[row + (s + cb) * n];
+            if (cur >= 0 && cur != ca && cur != cb) Qr[row + (s + cur) * n] = cv;
+            Qr[row + (s + ca) * n] = rotc[q] * x + rots[q] * y;
+            cur = cb;
+            cv = rotc[q] * y - rots[q] * x;
         }
+        if (cur >= 0) Qr[row + (s + cur) * n] = cv;
     }
 }
 
