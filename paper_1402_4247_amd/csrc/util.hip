@@ -135,7 +135,9 @@ constexpr int KBMAX = 64;
 // T factors of every reflector block at once, one workgroup per (block,
 // k-point): T_b (kk x kk, ld kb) from G_b = V_b^H V_b (ld kb).  The 256
 // threads take row r = tid / 4 of the recurrence and split its sum four
-// ways (fixed-order lane-exchange combine).
+// ways (fixed-order lane-exchange combine).  T(r, j) = -tau_j sum_q T(r, q)
+// G(q, j) needs only row r's own earlier entries, so the steps are ordered
+// within each wave and the workgroup synchronises only before the store.
 template <typename R>
 __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>* G, int64_t sG,
                                                    const cx<R>* tau, int64_t stau, cx<R>* T, int64_t strT)
@@ -177,8 +179,14 @@ __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>
             const cx<R> tj = tl[j];
             sT[j][r] = csel(r < j, cscale(cmul(tj, acc), (R)-1), csel(r == j, tj, czero<cx<R>>()));
         }
-        __syncthreads();
+        // row r of T depends only on row r's earlier entries, which the four
+        // lanes of the row (one wave) wrote themselves: a wave-level sync
+        // orders them, no workgroup barrier is needed between the steps
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __syncthreads();
     cx<R>* Tb = T + b * strT + (int64_t)blk * kb * kb;
     for (int e = tid; e < kk * kk; e += 256) {
         const int rr = e % kk, cc = e / kk;
