@@ -3,6 +3,8 @@
 // eigenvector normalisation (Eigen_HH's last step) fused with Part 2's
 // rearrangement of S (x_j = u_j / sqrt(s_j)) and its definiteness check, and
 // the triangular factor of a block of reflectors (compact WY).
+#include <utility>
+
 #include "common.hpp"
 #include "lanes.hpp"
 #include "kernels.hpp"
@@ -132,17 +134,46 @@ __global__ __launch_bounds__(256) void k_normalize_cols_real(int64_t n, double* 
 // T (kk x kk, upper) for reflectors c0..c0+kk-1 (compact WY):
 // T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V_b^H V_b.
 constexpr int KBMAX = 64;
+// Step q of the T recurrence below, for one lane of row r's quad: acc[m]
+// holds the running sum of column part + 4m.  q is a template argument so
+// that acc stays in registers (every index into it is a constant).
+template <int Q, typename R>
+__device__ inline void larft_step(cx<R> (&acc)[KBMAX / 4], const cx<R> (*gl)[KBMAX + 1], const cx<R>* tl, int r,
+                                  int part, bool store, cx<R>* Tb, int kb)
+{
+    const cx<R> tq = tl[Q];
+    // in the lane with part == Q % 4, acc[Q / 4] is column Q's full sum
+    cx<R> t = csel(r < Q, cscale(cmul(tq, acc[Q >> 2]), (R)-1), csel(r == Q, tq, czero<cx<R>>()));
+    t.x = quad_bcast<Q & 3>(t.x);
+    t.y = quad_bcast<Q & 3>(t.y);
+    if (store) Tb[r + (int64_t)Q * kb] = t;
+    // the columns j > Q (a column j <= Q of a lane's set is finished and no
+    // longer read, so the first group holding a j > Q is the bound)
+#pragma unroll
+    for (int m = (Q < 3 ? 0 : (Q - 3) / 4 + 1); m < KBMAX / 4; ++m)
+        acc[m] = cfma(t, gl[part + 4 * m][Q], acc[m]);
+}
+template <typename R, int... Q>
+__device__ inline void larft_steps(std::integer_sequence<int, Q...>, int kk, cx<R> (&acc)[KBMAX / 4],
+                                   const cx<R> (*gl)[KBMAX + 1], const cx<R>* tl, int r, int part, bool store,
+                                   cx<R>* Tb, int kb)
+{
+    ((Q < kk ? (larft_step<Q, R>(acc, gl, tl, r, part, store, Tb, kb), 0) : 0), ...);
+}
 // T factors of every reflector block at once, one workgroup per (block,
-// k-point): T_b (kk x kk, ld kb) from G_b = V_b^H V_b (ld kb).  The 256
-// threads take row r = tid / 4 of the recurrence and split its sum four
-// ways (fixed-order lane-exchange combine).  T(r, j) = -tau_j sum_q T(r, q)
-// G(q, j) needs only row r's own earlier entries, so the steps are ordered
-// within each wave and the workgroup synchronises only before the store.
+// k-point): T_b (kk x kk, ld kb) from G_b = V_b^H V_b (ld kb).  Row r of T
+// (T(r, j) = -tau_j sum_{q<j} T(r, q) G(q, j), T(r, r) = tau_r, zero below
+// the diagonal) depends on row r alone; it is taken by the quad of lanes
+// 4r .. 4r+3, lane p of which keeps the running sums of the columns
+// j = p + 4m in registers.  Step q finishes T(r, q) in the lane that owns
+// column q, broadcasts it over the quad and adds its term to every later
+// column's sum (right-looking), so the serial chain per step is one complex
+// product, one broadcast and one fused multiply-add, and no step waits for
+// memory written by another.
 template <typename R>
 __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>* G, int64_t sG,
                                                    const cx<R>* tau, int64_t stau, cx<R>* T, int64_t strT)
 {
-    __shared__ cx<R> sT[KBMAX][KBMAX + 1];   // sT[col][row]
     __shared__ cx<R> gl[KBMAX][KBMAX + 1];   // gl[col][row] = G(row, col)
     __shared__ cx<R> tl[KBMAX];
     const int blk = blockIdx.x;
@@ -157,41 +188,11 @@ __global__ __launch_bounds__(256) void k_larft_all(int kb, int nref, const cx<R>
     }
     if (tid < kk) tl[tid] = tau[b * stau + c0 + tid];
     __syncthreads();
-    for (int j = 0; j < kk; ++j) {
-        cx<R> acc = czero<cx<R>>();
-        // the terms q = r + part, +4, ... < j in order, their LDS reads four
-        // at a time (one round trip per four terms instead of per term)
-        for (int q0 = r + part; q0 < j; q0 += 16) {
-            cx<R> tv[4], gv[4];
+    cx<R> acc[KBMAX / 4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = q0 + 4 * u, qc = q < j ? q : q0;
-                tv[u] = sT[qc][r];
-                gv[u] = gl[j][qc];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (q0 + 4 * u < j) acc = cfma(tv[u], gv[u], acc);
-        }
-        acc.x = dpp_sum<4>(acc.x);
-        acc.y = dpp_sum<4>(acc.y);
-        if (part == 0 && r < kk) {
-            const cx<R> tj = tl[j];
-            sT[j][r] = csel(r < j, cscale(cmul(tj, acc), (R)-1), csel(r == j, tj, czero<cx<R>>()));
-        }
-        // row r of T depends only on row r's earlier entries, which the four
-        // lanes of the row (one wave) wrote themselves: a wave-level sync
-        // orders them, no workgroup barrier is needed between the steps
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    __syncthreads();
+    for (int m = 0; m < KBMAX / 4; ++m) acc[m] = czero<cx<R>>();
     cx<R>* Tb = T + b * strT + (int64_t)blk * kb * kb;
-    for (int e = tid; e < kk * kk; e += 256) {
-        const int rr = e % kk, cc = e / kk;
-        Tb[rr + (int64_t)cc * kb] = sT[cc][rr];
-    }
+    larft_steps<R>(std::make_integer_sequence<int, KBMAX>{}, kk, acc, gl, tl, r, part, part == 0 && r < kk, Tb, kb);
 }
 
 }  // namespace
