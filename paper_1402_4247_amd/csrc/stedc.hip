@@ -191,6 +191,9 @@ __global__ __launch_bounds__(64) void dc_leaf(DcWs ws, int tl)
                 sn = t * c;
                 rotated = true;
             }
+            // a round in which no pair rotates (all of the final sweep) leaves
+            // A and V as they are: skip its two phases
+            if (!__builtin_amdgcn_ballot_w64(sn != 0.0)) continue;
             wave_sync();
             // columns p, q of A and of V: rows i = lane / 8 and lane / 8 + 8
 #pragma unroll
