@@ -18,11 +18,8 @@ namespace kgev {
 
 namespace {
 
+constexpr int GB_K = 16;   // K step per LDS stage
 constexpr int G_THREADS = 256;
-// K step per LDS stage: 16 for the 64 x 64 tiles; 32 for the 32 x 32 tiles,
-// which run the small products, where each step's load latency (not the
-// multiply) sets the time, so half the steps is nearly half the time
-template <int BM> constexpr int kstep() { return BM == 32 ? 32 : 16; }
 
 template <typename R>
 struct CGemmArgs {
@@ -76,22 +73,22 @@ __device__ inline void tile_of(int64_t L, int64_t total, int tiles_m, int tiles_
     tn = local / rows_g;
 }
 
-// global -> registers: this thread's elements of the op(A) tile (BM x KS).
+// global -> registers: this thread's elements of the op(A) tile (BM x GB_K).
 // The loads come from clamped (in-bounds) addresses with no branch, so they
 // stay in flight across the MFMA work of the current step; the bounds mask
 // and the conjugation of op = ^H are applied when the registers are stored
 // to LDS.
-template <typename R, int BM, int TA, int KS>
+template <typename R, int BM, int TA>
 __device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int64_t m, int64_t K, int64_t i0,
-                              int64_t k0, int tid, cx<R> (&ra)[BM * KS / G_THREADS], unsigned& okmask)
+                              int64_t k0, int tid, cx<R> (&ra)[BM * GB_K / G_THREADS], unsigned& okmask)
 {
-    constexpr int NE = BM * KS / G_THREADS;
+    constexpr int NE = BM * GB_K / G_THREADS;
     okmask = 0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int r = TA ? e / KS : e % BM;
-        const int kk = TA ? e % KS : e / BM;
+        const int r = TA ? e / GB_K : e % BM;
+        const int kk = TA ? e % GB_K : e / BM;
         const int64_t gi = i0 + r, gk = k0 + kk;
         const bool ok = gi < m && gk < K;
         const int64_t gic = gi < m ? gi : m - 1, gkc = gk < K ? gk : K - 1;
@@ -100,34 +97,34 @@ __device__ inline void load_a(const cx<R>* __restrict__ A, int64_t lda, int64_t 
     }
 }
 
-template <typename R, int BM, int TA, int KS>
-__device__ inline void store_a(R (*sr)[BM + 1], R (*si)[BM + 1], int tid, const cx<R> (&ra)[BM * KS / G_THREADS],
+template <typename R, int BM, int TA>
+__device__ inline void store_a(R (*sr)[BM + 1], R (*si)[BM + 1], int tid, const cx<R> (&ra)[BM * GB_K / G_THREADS],
                                unsigned okmask)
 {
-    constexpr int NE = BM * KS / G_THREADS;
+    constexpr int NE = BM * GB_K / G_THREADS;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int r = TA ? e / KS : e % BM;
-        const int kk = TA ? e % KS : e / BM;
+        const int r = TA ? e / GB_K : e % BM;
+        const int kk = TA ? e % GB_K : e / BM;
         const bool ok = (okmask >> q) & 1u;
         sr[kk][r] = ok ? ra[q].x : (R)0;
         si[kk][r] = ok ? (TA ? -ra[q].y : ra[q].y) : (R)0;
     }
 }
 
-// op(B) tile (KS x BN)
-template <typename R, int BN, int TB, int KS>
+// op(B) tile (GB_K x BN)
+template <typename R, int BN, int TB>
 __device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int64_t n, int64_t K, int64_t j0,
-                              int64_t k0, int tid, cx<R> (&rb)[BN * KS / G_THREADS], unsigned& okmask)
+                              int64_t k0, int tid, cx<R> (&rb)[BN * GB_K / G_THREADS], unsigned& okmask)
 {
-    constexpr int NE = BN * KS / G_THREADS;
+    constexpr int NE = BN * GB_K / G_THREADS;
     okmask = 0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int c = TB == 1 ? e % BN : e / KS;
-        const int kk = TB == 1 ? e / BN : e % KS;
+        const int c = TB == 1 ? e % BN : e / GB_K;
+        const int kk = TB == 1 ? e / BN : e % GB_K;
         const int64_t gj = j0 + c, gk = k0 + kk;
         const bool ok = gj < n && gk < K;
         const int64_t gjc = gj < n ? gj : n - 1, gkc = gk < K ? gk : K - 1;
@@ -139,16 +136,16 @@ __device__ inline void load_b(const cx<R>* __restrict__ B, int64_t ldb, int64_t 
     }
 }
 
-template <typename R, int BN, int TB, int KS>
-__device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const cx<R> (&rb)[BN * KS / G_THREADS],
+template <typename R, int BN, int TB>
+__device__ inline void store_b(R (*sr)[BN + 1], R (*si)[BN + 1], int tid, const cx<R> (&rb)[BN * GB_K / G_THREADS],
                                unsigned okmask)
 {
-    constexpr int NE = BN * KS / G_THREADS;
+    constexpr int NE = BN * GB_K / G_THREADS;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + G_THREADS * q;
-        const int c = TB == 1 ? e % BN : e / KS;
-        const int kk = TB == 1 ? e / BN : e % KS;
+        const int c = TB == 1 ? e % BN : e / GB_K;
+        const int kk = TB == 1 ? e / BN : e % GB_K;
         const bool ok = (okmask >> q) & 1u;
         sr[kk][c] = ok ? rb[q].x : (R)0;
         if constexpr (TB != 2) si[kk][c] = ok ? (TB ? -rb[q].y : rb[q].y) : (R)0;
@@ -165,7 +162,6 @@ __global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
     using M = Mfma<R>;
     using acc_t = typename M::acc_t;
     constexpr int TM = BM / 32, TN = BN / 32;      // MFMA tiles per wave
-    constexpr int GB_K = kstep<BM>();
     __shared__ R sAr[2][GB_K][BM + 1], sAi[2][GB_K][BM + 1];
     __shared__ R sBr[2][GB_K][BN + 1], sBi[2][GB_K][BN + 1];
 
@@ -211,19 +207,19 @@ __global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
     unsigned oka = 0, okb = 0;
     int cur = 0;
     if (total_k > 0) {
-        load_a<R, BM, TA, GB_K>(p.A[0] + bo * p.sA[0] + bi * p.sA2[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
-        load_b<R, BN, TB, GB_K>(bbase(0), p.ldb[0], n, K, j0, 0, tid, rb, okb);
-        store_a<R, BM, TA, GB_K>(sAr[0], sAi[0], tid, ra, oka);
-        store_b<R, BN, TB, GB_K>(sBr[0], sBi[0], tid, rb, okb);
+        load_a<R, BM, TA>(p.A[0] + bo * p.sA[0] + bi * p.sA2[0], p.lda[0], m, K, i0, 0, tid, ra, oka);
+        load_b<R, BN, TB>(bbase(0), p.ldb[0], n, K, j0, 0, tid, rb, okb);
+        store_a<R, BM, TA>(sAr[0], sAi[0], tid, ra, oka);
+        store_b<R, BN, TB>(sBr[0], sBi[0], tid, rb, okb);
     }
     __syncthreads();
     for (int it = 0; it < total_k; ++it) {
         const int nx = it + 1;
         const int sn = nx / nkt, kt = nx % nkt;
         if (nx < total_k) {
-            load_a<R, BM, TA, GB_K>(p.A[sn] + bo * p.sA[sn] + bi * p.sA2[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid,
+            load_a<R, BM, TA>(p.A[sn] + bo * p.sA[sn] + bi * p.sA2[sn], p.lda[sn], m, K, i0, (int64_t)kt * GB_K, tid,
                               ra, oka);
-            load_b<R, BN, TB, GB_K>(bbase(sn), p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid,
+            load_b<R, BN, TB>(bbase(sn), p.ldb[sn], n, K, j0, (int64_t)kt * GB_K, tid,
                               rb, okb);
         }
 #pragma unroll
@@ -278,8 +274,8 @@ __global__ __launch_bounds__(G_THREADS, 2) void cgemm_kernel(CGemmArgs<R> p)
         }
         if (nx < total_k) {
             const int nxt = cur ^ 1;
-            store_a<R, BM, TA, GB_K>(sAr[nxt], sAi[nxt], tid, ra, oka);
-            store_b<R, BN, TB, GB_K>(sBr[nxt], sBi[nxt], tid, rb, okb);
+            store_a<R, BM, TA>(sAr[nxt], sAi[nxt], tid, ra, oka);
+            store_b<R, BN, TB>(sBr[nxt], sBi[nxt], tid, rb, okb);
         }
         __syncthreads();
         cur ^= 1;
